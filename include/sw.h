@@ -1,0 +1,204 @@
+/*
+ * sw.h - C ABI of the mW Stillinger-Weber molecular-dynamics engine for
+ * AMD MI355X (gfx950).
+ *
+ * The model (Molinero & Moore, "Water modeled as an intermediate element
+ * between carbon and silicon", Sec. II.A, the equations for E, phi2 and phi3):
+ *
+ *   E = sum_i sum_{j>i} phi2(r_ij) + sum_i sum_{j!=i} sum_{k>j,k!=i} phi3(r_ij, r_ik, theta_jik)
+ *   phi2(r)     = A eps [B (sig/r)^p - (sig/r)^q] exp(sig / (r - a sig))
+ *   phi3(r,s,t) = lam eps (cos t - cos t0)^2 exp(gam sig/(r - a sig)) exp(gam sig/(s - a sig))
+ *
+ * with every term zero beyond the reduced cut-off a*sig, the vertex of
+ * theta_jik at atom i, and the mW parameters of Sec. II.D (lam = 23.15,
+ * eps = 6.189 kcal/mol, sig = 2.3925 A; A, B, p = 4, q = 0, gam = 1.2, a = 1.8
+ * from Sec. II.A; cos t0 = -1/3).  Time integration is velocity Verlet; the
+ * paper's production step is 10 fs (Sec. II.B).
+ *
+ * Units: Angstrom, fs, kcal/mol, g/mol, K.  Acceleration a = 4.184e-4 F / m.
+ *
+ * Conventions shared by every call:
+ *  - All array arguments documented as "device" are device pointers owned by
+ *    the caller; the library never frees them.  "host" pointers are read
+ *    during the call only.
+ *  - Atom arrays x, v, f are float[N][4] (x, y, z, w); w is ignored on input
+ *    and written as 0 on output.  N = offsets[R] is the total over replicas;
+ *    replica r owns atoms offsets[r] .. offsets[r+1]-1.  Atom order in every
+ *    caller array is the caller's own: the library keeps its own spatially
+ *    sorted copy internally and scatters results back.
+ *  - `stream` is a hipStream_t passed as void*; NULL means the default stream.
+ *    All work is enqueued on it.  Calls that report device-side error flags
+ *    (overflow, overlap) synchronise the stream before returning.
+ *  - Return values are sw_status codes (0 = success, negative = error).  No
+ *    exception crosses the ABI.  One context must not be used from two host
+ *    threads at once.
+ */
+#ifndef SW_H
+#define SW_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Parameter block, Sec. II.A (A, B, p, q, gamma, a, theta0) and Sec. II.D
+ * (lambda, epsilon, sigma).  The GPU kernels implement the Stillinger-Weber
+ * exponents p = 4, q = 0; other values return SW_EUNSUPPORTED. */
+typedef struct sw_params {
+  double lambda;      /* three-body strength                         */
+  double epsilon;     /* energy scale, kcal/mol                      */
+  double sigma;       /* length scale, Angstrom                      */
+  double A, B;        /* two-body form constants                     */
+  double p, q;        /* two-body exponents                          */
+  double gamma;       /* three-body radial decay                     */
+  double a;           /* reduced cut-off: every term vanishes at a*sigma */
+  double cos_theta0;  /* cosine of the favoured angle                */
+} sw_params;
+
+typedef enum sw_status {
+  SW_OK = 0,
+  SW_EINVAL = -1,          /* bad argument (NULL pointer, size, value)                 */
+  SW_EBOX_TOO_SMALL = -2,  /* a box edge holds fewer than 3 cells of cutoff + skin     */
+  SW_ENBR_OVERFLOW = -3,   /* a neighbour row exceeded the capacity even after growth  */
+  SW_ECELL_OVERFLOW = -4,  /* a binning cell exceeded its capacity even after growth   */
+  SW_EOVERLAP = -5,        /* two atoms closer than 0.5 A, a NaN, or a step moving an
+                              atom by more than a quarter box edge                     */
+  SW_EHIP = -6,            /* a HIP runtime call failed (see sw_last_hip_error)         */
+  SW_ENOMEM = -7,          /* device allocation failed                                 */
+  SW_EUNSUPPORTED = -8,    /* parameter or option outside what the kernels implement  */
+  SW_ESTATE = -9           /* call needs state the context does not have              */
+} sw_status;
+
+/* Opaque context: replica layout, cell grids, neighbour rows, workspaces. */
+typedef struct sw_ctx sw_ctx;
+
+/* Fills *out with the mW parameters (Sec. II.A constants, Sec. II.D values). */
+void sw_params_mw(sw_params* out);
+
+/* Creates a context for n_replicas independent periodic orthorhombic boxes.
+ *  h_offsets   host, int64[n_replicas+1], offsets[0] = 0, non-decreasing; every
+ *              replica holds at least 2 atoms.
+ *  h_box       host, double[n_replicas][3], box edges in Angstrom.
+ *  cutoff      largest a*sigma any later call may use (Angstrom, > 0).
+ *  skin        Verlet skin (Angstrom, >= 0).  Neighbour rows hold every atom
+ *              within cutoff + skin; rows are rebuilt when some atom has moved
+ *              more than half of (cutoff + skin - a*sigma) since the last build.
+ *  nbr_capacity initial slots per neighbour row (grown automatically, <= 512).
+ * Errors: SW_EINVAL, SW_EBOX_TOO_SMALL (an edge shorter than 3 (cutoff + skin)),
+ * SW_ENOMEM, SW_EHIP.  On success *out owns device memory until sw_destroy. */
+int sw_create(sw_ctx** out, int n_replicas, const long long* h_offsets, const double* h_box,
+              double cutoff, double skin, int nbr_capacity);
+
+/* Releases everything the context owns.  NULL is ignored. */
+void sw_destroy(sw_ctx* ctx);
+
+/* Neighbour search (cell binning, Morton-ordered counting sort, Verlet rows).
+ * The paper's cut-off a*sigma (Sec. II.A) bounds the interaction range; the
+ * rows list every j != i within cutoff + skin.
+ *  x      device float[N][4] positions (any values; wrapped into the box).
+ * After this call the context holds a spatial order and rows for x; sw_forces
+ * reuses them while they stay valid.  Synchronises; returns SW_ENBR_OVERFLOW /
+ * SW_ECELL_OVERFLOW only if growth failed. */
+int sw_build_neighbors(sw_ctx* ctx, const float* x, void* stream);
+
+/* Copies the current rows out, in the caller's atom order.
+ *  h_counts host int[N]; h_rows host int[N][max_per_row] (caller atom indices,
+ *  each row ascending; unused slots set to -1).  Returns SW_EINVAL if a row
+ *  is longer than max_per_row, SW_ESTATE before any build. */
+int sw_get_neighbors(sw_ctx* ctx, int* h_counts, int* h_rows, int max_per_row);
+
+/* Energy, forces and virial of Eq. E (Sec. II.A) at positions x.
+ *  x       device float[N][4].
+ *  params  host; p must be 4, q 0, a*sigma <= the context's cutoff.
+ *  f       device float[N][4] out: -dE/dx, kcal/mol/A.
+ *  energy  device double[R][2] out (may be NULL): E2, E3 per replica, kcal/mol.
+ *  virial  device double[R][6] out (may be NULL): W_xx, yy, zz, xy, xz, yz with
+ *          W_ab = sum over terms of sum over legs d_a F_b, kcal/mol.
+ * Rebuilds rows first when x has moved too far from the last build.
+ * Synchronises. */
+int sw_forces(sw_ctx* ctx, const float* x, const sw_params* params, float* f, double* energy,
+              double* virial, void* stream);
+
+/* Thermostat kinds for sw_step. */
+enum { SW_NVE = 0, SW_RESCALE = 1, SW_BERENDSEN = 2 };
+
+/* Width of one thermo record per replica (doubles). */
+#define SW_THERMO_WIDTH 12
+
+/* nsteps steps of velocity Verlet (kick-drift-kick) from (x, v):
+ *   v += dt/2 a(x);  x += dt v;  v += dt/2 a(x);  then the thermostat
+ * with a = 4.184e-4 F / mass.  Thermostats act on the full-step velocities:
+ * SW_RESCALE multiplies v by sqrt(T0/T); SW_BERENDSEN by
+ * sqrt(1 + dt/tau (T0/T - 1)); T = 2 KE / ((3N_r - 3) k_B) per replica.
+ *  x, v    device float[N][4] in/out (A, A/fs).
+ *  f       device float[N][4] out: forces at the final positions.
+ *  mass    g/mol (> 0); dt fs (> 0); nsteps >= 0.
+ *  h_T0    host double[R] target temperatures (K); required unless SW_NVE.
+ *  tau_fs  Berendsen time constant (fs).
+ *  thermo  device double[nsteps / thermo_every][R][SW_THERMO_WIDTH] out, may
+ *          be NULL: for each recorded step (every thermo_every-th step) and
+ *          replica: E2, E3, KE (before the thermostat), W xx yy zz xy xz yz,
+ *          K xx yy zz (K_aa = sum m v_a^2 in kcal/mol).
+ * Synchronises at the end to report device-side flags; on a neighbour or
+ * cell overflow the capacity is grown and the whole call is redone from the
+ * untouched inputs. */
+int sw_step(sw_ctx* ctx, float* x, float* v, float* f, const sw_params* params, double mass,
+            double dt, int nsteps, int thermostat, const double* h_T0, double tau_fs,
+            double* thermo, int thermo_every, void* stream);
+
+/* Tangent of the force field along w at positions x (forward mode):
+ *  hvp     device float[N][4] out: (dF/dx) w = -H w (H is symmetric, so this
+ *          is also (dF/dx)^T w).
+ *  wdF     device double[R][3] out (may be NULL): w . dF/d(lambda, epsilon, sigma).
+ *  dU      device double[R][3] out (may be NULL): dU/d(lambda, epsilon, sigma).
+ * Uses the reduced form of Sec. II.A: dF/deps = F/eps, dF/dlambda = F3/lambda,
+ * dF/dsigma = -(1/sigma) dW/dx with W the virial trace. Synchronises. */
+int sw_grad(sw_ctx* ctx, const float* x, const float* w, const sw_params* params, float* hvp,
+            double* wdF, double* dU, void* stream);
+
+/* Gradient of a trajectory observable by the discrete adjoint of NVE velocity
+ * Verlet, with checkpoints every ckpt_every steps and recomputation:
+ *   L_r = 1/(S+1) sum_{s=0..S} [aU U_r(x_s) + a3 U3_r(x_s)] / N_r
+ *         + xbar_S . x_S + vbar_S . v_S
+ * (U = E2 + E3, U3 = E3, S = nsteps).
+ *  x0, v0   device float[N][4] initial state (unchanged).
+ *  xbar_S, vbar_S device float[N][4] terminal seeds, may be NULL (= 0).
+ *  loss     device double[R] out.
+ *  xbar0, vbar0 device float[N][4] out: dL/dx0, dL/dv0.
+ *  thbar    device double[R][3] out: dL/d(lambda, epsilon, sigma).
+ *  xS, vS   device float[N][4] out (may be NULL): final state.
+ * Synchronises. */
+int sw_adjoint(sw_ctx* ctx, const float* x0, const float* v0, const sw_params* params,
+               double mass, double dt, int nsteps, int ckpt_every, double aU, double a3,
+               const float* xbar_S, const float* vbar_S, double* loss, float* xbar0,
+               float* vbar0, double* thbar, float* xS, float* vS, void* stream);
+
+/* Execution options (chosen by the autotuner). */
+typedef struct sw_tuning {
+  int lanes_per_atom;   /* 4, 8 or 16 lanes of a wavefront share one atom      */
+  int graph_steps;      /* steps per captured hipGraph (0 = plain launches)    */
+  int persistent;       /* 1: sw_step runs as one cooperative persistent launch */
+  int rebuild_every;    /* also rebuild rows at least this often (0 = only on
+                           displacement)                                        */
+} sw_tuning;
+int sw_set_tuning(sw_ctx* ctx, const sw_tuning* t);
+int sw_get_tuning(const sw_ctx* ctx, sw_tuning* t);
+
+/* Queries (value written to *out). */
+enum {
+  SW_Q_NATOMS = 0,        /* total atoms N                             */
+  SW_Q_NREPLICAS = 1,
+  SW_Q_NBR_CAPACITY = 2,  /* current slots per row                     */
+  SW_Q_REBUILDS = 3,      /* row rebuilds since creation               */
+  SW_Q_CELL_CAPACITY = 5,
+  SW_Q_DEVICE_BYTES = 6,  /* device memory owned by the context        */
+  SW_Q_STEPS = 7          /* integration steps since creation          */
+};
+int sw_query(sw_ctx* ctx, int what, long long* out);
+
+const char* sw_status_string(int status);
+int sw_last_hip_error(const sw_ctx* ctx);   /* hipError_t of the last SW_EHIP */
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SW_H */

@@ -1,0 +1,536 @@
+// Host side of libsw: context management, argument checks and the C ABI
+// declared in include/sw.h.  Every step of the computation runs in the HIP
+// kernels of sw_kernels.hip (and sw_tangent.hip); this file only lays out
+// memory, checks arguments and enqueues launches.
+
+#include "sw.h"
+#include "sw_internal.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+using namespace swk;
+
+struct sw_ctx {
+  int R = 0;
+  long long N = 0;
+  int npad = 0;
+  std::vector<long long> uoff;
+  std::vector<double> box;
+  double cutoff = 0.0, skin = 0.0;
+  int cap = 0, cc = 32;
+  std::vector<RepInfo> reps;
+  int ctot = 0;
+  std::vector<int> tile_rep, cell_rank;
+  sw_tuning tune{8, 0, 0, 0};
+  Dev d{};
+  RepInfo* d_reps = nullptr;
+  int* d_tile_rep = nullptr;
+  long long* d_uoff = nullptr;
+  int* d_cell_rank = nullptr;
+  double* d_T0 = nullptr;
+  uint4* d_uq = nullptr;
+  int *d_key = nullptr, *d_scnt = nullptr, *d_sstart = nullptr, *d_scur = nullptr, *d_order = nullptr;
+  Tan t{};
+  bool have_order = false;
+  long long steps = 0;
+  int last_hip = 0;
+  size_t bytes = 0;
+  std::vector<void*> allocs;       // everything freed by free_all
+  std::vector<void*> grow_allocs;  // capacity-dependent buffers
+};
+
+namespace {
+
+constexpr int kMaxCap = 512;
+constexpr double kLog2e = 1.4426950408889634;
+
+unsigned part1by2(unsigned x) {
+  x &= 0x3ffu;
+  x = (x | (x << 16)) & 0x030000ffu;
+  x = (x | (x << 8)) & 0x0300f00fu;
+  x = (x | (x << 4)) & 0x030c30c3u;
+  x = (x | (x << 2)) & 0x09249249u;
+  return x;
+}
+
+int fail_hip(sw_ctx* c, hipError_t e) {
+  if (c) c->last_hip = (int)e;
+  return SW_EHIP;
+}
+
+template <class T>
+hipError_t dalloc(sw_ctx* c, T** p, size_t n, std::vector<void*>& list) {
+  *p = nullptr;
+  if (n == 0) n = 1;
+  hipError_t e = hipMalloc((void**)p, n * sizeof(T));
+  if (e != hipSuccess) return e;
+  list.push_back((void*)*p);
+  c->bytes += n * sizeof(T);
+  return hipSuccess;
+}
+
+void free_list(std::vector<void*>& list) {
+  for (void* p : list) (void)hipFree(p);
+  list.clear();
+}
+
+int lpa_for(const sw_ctx* c) {
+  int lpa = c->tune.lanes_per_atom;
+  // rebuild staging needs 2 * (256 / lpa) * cap ints of LDS; keep it <= 64 KiB
+  while (lpa < 16 && 2 * (kBlock / lpa) * c->cap * 4 + 4 * (kBlock / lpa) > 65536) lpa *= 2;
+  return lpa;
+}
+
+// Buffers whose size depends on the row and cell capacities.
+hipError_t alloc_capacity(sw_ctx* c) {
+  free_list(c->grow_allocs);
+  hipError_t e;
+  if ((e = dalloc(c, &c->d.nl, (size_t)c->npad * c->cap, c->grow_allocs)) != hipSuccess) return e;
+  for (int k = 0; k < 2; ++k)
+    if ((e = dalloc(c, &c->d.gmem[k], (size_t)c->ctot * c->cc, c->grow_allocs)) != hipSuccess) return e;
+  c->d.cap = c->cap;
+  c->d.cc = c->cc;
+  return hipSuccess;
+}
+
+hipError_t alloc_all(sw_ctx* c) {
+  hipError_t e;
+  auto& L = c->allocs;
+  const size_t np = (size_t)c->npad;
+#define SWA(ptr, n) \
+  if ((e = dalloc(c, &(ptr), (n), L)) != hipSuccess) return e
+  SWA(c->d.u[0], np); SWA(c->d.u[1], np); SWA(c->d.v, np); SWA(c->d.f, np); SWA(c->d.uref, np);
+  SWA(c->d.ids, np); SWA(c->d.nn, np); SWA(c->d.mom, 3 * np);
+  SWA(c->d.gcnt[0], (size_t)c->ctot); SWA(c->d.gcnt[1], (size_t)c->ctot);
+  SWA(c->d.partial, (np / 16 + 1) * kNQ);
+  SWA(c->d.thermo_cur, (size_t)c->R * kNQ);
+  SWA(c->d.arrive, (size_t)c->R);
+  SWA(c->d.dmax, 2);
+  SWA(c->d.flags, F_NFLAGS);
+  SWA(c->d_reps, (size_t)c->R);
+  SWA(c->d_tile_rep, c->tile_rep.size());
+  SWA(c->d_uoff, (size_t)c->R + 1);
+  SWA(c->d_cell_rank, (size_t)c->ctot);
+  SWA(c->d_T0, (size_t)c->R);
+  SWA(c->d_uq, (size_t)c->N); SWA(c->d_key, (size_t)c->N); SWA(c->d_order, (size_t)c->N);
+  SWA(c->d_scnt, (size_t)c->ctot); SWA(c->d_sstart, (size_t)c->ctot); SWA(c->d_scur, (size_t)c->ctot);
+  SWA(c->t.w, np); SWA(c->t.mdot, 3 * np); SWA(c->t.fdot, np); SWA(c->t.f3, np);
+  SWA(c->t.tpartial, (np / 16 + 1) * kTQ);
+#undef SWA
+  if ((e = alloc_capacity(c)) != hipSuccess) return e;
+  c->d.reps = c->d_reps;
+  c->d.tile_rep = c->d_tile_rep;
+  c->d.T0 = c->d_T0;
+  c->d.npad = c->npad;
+  c->d.ctot = c->ctot;
+  c->d.R = c->R;
+  if ((e = hipMemcpy(c->d_reps, c->reps.data(), sizeof(RepInfo) * c->R, hipMemcpyHostToDevice)) != hipSuccess) return e;
+  if ((e = hipMemcpy(c->d_tile_rep, c->tile_rep.data(), sizeof(int) * c->tile_rep.size(), hipMemcpyHostToDevice)) != hipSuccess) return e;
+  if ((e = hipMemcpy(c->d_uoff, c->uoff.data(), sizeof(long long) * (c->R + 1), hipMemcpyHostToDevice)) != hipSuccess) return e;
+  if ((e = hipMemcpy(c->d_cell_rank, c->cell_rank.data(), sizeof(int) * c->ctot, hipMemcpyHostToDevice)) != hipSuccess) return e;
+  if ((e = hipMemset(c->d.arrive, 0, sizeof(int) * c->R)) != hipSuccess) return e;
+  if ((e = hipMemset(c->d.flags, 0, sizeof(int) * F_NFLAGS)) != hipSuccess) return e;
+  if ((e = hipMemset(c->d.dmax, 0, sizeof(unsigned) * 2)) != hipSuccess) return e;
+  if ((e = hipMemset(c->d.thermo_cur, 0, sizeof(double) * kNQ * c->R)) != hipSuccess) return e;
+  return hipSuccess;
+}
+
+int make_phys(const sw_ctx* c, const sw_params* P, double mass, double dt, Phys* o) {
+  if (!P) return SW_EINVAL;
+  if (P->p != 4.0 || P->q != 0.0) return SW_EUNSUPPORTED;
+  const double rc = P->a * P->sigma;
+  if (!(rc > 0.0) || !(P->sigma > 0.0) || !(P->epsilon > 0.0) || !std::isfinite(P->lambda) ||
+      !std::isfinite(P->gamma) || !std::isfinite(P->cos_theta0))
+    return SW_EINVAL;
+  if (rc > c->cutoff * (1.0 + 1e-12)) return SW_EINVAL;
+  const double rl = c->cutoff + c->skin;
+  o->rc = (float)rc;
+  o->rc2 = (float)(rc * rc);
+  o->rl2 = (float)(rl * rl);
+  o->half_skin = (float)(0.5 * (rl - rc) - 1e-4);
+  o->sig = (float)P->sigma;
+  o->sig_l2e = (float)(P->sigma * kLog2e);
+  o->gsig = (float)(P->gamma * P->sigma);
+  o->gsig_l2e = (float)(P->gamma * P->sigma * kLog2e);
+  o->Aeps = (float)(P->A * P->epsilon);
+  o->B = (float)P->B;
+  o->lameps = (float)(P->lambda * P->epsilon);
+  o->c0 = (float)P->cos_theta0;
+  o->qc = (float)((1.0 - P->cos_theta0) * (1.0 - P->cos_theta0));
+  const double m = mass > 0.0 ? mass : 1.0;
+  o->hdt_cm = (float)(0.5 * dt * kAcc / m);
+  o->dt = (float)dt;
+  o->half_m_acc = (float)(0.5 * m / kAcc);
+  o->m_acc = (float)(m / kAcc);
+  o->dt_d = dt;
+  o->tau_d = 1.0;
+  o->thermostat = 0;
+  return SW_OK;
+}
+
+hipError_t reset_flags(sw_ctx* c, hipStream_t s) {
+  // keep the cumulative rebuild counter (slot F_REBUILDS)
+  hipError_t e = launch_fill_i32(c->d.flags, 0, F_REBUILDS, s);
+  if (e != hipSuccess) return e;
+  return launch_fill_i32((int*)c->d.dmax, 0, 2, s);
+}
+
+struct Flags { int nbr_over, nbr_need, cell_over, overlap; };
+
+hipError_t read_flags(sw_ctx* c, hipStream_t s, Flags* f) {
+  int h[F_NFLAGS];
+  hipError_t e = hipMemcpyAsync(h, c->d.flags, sizeof h, hipMemcpyDeviceToHost, s);
+  if (e != hipSuccess) return e;
+  if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
+  f->nbr_over = h[F_NBR_OVER];
+  f->nbr_need = h[F_NBR_NEED];
+  f->cell_over = h[F_CELL_OVER];
+  f->overlap = h[F_OVERLAP];
+  return hipSuccess;
+}
+
+// Grows the capacities named by the flags.  Returns SW_OK if something grew.
+int grow(sw_ctx* c, const Flags& f) {
+  bool grew = false;
+  if (f.nbr_over) {
+    int need = std::max(f.nbr_need + f.nbr_need / 4 + 4, c->cap + 8);
+    need = (need + 3) & ~3;
+    if (c->cap >= kMaxCap) return SW_ENBR_OVERFLOW;
+    c->cap = std::min(need, kMaxCap);
+    grew = true;
+  }
+  if (f.cell_over) {
+    if (c->cc >= 4096) return SW_ECELL_OVERFLOW;
+    c->cc *= 2;
+    grew = true;
+  }
+  if (!grew) return SW_EINVAL;
+  hipError_t e = alloc_capacity(c);
+  if (e != hipSuccess) return e == hipErrorOutOfMemory ? SW_ENOMEM : fail_hip(c, e);
+  c->have_order = false;
+  return SW_OK;
+}
+
+// Sort the caller's atoms along the Morton curve of the binning cells, load
+// them (and velocities if given) into internal order, bin into grid 0.
+hipError_t sort_in(sw_ctx* c, const float* x, const float* v, hipStream_t s) {
+  hipError_t e = launch_sort(c->d, (const float4*)x, (const float4*)v, c->N, c->d_uoff, c->R, c->d_cell_rank,
+                             c->d_uq, c->d_key, c->d_scnt, c->d_sstart, c->d_scur, c->d_order, s);
+  if (e != hipSuccess) return e;
+  if ((e = launch_fill_i32(c->d.gcnt[0], 0, c->ctot, s)) != hipSuccess) return e;
+  if ((e = launch_bin(c->d, 0, 0, s)) != hipSuccess) return e;
+  c->have_order = true;
+  return hipSuccess;
+}
+
+bool valid_ptr(const void* p) { return p != nullptr; }
+
+}  // namespace
+
+extern "C" {
+
+void sw_params_mw(sw_params* out) {
+  if (!out) return;
+  out->lambda = 23.15;
+  out->epsilon = 6.189;
+  out->sigma = 2.3925;
+  out->A = 7.049556277;
+  out->B = 0.6022245584;
+  out->p = 4.0;
+  out->q = 0.0;
+  out->gamma = 1.2;
+  out->a = 1.8;
+  out->cos_theta0 = -1.0 / 3.0;
+}
+
+const char* sw_status_string(int s) {
+  switch (s) {
+    case SW_OK: return "ok";
+    case SW_EINVAL: return "invalid argument";
+    case SW_EBOX_TOO_SMALL: return "box edge shorter than three cells of cutoff + skin";
+    case SW_ENBR_OVERFLOW: return "neighbour row capacity exceeded";
+    case SW_ECELL_OVERFLOW: return "binning cell capacity exceeded";
+    case SW_EOVERLAP: return "atoms overlap (< 0.5 A), non-finite values, or a step longer than a quarter box";
+    case SW_EHIP: return "HIP runtime error";
+    case SW_ENOMEM: return "device memory exhausted";
+    case SW_EUNSUPPORTED: return "unsupported parameter or option";
+    case SW_ESTATE: return "context has no neighbour rows yet";
+  }
+  return "unknown status";
+}
+
+int sw_last_hip_error(const sw_ctx* ctx) { return ctx ? ctx->last_hip : 0; }
+
+int sw_create(sw_ctx** out, int n_replicas, const long long* h_offsets, const double* h_box, double cutoff,
+              double skin, int nbr_capacity) {
+  if (!out) return SW_EINVAL;
+  *out = nullptr;
+  if (n_replicas <= 0 || !h_offsets || !h_box || !(cutoff > 0.0) || !(skin >= 0.0) || nbr_capacity <= 0 ||
+      nbr_capacity > kMaxCap || !std::isfinite(cutoff) || !std::isfinite(skin))
+    return SW_EINVAL;
+  if (h_offsets[0] != 0) return SW_EINVAL;
+  for (int r = 0; r < n_replicas; ++r) {
+    if (h_offsets[r + 1] - h_offsets[r] < 2) return SW_EINVAL;
+    for (int k = 0; k < 3; ++k)
+      if (!(h_box[3 * r + k] > 0.0) || !std::isfinite(h_box[3 * r + k])) return SW_EINVAL;
+  }
+  if (h_offsets[n_replicas] >= (1LL << 30)) return SW_EINVAL;
+  sw_ctx* c = new (std::nothrow) sw_ctx;
+  if (!c) return SW_ENOMEM;
+  c->R = n_replicas;
+  c->N = h_offsets[n_replicas];
+  c->uoff.assign(h_offsets, h_offsets + n_replicas + 1);
+  c->box.assign(h_box, h_box + 3 * n_replicas);
+  c->cutoff = cutoff;
+  c->skin = skin;
+  c->cap = (nbr_capacity + 3) & ~3;
+  const double rl = cutoff + skin;
+  int ioff = 0, coff = 0;
+  for (int r = 0; r < n_replicas; ++r) {
+    RepInfo R{};
+    const int n = (int)(h_offsets[r + 1] - h_offsets[r]);
+    for (int k = 0; k < 3; ++k) {
+      const double L = h_box[3 * r + k];
+      R.L[k] = L;
+      R.scale[k] = (float)(L / kTwo32);
+      R.inv_scale[k] = (float)(kTwo32 / L);
+      const int nc = (int)std::floor(L / rl);
+      if (nc < 3) {
+        delete c;
+        return SW_EBOX_TOO_SMALL;
+      }
+      R.nc[k] = std::min(nc, 1024);
+    }
+    R.ncell = R.nc[0] * R.nc[1] * R.nc[2];
+    R.cell_off = coff;
+    R.ioff = ioff;
+    R.n = n;
+    R.iend = ioff + n;
+    R.ipad_end = ioff + ((n + kTile - 1) / kTile) * kTile;
+    R.uoff = h_offsets[r];
+    R.ndof_kb = (3.0 * n - 3.0) * kBoltz;
+    // Morton rank of every cell of this replica
+    std::vector<std::pair<unsigned, int>> codes(R.ncell);
+    for (int x = 0; x < R.nc[0]; ++x)
+      for (int y = 0; y < R.nc[1]; ++y)
+        for (int z = 0; z < R.nc[2]; ++z) {
+          const int local = (x * R.nc[1] + y) * R.nc[2] + z;
+          codes[local] = {(part1by2(x) << 2) | (part1by2(y) << 1) | part1by2(z), local};
+        }
+    std::sort(codes.begin(), codes.end());
+    c->cell_rank.resize(coff + R.ncell);
+    for (int k = 0; k < R.ncell; ++k) c->cell_rank[coff + codes[k].second] = coff + k;
+    for (int t = ioff / kTile; t < R.ipad_end / kTile; ++t) c->tile_rep.push_back(r);
+    ioff = R.ipad_end;
+    coff += R.ncell;
+    c->reps.push_back(R);
+  }
+  c->npad = ioff;
+  c->ctot = coff;
+  // binning cells hold ~ n * rl^3 atoms on average; start at 4x that, min 32
+  double mean = 0.0;
+  for (const auto& R : c->reps) mean = std::max(mean, (double)R.n / R.ncell);
+  c->cc = std::max(32, (int)std::ceil(4.0 * mean / 8.0) * 8);
+  hipError_t e = alloc_all(c);
+  if (e != hipSuccess) {
+    free_list(c->grow_allocs);
+    free_list(c->allocs);
+    delete c;
+    return e == hipErrorOutOfMemory ? SW_ENOMEM : SW_EHIP;
+  }
+  *out = c;
+  return SW_OK;
+}
+
+void sw_destroy(sw_ctx* ctx) {
+  if (!ctx) return;
+  (void)hipDeviceSynchronize();
+  free_list(ctx->grow_allocs);
+  free_list(ctx->allocs);
+  delete ctx;
+}
+
+int sw_set_tuning(sw_ctx* ctx, const sw_tuning* t) {
+  if (!ctx || !t) return SW_EINVAL;
+  if (t->lanes_per_atom != 4 && t->lanes_per_atom != 8 && t->lanes_per_atom != 16) return SW_EUNSUPPORTED;
+  if (t->graph_steps < 0 || t->rebuild_every < 0 || (t->persistent != 0 && t->persistent != 1)) return SW_EINVAL;
+  ctx->tune = *t;
+  return SW_OK;
+}
+
+int sw_get_tuning(const sw_ctx* ctx, sw_tuning* t) {
+  if (!ctx || !t) return SW_EINVAL;
+  *t = ctx->tune;
+  return SW_OK;
+}
+
+int sw_build_neighbors(sw_ctx* ctx, const float* x, void* stream) {
+  if (!ctx || !valid_ptr(x)) return SW_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  sw_params P;
+  sw_params_mw(&P);
+  P.a = ctx->cutoff / P.sigma;  // rows only need the row radius; moments use the full cut-off
+  Phys ph;
+  int st = make_phys(ctx, &P, 1.0, 1.0, &ph);
+  if (st != SW_OK) return st;
+  for (int attempt = 0; attempt < 6; ++attempt) {
+    hipError_t e;
+    if ((e = reset_flags(ctx, s)) != hipSuccess) return fail_hip(ctx, e);
+    if ((e = sort_in(ctx, x, nullptr, s)) != hipSuccess) return fail_hip(ctx, e);
+    if ((e = launch_moments(ctx->d, ph, lpa_for(ctx), 0, 1, 0, s)) != hipSuccess) return fail_hip(ctx, e);
+    Flags f;
+    if ((e = read_flags(ctx, s, &f)) != hipSuccess) return fail_hip(ctx, e);
+    if (!f.nbr_over && !f.cell_over) return SW_OK;
+    if ((st = grow(ctx, f)) != SW_OK) return st;
+  }
+  return SW_ENBR_OVERFLOW;
+}
+
+int sw_get_neighbors(sw_ctx* ctx, int* h_counts, int* h_rows, int max_per_row) {
+  if (!ctx || !h_counts || !h_rows || max_per_row <= 0) return SW_EINVAL;
+  if (!ctx->have_order) return SW_ESTATE;
+  const size_t np = ctx->npad;
+  std::vector<int> nn(np), ids(np), nl(np * ctx->cap);
+  hipError_t e;
+  if ((e = hipDeviceSynchronize()) != hipSuccess) return fail_hip(ctx, e);
+  if ((e = hipMemcpy(nn.data(), ctx->d.nn, sizeof(int) * np, hipMemcpyDeviceToHost)) != hipSuccess) return fail_hip(ctx, e);
+  if ((e = hipMemcpy(ids.data(), ctx->d.ids, sizeof(int) * np, hipMemcpyDeviceToHost)) != hipSuccess) return fail_hip(ctx, e);
+  if ((e = hipMemcpy(nl.data(), ctx->d.nl, sizeof(int) * np * ctx->cap, hipMemcpyDeviceToHost)) != hipSuccess) return fail_hip(ctx, e);
+  for (size_t i = 0; i < np; ++i) {
+    const int k = ids[i];
+    if (k < 0) continue;
+    if (nn[i] > max_per_row) return SW_EINVAL;
+    h_counts[k] = nn[i];
+    int* row = h_rows + (size_t)k * max_per_row;
+    for (int s = 0; s < nn[i]; ++s) row[s] = ids[nl[i * ctx->cap + s]];
+    std::sort(row, row + nn[i]);
+    for (int s = nn[i]; s < max_per_row; ++s) row[s] = -1;
+  }
+  return SW_OK;
+}
+
+int sw_forces(sw_ctx* ctx, const float* x, const sw_params* params, float* f, double* energy, double* virial,
+              void* stream) {
+  if (!ctx || !valid_ptr(x) || !valid_ptr(f)) return SW_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  Phys ph;
+  int st = make_phys(ctx, params, 1.0, 1.0, &ph);
+  if (st != SW_OK) return st;
+  for (int attempt = 0; attempt < 6; ++attempt) {
+    hipError_t e;
+    if ((e = reset_flags(ctx, s)) != hipSuccess) return fail_hip(ctx, e);
+    int force_rebuild = 0;
+    if (!ctx->have_order) {
+      if ((e = sort_in(ctx, x, nullptr, s)) != hipSuccess) return fail_hip(ctx, e);
+      force_rebuild = 1;
+    } else {
+      if ((e = launch_gather_ids(ctx->d, (const float4*)x, 0, s)) != hipSuccess) return fail_hip(ctx, e);
+      if ((e = launch_fill_i32(ctx->d.gcnt[0], 0, ctx->ctot, s)) != hipSuccess) return fail_hip(ctx, e);
+      if ((e = launch_bin(ctx->d, 0, 1, s)) != hipSuccess) return fail_hip(ctx, e);
+    }
+    const int lpa = lpa_for(ctx);
+    if ((e = launch_moments(ctx->d, ph, lpa, 0, force_rebuild, 1, s)) != hipSuccess) return fail_hip(ctx, e);
+    if ((e = launch_forces(ctx->d, ph, lpa, MODE_FORCES, 1, 0, nullptr, s)) != hipSuccess) return fail_hip(ctx, e);
+    Flags fl;
+    if ((e = read_flags(ctx, s, &fl)) != hipSuccess) return fail_hip(ctx, e);
+    if (fl.nbr_over || fl.cell_over) {
+      if ((st = grow(ctx, fl)) != SW_OK) return st;
+      continue;
+    }
+    if ((e = launch_scatter_out(ctx->d, 0, nullptr, nullptr, (float4*)f, s)) != hipSuccess) return fail_hip(ctx, e);
+    if ((energy || virial) && (e = launch_copy_thermo(ctx->d, energy, virial, s)) != hipSuccess)
+      return fail_hip(ctx, e);
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) return fail_hip(ctx, e);
+    return fl.overlap ? SW_EOVERLAP : SW_OK;
+  }
+  return SW_ENBR_OVERFLOW;
+}
+
+int sw_step(sw_ctx* ctx, float* x, float* v, float* f, const sw_params* params, double mass, double dt,
+            int nsteps, int thermostat, const double* h_T0, double tau_fs, double* thermo, int thermo_every,
+            void* stream) {
+  if (!ctx || !valid_ptr(x) || !valid_ptr(v) || !valid_ptr(f)) return SW_EINVAL;
+  if (!(mass > 0.0) || !(dt > 0.0) || nsteps < 0 || !std::isfinite(mass) || !std::isfinite(dt)) return SW_EINVAL;
+  if (thermostat < SW_NVE || thermostat > SW_BERENDSEN) return SW_EINVAL;
+  if (thermostat != SW_NVE && !h_T0) return SW_EINVAL;
+  if (thermostat == SW_BERENDSEN && !(tau_fs > 0.0)) return SW_EINVAL;
+  if (thermo && thermo_every <= 0) return SW_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  Phys ph;
+  int st = make_phys(ctx, params, mass, dt, &ph);
+  if (st != SW_OK) return st;
+  ph.thermostat = thermostat;
+  ph.tau_d = thermostat == SW_BERENDSEN ? tau_fs : 1.0;
+  hipError_t e;
+  if (thermostat != SW_NVE) {
+    for (int r = 0; r < ctx->R; ++r)
+      if (!(h_T0[r] >= 0.0) || !std::isfinite(h_T0[r])) return SW_EINVAL;
+    if ((e = hipMemcpyAsync(ctx->d_T0, h_T0, sizeof(double) * ctx->R, hipMemcpyHostToDevice, s)) != hipSuccess)
+      return fail_hip(ctx, e);
+  }
+  const int lpa = lpa_for(ctx);
+  for (int attempt = 0; attempt < 6; ++attempt) {
+    if ((e = reset_flags(ctx, s)) != hipSuccess) return fail_hip(ctx, e);
+    if ((e = sort_in(ctx, x, v, s)) != hipSuccess) return fail_hip(ctx, e);
+    if ((e = launch_moments(ctx->d, ph, lpa, 0, 1, 0, s)) != hipSuccess) return fail_hip(ctx, e);
+    if (nsteps == 0) {
+      if ((e = launch_forces(ctx->d, ph, lpa, MODE_FORCES, 1, 0, nullptr, s)) != hipSuccess) return fail_hip(ctx, e);
+    } else {
+      if ((e = launch_forces(ctx->d, ph, lpa, MODE_START, 0, 0, nullptr, s)) != hipSuccess) return fail_hip(ctx, e);
+      for (int t = 1; t <= nsteps; ++t) {
+        const int par = t & 1;
+        const bool rec = thermo && (t % thermo_every == 0);
+        double* row = rec ? thermo + (size_t)(t / thermo_every - 1) * ctx->R * kNQ : nullptr;
+        const int force_rb = ctx->tune.rebuild_every > 0 && (t % ctx->tune.rebuild_every == 0);
+        if ((e = launch_moments(ctx->d, ph, lpa, par, force_rb, rec, s)) != hipSuccess) return fail_hip(ctx, e);
+        if (thermostat == SW_NVE) {
+          const int mode = t == nsteps ? MODE_NVE_LAST : MODE_NVE;
+          if ((e = launch_forces(ctx->d, ph, lpa, mode, rec, par, row, s)) != hipSuccess) return fail_hip(ctx, e);
+        } else {
+          if ((e = launch_forces(ctx->d, ph, lpa, MODE_KICK, rec, par, row, s)) != hipSuccess) return fail_hip(ctx, e);
+          if ((e = launch_thermostat(ctx->d, ph, par, t == nsteps, s)) != hipSuccess) return fail_hip(ctx, e);
+        }
+      }
+    }
+    Flags fl;
+    if ((e = read_flags(ctx, s, &fl)) != hipSuccess) return fail_hip(ctx, e);
+    if (fl.nbr_over || fl.cell_over) {
+      if ((st = grow(ctx, fl)) != SW_OK) return st;
+      continue;
+    }
+    const int par_final = nsteps & 1;
+    if ((e = launch_scatter_out(ctx->d, par_final, (float4*)x, (float4*)v, (float4*)f, s)) != hipSuccess)
+      return fail_hip(ctx, e);
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) return fail_hip(ctx, e);
+    ctx->steps += nsteps;
+    return fl.overlap ? SW_EOVERLAP : SW_OK;
+  }
+  return SW_ENBR_OVERFLOW;
+}
+
+int sw_query(sw_ctx* ctx, int what, long long* out) {
+  if (!ctx || !out) return SW_EINVAL;
+  switch (what) {
+    case SW_Q_NATOMS: *out = ctx->N; return SW_OK;
+    case SW_Q_NREPLICAS: *out = ctx->R; return SW_OK;
+    case SW_Q_NBR_CAPACITY: *out = ctx->cap; return SW_OK;
+    case SW_Q_CELL_CAPACITY: *out = ctx->cc; return SW_OK;
+    case SW_Q_DEVICE_BYTES: *out = (long long)ctx->bytes; return SW_OK;
+    case SW_Q_STEPS: *out = ctx->steps; return SW_OK;
+    case SW_Q_REBUILDS: {
+      int h[F_NFLAGS];
+      hipError_t e = hipDeviceSynchronize();
+      if (e == hipSuccess) e = hipMemcpy(h, ctx->d.flags, sizeof h, hipMemcpyDeviceToHost);
+      if (e != hipSuccess) return fail_hip(ctx, e);
+      *out = h[F_REBUILDS];
+      return SW_OK;
+    }
+  }
+  return SW_EINVAL;
+}
+
+}  // extern "C"

@@ -1,0 +1,121 @@
+// Internal layout shared by the HIP kernels and the host side of libsw.
+// Not part of the public ABI (include/sw.h is).
+//
+// Data layout in HBM (all arrays indexed by the internal atom index i, which
+// is the caller's atom order re-sorted per replica along a Morton curve over
+// the binning cells, each replica padded to a multiple of 64 atoms):
+//   u[2][Npad]        uint4   positions as unsigned 32-bit fractions of the box
+//                             edge (x = u * L / 2^32); ping-pong buffers
+//   v[Npad], f[Npad]  float4  velocities (A/fs), forces (kcal/mol/A)
+//   uref[Npad]        uint4   positions at the last neighbour-row build
+//   ids[Npad]         int     caller index of internal atom i (-1 for padding)
+//   nl[Npad][cap]     int     neighbour rows (internal indices, ascending)
+//   nn[Npad]          int     row lengths
+//   mom[Npad][3]      float4  per-centre three-body moments and energies
+//   gcnt[2][Ctot], gmem[2][Ctot][cc]   binning cells (ping-pong)
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace swk {
+
+constexpr int kBlock = 256;        // threads per block of every atom kernel
+constexpr int kTile = 64;          // replicas are padded to multiples of this
+constexpr int kNQ = 12;            // thermo quantities per replica
+constexpr double kAcc = 4.184e-4;  // (A/fs^2) per ((kcal/mol/A)/(g/mol))
+constexpr double kBoltz = 8.314462618 / 4184.0;  // kcal/(mol K)
+constexpr double kTwo32 = 4294967296.0;
+
+// Flag slots in Dev::flags.
+enum { F_NBR_OVER = 0, F_NBR_NEED = 1, F_CELL_OVER = 2, F_OVERLAP = 3, F_REBUILDS = 4,
+       F_MAXROW = 5, F_NFLAGS = 8 };
+
+struct RepInfo {
+  double L[3];        // box edges (A)
+  float scale[3];     // L / 2^32 : fraction units -> A
+  float inv_scale[3]; // 2^32 / L
+  int nc[3];          // binning cells per edge (each edge >= cutoff + skin)
+  int cell_off;       // first cell of this replica in the concatenated grid
+  int ncell;
+  int ioff;           // first internal atom
+  int iend;           // ioff + n
+  int ipad_end;       // ioff + roundup(n, 64)
+  int n;
+  long long uoff;     // first caller atom
+  double ndof_kb;     // (3n - 3) k_B
+};
+
+// Device pointers and sizes of one context (passed by value to kernels).
+struct Dev {
+  uint4* u[2];
+  float4* v;
+  float4* f;
+  uint4* uref;
+  int* ids;
+  int* nl;
+  int* nn;
+  float4* mom;
+  int* gcnt[2];
+  int* gmem[2];
+  double* partial;     // [nblocks][kNQ]
+  double* thermo_cur;  // [R][kNQ]
+  int* arrive;         // [R]
+  unsigned* dmax;      // [2] largest displacement since the build (float bits, A)
+  int* flags;          // [F_NFLAGS]
+  const RepInfo* reps;
+  const int* tile_rep; // [Npad / 64] replica of each 64-atom tile
+  const double* T0;    // [R] thermostat targets
+  int npad, cap, cc, ctot, R;
+};
+
+// Per-call physical constants, pre-folded for the kernels.
+struct Phys {
+  float rc, rc2;        // a*sigma and its square
+  float rl2;            // (cutoff + skin)^2 : row radius
+  float half_skin;      // rebuild when an atom moved more than this (A)
+  float sig, sig_l2e;   // sigma, sigma*log2(e)
+  float gsig, gsig_l2e; // gamma*sigma and times log2(e)
+  float Aeps, B;        // A*epsilon, B
+  float lameps, c0, qc; // lambda*epsilon, cos(theta0), (1 - cos theta0)^2
+  float hdt_cm;         // dt/2 * 4.184e-4 / mass
+  float dt;
+  float half_m_acc;     // 0.5 * mass / 4.184e-4 (KE in kcal/mol from A/fs)
+  float m_acc;          // mass / 4.184e-4
+  double dt_d, tau_d;   // thermostat
+  int thermostat;       // SW_NVE / SW_RESCALE / SW_BERENDSEN
+};
+
+// Kernel modes of the force kernel.
+enum { MODE_FORCES = 0, MODE_START = 1, MODE_NVE = 2, MODE_NVE_LAST = 3, MODE_KICK = 4 };
+
+// Host launchers (sw_kernels.hip).  Each returns a hipError_t.
+hipError_t launch_sort(const Dev& d, const float4* x_user, const float4* v_user, long long n_user,
+                       const long long* uoff, int R, const int* cell_rank, uint4* uq, int* key,
+                       int* cnt, int* start, int* cursor, int* order, hipStream_t s);
+hipError_t launch_gather_ids(const Dev& d, const float4* x_user, int par, hipStream_t s);
+hipError_t launch_bin(const Dev& d, int par, int check_disp, hipStream_t s);
+hipError_t launch_moments(const Dev& d, const Phys& p, int lpa, int par, int force_rebuild,
+                          int energy, hipStream_t s);
+hipError_t launch_forces(const Dev& d, const Phys& p, int lpa, int mode, int vir, int par,
+                         double* ring_row, hipStream_t s);
+hipError_t launch_thermostat(const Dev& d, const Phys& p, int par, int last, hipStream_t s);
+hipError_t launch_scatter_out(const Dev& d, int par, float4* x_user, float4* v_user,
+                              float4* f_user, hipStream_t s);
+hipError_t launch_copy_thermo(const Dev& d, double* energy, double* virial, hipStream_t s);
+hipError_t launch_fill_i32(int* p, int value, long long n, hipStream_t s);
+hipError_t launch_fill_f32(float* p, float value, long long n, hipStream_t s);
+
+// Tangent (forward-mode) kernels for sw_grad / sw_adjoint.
+struct Tan {
+  float4* w;        // [Npad] tangent direction (A)
+  float4* mdot;     // [Npad][3] tangent of the moments
+  float4* fdot;     // [Npad] tangent of the forces
+  float4* f3;       // [Npad] three-body part of the forces
+  double* tpartial; // [nblocks][kTQ]
+};
+constexpr int kTQ = 8;  // E2, E3, W2tr, W3tr, wdotF, wdotF3, wdotWdot(tangent of W trace), pad
+hipError_t launch_tan_moments(const Dev& d, const Tan& t, const Phys& p, int par, hipStream_t s);
+hipError_t launch_tan_forces(const Dev& d, const Tan& t, const Phys& p, int par, double* out_rows,
+                             hipStream_t s);
+
+}  // namespace swk

@@ -1,0 +1,720 @@
+// HIP kernels of the mW Stillinger-Weber engine for gfx950 (MI355X).
+//
+// Model: Eq. E of Sec. II.A (pair term phi2 plus the three-body term phi3 with
+// its vertex at the centre atom), parameters of Sec. II.A / II.D.
+//
+// The three-body energy of centre i is evaluated from per-centre moments.
+// With e_j = exp(gamma sigma / (r_ij - a sigma)), unit vectors u_j and
+// c0 = cos(theta0):
+//   T = sum_j e_j u_j u_j^T,  V = sum_j e_j u_j,  S = sum_j e_j,  P = sum_j e_j^2
+//   sum_{j<k} e_j e_k (u_j.u_k - c0)^2 = 1/2 [ |T|_F^2 - 2 c0 |V|^2 + c0^2 S^2 - (1-c0)^2 P ]
+// an exact identity (the diagonal j = k terms are removed by the P term), so
+// E3_i = lambda eps times the bracket.  Its gradient with respect to the leg
+// vector d_j = r_j u_j is
+//   G_j = lambda eps e_j [ g_j q_j u_j + (2/r_j) (I - u_j u_j^T)(T u_j - c0 V) ]
+//   q_j = u_j^T T u_j - 2 c0 V.u_j + c0^2 S - e_j (1-c0)^2,  g_j = -gamma sigma/(r_j - a sigma)^2
+// The force on atom m gathers its own centre's G (with + sign) and minus the
+// G of every neighbour centre i evaluated on the leg i->m, so each atom writes
+// only its own force: no atomics, deterministic sums.  One moments kernel and
+// one force kernel make a step; the force kernel also integrates.
+//
+// Positions are unsigned 32-bit fractions of the box edge: the minimum image
+// of a difference is its two's-complement value, exact for any box size.
+
+#include "sw_internal.h"
+
+namespace swk {
+namespace {
+
+__device__ __forceinline__ int xcd_remap(int bid, int G) {
+  // Blocks are dealt round-robin to the 8 XCDs; give each XCD a contiguous
+  // range of (spatially sorted) tiles so neighbour gathers share its L2.
+  const int xcd = bid & 7, local = bid >> 3;
+  const int per = G >> 3, rem = G & 7;
+  return xcd * per + min(xcd, rem) + local;
+}
+
+__device__ __forceinline__ float3 disp(const uint4& a, const uint4& b, const float sc0, const float sc1,
+                                       const float sc2) {
+  return make_float3((float)(int)(b.x - a.x) * sc0, (float)(int)(b.y - a.y) * sc1,
+                     (float)(int)(b.z - a.z) * sc2);
+}
+
+__device__ __forceinline__ int cell_of(const uint4& u, const int nc0, const int nc1, const int nc2) {
+  const int cx = (int)__umulhi(u.x, (unsigned)nc0);
+  const int cy = (int)__umulhi(u.y, (unsigned)nc1);
+  const int cz = (int)__umulhi(u.z, (unsigned)nc2);
+  return (cx * nc1 + cy) * nc2 + cz;
+}
+
+__device__ __forceinline__ unsigned quantize(float x, double inv_L) {
+  double fr = (double)x * inv_L;
+  fr -= floor(fr);
+  return (unsigned)(unsigned long long)(fr * kTwo32);  // 2^32 wraps to 0
+}
+
+template <int W>
+__device__ __forceinline__ float group_sum(float v) {
+#pragma unroll
+  for (int m = W / 2; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+  return v;
+}
+
+__device__ __forceinline__ float wave_max(float v) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) v = fmaxf(v, __shfl_xor(v, m, 64));
+  return v;
+}
+
+__device__ __forceinline__ float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ float ex2(float x) { return __builtin_amdgcn_exp2f(x); }
+
+// Drift by dt*v in fraction units, bin into grid `gp`, return the distance
+// from the row-build reference.  Flags steps longer than a quarter edge.
+__device__ __forceinline__ float drift_bin(const Dev& d, const Phys& p, const RepInfo& R, int i,
+                                           uint4 u, const float4& v, int gp) {
+  const float mx = p.dt * v.x * R.inv_scale[0];
+  const float my = p.dt * v.y * R.inv_scale[1];
+  const float mz = p.dt * v.z * R.inv_scale[2];
+  const float lim = 1073741824.0f;  // 2^30: a quarter of the edge
+  if (!(fabsf(mx) < lim && fabsf(my) < lim && fabsf(mz) < lim)) atomicOr(&d.flags[F_OVERLAP], 2);
+  u.x += (unsigned)__float2int_rn(fminf(fmaxf(mx, -lim), lim));
+  u.y += (unsigned)__float2int_rn(fminf(fmaxf(my, -lim), lim));
+  u.z += (unsigned)__float2int_rn(fminf(fmaxf(mz, -lim), lim));
+  d.u[gp][i] = u;
+  const int c = R.cell_off + cell_of(u, R.nc[0], R.nc[1], R.nc[2]);
+  const int slot = atomicAdd(&d.gcnt[gp][c], 1);
+  if (slot < d.cc) d.gmem[gp][(size_t)c * d.cc + slot] = i;
+  else atomicOr(&d.flags[F_CELL_OVER], 1);
+  const float3 dd = disp(d.uref[i], u, R.scale[0], R.scale[1], R.scale[2]);
+  return sqrtf(dd.x * dd.x + dd.y * dd.y + dd.z * dd.z);
+}
+
+// ----------------------------------------------------------------- sorting
+__global__ __launch_bounds__(kBlock) void k_sort_count(const float4* __restrict__ x, long long n,
+                                                      const long long* __restrict__ uoff, int R,
+                                                      const RepInfo* __restrict__ reps,
+                                                      const int* __restrict__ cell_rank,
+                                                      uint4* __restrict__ uq, int* __restrict__ key,
+                                                      int* __restrict__ cnt) {
+  const long long k = (long long)blockIdx.x * kBlock + threadIdx.x;
+  if (k >= n) return;
+  int lo = 0, hi = R - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (uoff[mid] <= k) lo = mid; else hi = mid - 1;
+  }
+  const RepInfo& Rp = reps[lo];
+  const float4 p = x[k];
+  const uint4 u = make_uint4(quantize(p.x, 1.0 / Rp.L[0]), quantize(p.y, 1.0 / Rp.L[1]),
+                             quantize(p.z, 1.0 / Rp.L[2]), 0u);
+  const int rank = cell_rank[Rp.cell_off + cell_of(u, Rp.nc[0], Rp.nc[1], Rp.nc[2])];
+  uq[k] = u;
+  key[k] = rank;
+  atomicAdd(&cnt[rank], 1);
+}
+
+// Exclusive scan of n counts with one block of 1024 threads.
+__global__ __launch_bounds__(1024) void k_scan(const int* __restrict__ cnt, int* __restrict__ start, int n) {
+  __shared__ int part[1024];
+  const int t = threadIdx.x;
+  const int per = (n + 1023) / 1024;
+  const int b = min(n, t * per), e = min(n, b + per);
+  int s = 0;
+  for (int k = b; k < e; ++k) s += cnt[k];
+  part[t] = s;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {
+    const int add = t >= off ? part[t - off] : 0;
+    __syncthreads();
+    part[t] += add;
+    __syncthreads();
+  }
+  int run = part[t] - s;
+  for (int k = b; k < e; ++k) {
+    start[k] = run;
+    run += cnt[k];
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_sort_scatter(long long n, const int* __restrict__ key,
+                                                        const int* __restrict__ start, int* __restrict__ cursor,
+                                                        int* __restrict__ order) {
+  const long long k = (long long)blockIdx.x * kBlock + threadIdx.x;
+  if (k >= n) return;
+  const int r = key[k];
+  order[start[r] + atomicAdd(&cursor[r], 1)] = (int)k;
+}
+
+// Within each cell, order atoms by caller index so the layout is deterministic.
+__global__ __launch_bounds__(kBlock) void k_sort_cells(int ncell, const int* __restrict__ cnt,
+                                                      const int* __restrict__ start, int* __restrict__ order) {
+  const int c = blockIdx.x * kBlock + threadIdx.x;
+  if (c >= ncell) return;
+  const int b = start[c], m = cnt[c];
+  for (int a = 1; a < m; ++a) {
+    const int v = order[b + a];
+    int q = a - 1;
+    while (q >= 0 && order[b + q] > v) {
+      order[b + q + 1] = order[b + q];
+      --q;
+    }
+    order[b + q + 1] = v;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_gather_sorted(Dev d, const uint4* __restrict__ uq,
+                                                         const float4* __restrict__ v_user,
+                                                         const int* __restrict__ order) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= d.npad) return;
+  const RepInfo& R = d.reps[d.tile_rep[i >> 6]];
+  const int local = i - R.ioff;
+  if (local < R.n) {
+    const int k = order[R.uoff + local];
+    d.ids[i] = k;
+    d.u[0][i] = uq[k];
+    float4 vv = v_user ? v_user[k] : make_float4(0.f, 0.f, 0.f, 0.f);
+    vv.w = 0.f;
+    d.v[i] = vv;
+  } else {
+    d.ids[i] = -1;
+    d.u[0][i] = make_uint4(0u, 0u, 0u, 0u);
+    d.u[1][i] = make_uint4(0u, 0u, 0u, 0u);
+    d.v[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+    d.f[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+    d.uref[i] = make_uint4(0u, 0u, 0u, 0u);
+    d.nn[i] = 0;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_gather_ids(Dev d, const float4* __restrict__ x_user, int par) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= d.npad) return;
+  const int k = d.ids[i];
+  if (k < 0) return;
+  const RepInfo& R = d.reps[d.tile_rep[i >> 6]];
+  const float4 p = x_user[k];
+  d.u[par][i] = make_uint4(quantize(p.x, 1.0 / R.L[0]), quantize(p.y, 1.0 / R.L[1]),
+                           quantize(p.z, 1.0 / R.L[2]), 0u);
+}
+
+// Bin positions u[par] into grid `par` (counts must be zero) and, if asked,
+// record the largest displacement from the row-build reference.
+__global__ __launch_bounds__(kBlock) void k_bin(Dev d, int par, int check) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  float dist = 0.f;
+  if (i < d.npad) {
+    const RepInfo& R = d.reps[d.tile_rep[i >> 6]];
+    if (i < R.iend) {
+      const uint4 u = d.u[par][i];
+      const int c = R.cell_off + cell_of(u, R.nc[0], R.nc[1], R.nc[2]);
+      const int slot = atomicAdd(&d.gcnt[par][c], 1);
+      if (slot < d.cc) d.gmem[par][(size_t)c * d.cc + slot] = i;
+      else atomicOr(&d.flags[F_CELL_OVER], 1);
+      if (check) {
+        const float3 dd = disp(d.uref[i], u, R.scale[0], R.scale[1], R.scale[2]);
+        dist = sqrtf(dd.x * dd.x + dd.y * dd.y + dd.z * dd.z);
+      }
+    }
+  }
+  dist = wave_max(dist);
+  if (check && (threadIdx.x & 63) == 0 && dist > 0.f) atomicMax(&d.dmax[par], __float_as_uint(dist));
+}
+
+// ----------------------------------------------------------------- moments
+// One group of LPA lanes per atom.  When the displacement flag (or the
+// caller) asks for it, the group first rebuilds the atom's neighbour row from
+// the 27 surrounding binning cells, then accumulates T, V, S (and P, E2 on
+// energy steps) over the active neighbours r < a sigma.
+template <int LPA, bool ENERGY>
+__global__ __launch_bounds__(kBlock) void k_moments(Dev d, Phys p, int par, int force_rebuild) {
+  constexpr int APB = kBlock / LPA;
+  extern __shared__ int lds[];
+  const int bid = xcd_remap(blockIdx.x, gridDim.x);
+  const int g = threadIdx.x / LPA, lane = threadIdx.x % LPA;
+  const int i = bid * APB + g;
+  const RepInfo& R = d.reps[d.tile_rep[(bid * APB) >> 6]];
+  const float sc0 = R.scale[0], sc1 = R.scale[1], sc2 = R.scale[2];
+
+  if (blockIdx.x == 0 && threadIdx.x == 0) d.dmax[par ^ 1] = 0u;
+  for (int c = blockIdx.x * kBlock + threadIdx.x; c < d.ctot; c += gridDim.x * kBlock) d.gcnt[par ^ 1][c] = 0;
+
+  const bool rebuild = force_rebuild || (__uint_as_float(d.dmax[par]) > p.half_skin);
+  const bool real = i < R.iend;
+  const uint4 ui = d.u[par][i];
+  const int cap = d.cap;
+  int nn = 0;
+  const int* row = d.nl + (size_t)i * cap;
+
+  if (rebuild) {
+    int* cand = lds + g * cap;
+    int* srt = lds + APB * cap + g * cap;
+    int* cnt = lds + 2 * APB * cap;
+    if (lane == 0) cnt[g] = 0;
+    __syncthreads();
+    if (real) {
+      const int n0 = R.nc[0], n1 = R.nc[1], n2 = R.nc[2];
+      const int cx = (int)__umulhi(ui.x, (unsigned)n0);
+      const int cy = (int)__umulhi(ui.y, (unsigned)n1);
+      const int cz = (int)__umulhi(ui.z, (unsigned)n2);
+      const int* gc = d.gcnt[par];
+      const int* gm = d.gmem[par];
+      const uint4* up = d.u[par];
+      for (int c = lane; c < 27; c += LPA) {
+        int xx = cx + c / 9 - 1, yy = cy + (c / 3) % 3 - 1, zz = cz + c % 3 - 1;
+        xx = xx < 0 ? xx + n0 : (xx >= n0 ? xx - n0 : xx);
+        yy = yy < 0 ? yy + n1 : (yy >= n1 ? yy - n1 : yy);
+        zz = zz < 0 ? zz + n2 : (zz >= n2 ? zz - n2 : zz);
+        const int cell = R.cell_off + (xx * n1 + yy) * n2 + zz;
+        const int m = min(gc[cell], d.cc);
+        const int* mem = gm + (size_t)cell * d.cc;
+        for (int k = 0; k < m; ++k) {
+          const int j = mem[k];
+          if (j == i) continue;
+          const float3 dd = disp(ui, up[j], sc0, sc1, sc2);
+          if (dd.x * dd.x + dd.y * dd.y + dd.z * dd.z < p.rl2) {
+            const int s = atomicAdd(&cnt[g], 1);
+            if (s < cap) cand[s] = j;
+          }
+        }
+      }
+    }
+    __syncthreads();
+    int total = cnt[g];
+    if (real && lane == 0 && total > cap) {
+      atomicOr(&d.flags[F_NBR_OVER], 1);
+      atomicMax(&d.flags[F_NBR_NEED], total);
+    }
+    total = min(total, cap);
+    if (real) {
+      for (int k = lane; k < total; k += LPA) {
+        const int vj = cand[k];
+        int rank = 0;
+        for (int q = 0; q < total; ++q) rank += cand[q] < vj;
+        srt[rank] = vj;
+        d.nl[(size_t)i * cap + rank] = vj;
+      }
+      if (lane == 0) {
+        d.nn[i] = total;
+        d.uref[i] = ui;
+      }
+    }
+    __syncthreads();
+    nn = real ? total : 0;
+    row = srt;
+    if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(&d.flags[F_REBUILDS], 1);
+  } else {
+    nn = real ? d.nn[i] : 0;
+  }
+
+  float T0 = 0.f, T1 = 0.f, T2 = 0.f, T3 = 0.f, T4 = 0.f, T5 = 0.f;
+  float V0 = 0.f, V1 = 0.f, V2 = 0.f, S = 0.f, P = 0.f, E2 = 0.f;
+  const uint4* up = d.u[par];
+  for (int s = lane; s < nn; s += LPA) {
+    const int j = row[s];
+    const float3 dd = disp(ui, up[j], sc0, sc1, sc2);
+    const float r2 = dd.x * dd.x + dd.y * dd.y + dd.z * dd.z;
+    if (r2 < p.rc2) {
+      const float ir = rsq(r2);
+      const float ux = dd.x * ir, uy = dd.y * ir, uz = dd.z * ir;
+      const float idr = rcp(r2 * ir - p.rc);
+      const float eg = ex2(p.gsig_l2e * idr);
+      const float ex = eg * ux, ey = eg * uy, ez = eg * uz;
+      T0 += ex * ux; T1 += ey * uy; T2 += ez * uz;
+      T3 += ex * uy; T4 += ex * uz; T5 += ey * uz;
+      V0 += ex; V1 += ey; V2 += ez; S += eg;
+      if (ENERGY) {
+        P += eg * eg;
+        const float e1 = ex2(p.sig_l2e * idr);
+        const float sr = p.sig * ir, s2 = sr * sr;
+        E2 += 0.5f * p.Aeps * (p.B * s2 * s2 - 1.f) * e1;
+      }
+    }
+  }
+  T0 = group_sum<LPA>(T0); T1 = group_sum<LPA>(T1); T2 = group_sum<LPA>(T2);
+  T3 = group_sum<LPA>(T3); T4 = group_sum<LPA>(T4); T5 = group_sum<LPA>(T5);
+  V0 = group_sum<LPA>(V0); V1 = group_sum<LPA>(V1); V2 = group_sum<LPA>(V2);
+  S = group_sum<LPA>(S);
+  float E3 = 0.f;
+  if (ENERGY) {
+    P = group_sum<LPA>(P);
+    E2 = group_sum<LPA>(E2);
+    const float tn2 = T0 * T0 + T1 * T1 + T2 * T2 + 2.f * (T3 * T3 + T4 * T4 + T5 * T5);
+    const float vn2 = V0 * V0 + V1 * V1 + V2 * V2;
+    E3 = 0.5f * p.lameps * (tn2 - 2.f * p.c0 * vn2 + p.c0 * p.c0 * S * S - p.qc * P);
+  }
+  if (real && lane == 0) {
+    float4* m = d.mom + 3 * (size_t)i;
+    m[0] = make_float4(T0, T1, T2, T3);
+    m[1] = make_float4(T4, T5, V0, V1);
+    m[2] = make_float4(V2, S, E2, E3);
+  }
+}
+
+// ----------------------------------------------------------------- forces
+// Block partial sums of the thermo quantities, then the last block of each
+// replica (arrival counter) adds the replica's partials in block order.
+template <int APB>
+__device__ void reduce_thermo(const Dev& d, int bid, int rep, const RepInfo& R, const double* q, bool writer,
+                              int g, double* ring_row) {
+  __shared__ double red[APB * kNQ];
+  __shared__ double tree[kBlock];
+  __shared__ int is_last;
+  if (writer) {
+#pragma unroll
+    for (int k = 0; k < kNQ; ++k) red[g * kNQ + k] = q[k];
+  }
+  __syncthreads();
+  if (threadIdx.x < kNQ) {
+    double acc = 0.0;
+    for (int a = 0; a < APB; ++a) acc += red[a * kNQ + threadIdx.x];
+    d.partial[(size_t)bid * kNQ + threadIdx.x] = acc;
+  }
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int nblk = (R.ipad_end - R.ioff) / APB;
+    is_last = atomicAdd(&d.arrive[rep], 1) == nblk - 1;
+  }
+  __syncthreads();
+  if (!is_last) return;
+  __threadfence();
+  const int b0 = R.ioff / APB, b1 = R.ipad_end / APB;
+  for (int k = 0; k < kNQ; ++k) {
+    double acc = 0.0;
+    for (int b = b0 + (int)threadIdx.x; b < b1; b += kBlock) acc += __ldg(&d.partial[(size_t)b * kNQ + k]);
+    tree[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = kBlock / 2; s > 0; s >>= 1) {
+      if ((int)threadIdx.x < s) tree[threadIdx.x] += tree[threadIdx.x + s];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+      d.thermo_cur[rep * kNQ + k] = tree[0];
+      if (ring_row) ring_row[rep * kNQ + k] = tree[0];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) d.arrive[rep] = 0;
+}
+
+// Force on each atom from its neighbours (pair term + its own centre's
+// three-body term + the legs of the neighbour centres), then, by mode:
+//   FORCES   store F (and thermo sums)
+//   START    v += dt/2 a; drift
+//   NVE      v += dt/2 a (full step: KE); v += dt/2 a; drift
+//   NVE_LAST v += dt/2 a (full step: KE)
+//   KICK     as NVE_LAST, the thermostat kernel follows
+template <int LPA, int MODE, bool VIR>
+__global__ __launch_bounds__(kBlock) void k_forces(Dev d, Phys p, int par, double* ring_row) {
+  constexpr int APB = kBlock / LPA;
+  const int bid = xcd_remap(blockIdx.x, gridDim.x);
+  const int g = threadIdx.x / LPA, lane = threadIdx.x % LPA;
+  const int i = bid * APB + g;
+  const int rep = d.tile_rep[(bid * APB) >> 6];
+  const RepInfo& R = d.reps[rep];
+  const float sc0 = R.scale[0], sc1 = R.scale[1], sc2 = R.scale[2];
+  const bool real = i < R.iend;
+  const uint4 ui = d.u[par][i];
+  const float c0 = p.c0, c02 = p.c0 * p.c0;
+
+  float Tm0 = 0.f, Tm1 = 0.f, Tm2 = 0.f, Tm3 = 0.f, Tm4 = 0.f, Tm5 = 0.f, Vm0 = 0.f, Vm1 = 0.f, Vm2 = 0.f,
+        Sm = 0.f, E2i = 0.f, E3i = 0.f;
+  int nn = 0;
+  if (real) {
+    const float4* m = d.mom + 3 * (size_t)i;
+    const float4 a = m[0], b = m[1], c = m[2];
+    Tm0 = a.x; Tm1 = a.y; Tm2 = a.z; Tm3 = a.w; Tm4 = b.x; Tm5 = b.y;
+    Vm0 = b.z; Vm1 = b.w; Vm2 = c.x; Sm = c.y; E2i = c.z; E3i = c.w;
+    nn = d.nn[i];
+  }
+  const int* row = d.nl + (size_t)i * d.cap;
+  const uint4* up = d.u[par];
+  float fx = 0.f, fy = 0.f, fz = 0.f;
+  float w0 = 0.f, w1 = 0.f, w2 = 0.f, w3 = 0.f, w4 = 0.f, w5 = 0.f;
+  for (int s = lane; s < nn; s += LPA) {
+    const int j = row[s];
+    const float3 dd = disp(ui, up[j], sc0, sc1, sc2);
+    const float r2 = dd.x * dd.x + dd.y * dd.y + dd.z * dd.z;
+    if (r2 < p.rc2) {
+      if (r2 < 0.25f) atomicOr(&d.flags[F_OVERLAP], 1);
+      const float ir = rsq(r2);
+      const float r = r2 * ir;
+      const float ux = dd.x * ir, uy = dd.y * ir, uz = dd.z * ir;
+      const float idr = rcp(r - p.rc);
+      const float idr2 = idr * idr;
+      const float e1 = ex2(p.sig_l2e * idr);
+      const float eg = ex2(p.gsig_l2e * idr);
+      const float sr = p.sig * ir, s4 = (sr * sr) * (sr * sr);
+      const float poly = p.B * s4 - 1.f;
+      const float dphi = p.Aeps * e1 * (-4.f * p.B * s4 * ir - poly * p.sig * idr2);
+      const float gg = -p.gsig * idr2;
+      const float4* mj = d.mom + 3 * (size_t)j;
+      const float4 na = mj[0], nb = mj[1], nc = mj[2];
+      const float Ts0 = Tm0 + na.x, Ts1 = Tm1 + na.y, Ts2 = Tm2 + na.z, Ts3 = Tm3 + na.w;
+      const float Ts4 = Tm4 + nb.x, Ts5 = Tm5 + nb.y;
+      const float Dv0 = Vm0 - nb.z, Dv1 = Vm1 - nb.w, Dv2 = Vm2 - nc.x, Ss = Sm + nc.y;
+      const float y0x = Ts0 * ux + Ts3 * uy + Ts4 * uz;
+      const float y0y = Ts3 * ux + Ts1 * uy + Ts5 * uz;
+      const float y0z = Ts4 * ux + Ts5 * uy + Ts2 * uz;
+      const float uTu = ux * y0x + uy * y0y + uz * y0z;
+      const float uDv = ux * Dv0 + uy * Dv1 + uz * Dv2;
+      const float q = uTu - 2.f * c0 * uDv + c02 * Ss - 2.f * p.qc * eg;
+      const float uy_ = uTu - c0 * uDv;
+      const float px = (y0x - c0 * Dv0) - uy_ * ux;
+      const float py = (y0y - c0 * Dv1) - uy_ * uy;
+      const float pz = (y0z - c0 * Dv2) - uy_ * uz;
+      const float le = p.lameps * eg;
+      const float a1 = dphi + le * gg * q;
+      const float a2 = 2.f * le * ir;
+      fx += a1 * ux + a2 * px;
+      fy += a1 * uy + a2 * py;
+      fz += a1 * uz + a2 * pz;
+      if (VIR) {
+        const float ymx = Tm0 * ux + Tm3 * uy + Tm4 * uz - c0 * Vm0;
+        const float ymy = Tm3 * ux + Tm1 * uy + Tm5 * uz - c0 * Vm1;
+        const float ymz = Tm4 * ux + Tm5 * uy + Tm2 * uz - c0 * Vm2;
+        const float uym = ux * ymx + uy * ymy + uz * ymz;                 // u.(T u) - c0 u.V
+        const float uVm = ux * Vm0 + uy * Vm1 + uz * Vm2;
+        const float qown = uym - c0 * uVm + c02 * Sm - p.qc * eg;         // u.T.u - 2 c0 u.V + ...
+        const float pox = ymx - uym * ux, poy = ymy - uym * uy, poz = ymz - uym * uz;
+        const float cA = -(0.5f * r * dphi + le * r * gg * qown);
+        const float cB = -2.f * le;
+        w0 += cA * ux * ux + cB * ux * pox;
+        w1 += cA * uy * uy + cB * uy * poy;
+        w2 += cA * uz * uz + cB * uz * poz;
+        w3 += cA * ux * uy + cB * ux * poy;
+        w4 += cA * ux * uz + cB * ux * poz;
+        w5 += cA * uy * uz + cB * uy * poz;
+      }
+    }
+  }
+  fx = group_sum<LPA>(fx); fy = group_sum<LPA>(fy); fz = group_sum<LPA>(fz);
+  if (VIR) {
+    w0 = group_sum<LPA>(w0); w1 = group_sum<LPA>(w1); w2 = group_sum<LPA>(w2);
+    w3 = group_sum<LPA>(w3); w4 = group_sum<LPA>(w4); w5 = group_sum<LPA>(w5);
+  }
+
+  constexpr bool kReduce = VIR || MODE == MODE_KICK;
+  double q[kNQ];
+#pragma unroll
+  for (int k = 0; k < kNQ; ++k) q[k] = 0.0;
+  float dist = 0.f;
+  if (real && lane == 0) {
+    const float4 F = make_float4(fx, fy, fz, 0.f);
+    d.f[i] = F;
+    if (VIR) {
+      q[0] = E2i; q[1] = E3i;
+      q[3] = w0; q[4] = w1; q[5] = w2; q[6] = w3; q[7] = w4; q[8] = w5;
+    }
+    if (MODE != MODE_FORCES) {
+      float4 v = d.v[i];
+      v.x += p.hdt_cm * F.x; v.y += p.hdt_cm * F.y; v.z += p.hdt_cm * F.z;
+      if (MODE != MODE_START) {
+        const float vx2 = v.x * v.x, vy2 = v.y * v.y, vz2 = v.z * v.z;
+        q[2] = (double)(p.half_m_acc * (vx2 + vy2 + vz2));
+        q[9] = (double)(p.m_acc * vx2); q[10] = (double)(p.m_acc * vy2); q[11] = (double)(p.m_acc * vz2);
+      }
+      if (MODE == MODE_NVE) {
+        v.x += p.hdt_cm * F.x; v.y += p.hdt_cm * F.y; v.z += p.hdt_cm * F.z;
+      }
+      if (MODE == MODE_START || MODE == MODE_NVE) dist = drift_bin(d, p, R, i, ui, v, par ^ 1);
+      d.v[i] = v;
+    }
+  }
+  if (MODE == MODE_START || MODE == MODE_NVE) {
+    dist = wave_max(dist);
+    if ((threadIdx.x & 63) == 0 && dist > 0.f) atomicMax(&d.dmax[par ^ 1], __float_as_uint(dist));
+  }
+  if (kReduce) reduce_thermo<APB>(d, bid, rep, R, q, lane == 0, g, ring_row);
+}
+
+// Thermostat on the full-step velocities, then (unless last) the next
+// half-kick and drift.
+__global__ __launch_bounds__(kBlock) void k_thermostat(Dev d, Phys p, int par, int last) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  float dist = 0.f;
+  if (i < d.npad) {
+    const int rep = d.tile_rep[i >> 6];
+    const RepInfo& R = d.reps[rep];
+    if (i < R.iend) {
+      const double T = 2.0 * d.thermo_cur[rep * kNQ + 2] / R.ndof_kb;
+      const double T0 = d.T0[rep];
+      double s = 1.0;
+      if (T > 0.0) {
+        s = p.thermostat == 1 ? sqrt(T0 / T) : sqrt(fmax(0.0, 1.0 + p.dt_d / p.tau_d * (T0 / T - 1.0)));
+      }
+      float4 v = d.v[i];
+      const float sf = (float)s;
+      v.x *= sf; v.y *= sf; v.z *= sf;
+      if (!last) {
+        const float4 F = d.f[i];
+        v.x += p.hdt_cm * F.x; v.y += p.hdt_cm * F.y; v.z += p.hdt_cm * F.z;
+        dist = drift_bin(d, p, R, i, d.u[par][i], v, par ^ 1);
+      }
+      d.v[i] = v;
+    }
+  }
+  if (!last) {
+    dist = wave_max(dist);
+    if ((threadIdx.x & 63) == 0 && dist > 0.f) atomicMax(&d.dmax[par ^ 1], __float_as_uint(dist));
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_scatter_out(Dev d, int par, float4* __restrict__ x,
+                                                       float4* __restrict__ v, float4* __restrict__ f) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= d.npad) return;
+  const int k = d.ids[i];
+  if (k < 0) return;
+  const RepInfo& R = d.reps[d.tile_rep[i >> 6]];
+  if (x) {
+    const uint4 u = d.u[par][i];
+    x[k] = make_float4((float)((double)u.x * (R.L[0] / kTwo32)), (float)((double)u.y * (R.L[1] / kTwo32)),
+                       (float)((double)u.z * (R.L[2] / kTwo32)), 0.f);
+  }
+  if (v) {
+    float4 a = d.v[i];
+    a.w = 0.f;
+    v[k] = a;
+  }
+  if (f) {
+    float4 a = d.f[i];
+    a.w = 0.f;
+    f[k] = a;
+  }
+}
+
+__global__ void k_copy_thermo(const double* __restrict__ cur, int R, double* energy, double* virial) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= R) return;
+  if (energy) {
+    energy[2 * r] = cur[r * kNQ + 0];
+    energy[2 * r + 1] = cur[r * kNQ + 1];
+  }
+  if (virial)
+    for (int k = 0; k < 6; ++k) virial[6 * r + k] = cur[r * kNQ + 3 + k];
+}
+
+__global__ void k_fill_i32(int* p, int value, long long n) {
+  const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) p[k] = value;
+}
+__global__ void k_fill_f32(float* p, float value, long long n) {
+  const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) p[k] = value;
+}
+
+inline unsigned nblk(long long n, int b) { return (unsigned)((n + b - 1) / b); }
+
+template <int LPA>
+hipError_t moments_lpa(const Dev& d, const Phys& p, int par, int force_rebuild, int energy, hipStream_t s) {
+  constexpr int APB = kBlock / LPA;
+  const size_t lds = sizeof(int) * (2 * (size_t)APB * d.cap + APB);
+  const unsigned grid = (unsigned)(d.npad / APB);
+  if (energy) hipLaunchKernelGGL((k_moments<LPA, true>), dim3(grid), dim3(kBlock), lds, s, d, p, par, force_rebuild);
+  else hipLaunchKernelGGL((k_moments<LPA, false>), dim3(grid), dim3(kBlock), lds, s, d, p, par, force_rebuild);
+  return hipGetLastError();
+}
+
+template <int LPA, int MODE>
+hipError_t forces_mode(const Dev& d, const Phys& p, int vir, int par, double* ring_row, hipStream_t s) {
+  constexpr int APB = kBlock / LPA;
+  const unsigned grid = (unsigned)(d.npad / APB);
+  if (vir) hipLaunchKernelGGL((k_forces<LPA, MODE, true>), dim3(grid), dim3(kBlock), 0, s, d, p, par, ring_row);
+  else hipLaunchKernelGGL((k_forces<LPA, MODE, false>), dim3(grid), dim3(kBlock), 0, s, d, p, par, ring_row);
+  return hipGetLastError();
+}
+
+template <int LPA>
+hipError_t forces_lpa(const Dev& d, const Phys& p, int mode, int vir, int par, double* ring_row, hipStream_t s) {
+  switch (mode) {
+    case MODE_FORCES: return forces_mode<LPA, MODE_FORCES>(d, p, 1, par, ring_row, s);
+    case MODE_START: return forces_mode<LPA, MODE_START>(d, p, 0, par, ring_row, s);
+    case MODE_NVE: return forces_mode<LPA, MODE_NVE>(d, p, vir, par, ring_row, s);
+    case MODE_NVE_LAST: return forces_mode<LPA, MODE_NVE_LAST>(d, p, vir, par, ring_row, s);
+    case MODE_KICK: return forces_mode<LPA, MODE_KICK>(d, p, vir, par, ring_row, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+}  // namespace
+
+hipError_t launch_sort(const Dev& d, const float4* x_user, const float4* v_user, long long n_user,
+                       const long long* uoff, int R, const int* cell_rank, uint4* uq, int* key, int* cnt,
+                       int* start, int* cursor, int* order, hipStream_t s) {
+  hipError_t e;
+  if ((e = launch_fill_i32(cnt, 0, d.ctot, s)) != hipSuccess) return e;
+  if ((e = launch_fill_i32(cursor, 0, d.ctot, s)) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_sort_count, dim3(nblk(n_user, kBlock)), dim3(kBlock), 0, s, x_user, n_user, uoff, R,
+                     d.reps, cell_rank, uq, key, cnt);
+  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, cnt, start, d.ctot);
+  hipLaunchKernelGGL(k_sort_scatter, dim3(nblk(n_user, kBlock)), dim3(kBlock), 0, s, n_user, key, start, cursor,
+                     order);
+  hipLaunchKernelGGL(k_sort_cells, dim3(nblk(d.ctot, kBlock)), dim3(kBlock), 0, s, d.ctot, cnt, start, order);
+  hipLaunchKernelGGL(k_gather_sorted, dim3(nblk(d.npad, kBlock)), dim3(kBlock), 0, s, d, uq, v_user, order);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather_ids(const Dev& d, const float4* x_user, int par, hipStream_t s) {
+  hipLaunchKernelGGL(k_gather_ids, dim3(nblk(d.npad, kBlock)), dim3(kBlock), 0, s, d, x_user, par);
+  return hipGetLastError();
+}
+
+hipError_t launch_bin(const Dev& d, int par, int check_disp, hipStream_t s) {
+  hipLaunchKernelGGL(k_bin, dim3(nblk(d.npad, kBlock)), dim3(kBlock), 0, s, d, par, check_disp);
+  return hipGetLastError();
+}
+
+hipError_t launch_moments(const Dev& d, const Phys& p, int lpa, int par, int force_rebuild, int energy,
+                          hipStream_t s) {
+  switch (lpa) {
+    case 4: return moments_lpa<4>(d, p, par, force_rebuild, energy, s);
+    case 8: return moments_lpa<8>(d, p, par, force_rebuild, energy, s);
+    case 16: return moments_lpa<16>(d, p, par, force_rebuild, energy, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_forces(const Dev& d, const Phys& p, int lpa, int mode, int vir, int par, double* ring_row,
+                         hipStream_t s) {
+  switch (lpa) {
+    case 4: return forces_lpa<4>(d, p, mode, vir, par, ring_row, s);
+    case 8: return forces_lpa<8>(d, p, mode, vir, par, ring_row, s);
+    case 16: return forces_lpa<16>(d, p, mode, vir, par, ring_row, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_thermostat(const Dev& d, const Phys& p, int par, int last, hipStream_t s) {
+  hipLaunchKernelGGL(k_thermostat, dim3(nblk(d.npad, kBlock)), dim3(kBlock), 0, s, d, p, par, last);
+  return hipGetLastError();
+}
+
+hipError_t launch_scatter_out(const Dev& d, int par, float4* x_user, float4* v_user, float4* f_user,
+                              hipStream_t s) {
+  hipLaunchKernelGGL(k_scatter_out, dim3(nblk(d.npad, kBlock)), dim3(kBlock), 0, s, d, par, x_user, v_user,
+                     f_user);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy_thermo(const Dev& d, double* energy, double* virial, hipStream_t s) {
+  hipLaunchKernelGGL(k_copy_thermo, dim3(nblk(d.R, 64)), dim3(64), 0, s, d.thermo_cur, d.R, energy, virial);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_i32(int* p, int value, long long n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_i32, dim3(nblk(n, kBlock)), dim3(kBlock), 0, s, p, value, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_f32(float* p, float value, long long n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_f32, dim3(nblk(n, kBlock)), dim3(kBlock), 0, s, p, value, n);
+  return hipGetLastError();
+}
+
+}  // namespace swk

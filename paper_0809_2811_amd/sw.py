@@ -1,0 +1,312 @@
+"""ctypes binding of libsw (include/sw.h).
+
+Argument marshalling only: every function here checks tensor shapes, dtypes
+and devices, then calls the C entry point of the same name with raw device
+pointers and the current HIP stream.  All computation happens in the HIP
+kernels.  There is no CPU fallback: if libsw.so is missing or no GPU is
+present, the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import pathlib
+from typing import Optional, Sequence
+
+import numpy as np
+
+_LIB_PATH = pathlib.Path(__file__).resolve().parent / "libsw.so"
+_lib = None
+
+SW_OK = 0
+SW_EINVAL = -1
+SW_EBOX_TOO_SMALL = -2
+SW_ENBR_OVERFLOW = -3
+SW_ECELL_OVERFLOW = -4
+SW_EOVERLAP = -5
+SW_EHIP = -6
+SW_ENOMEM = -7
+SW_EUNSUPPORTED = -8
+SW_ESTATE = -9
+
+SW_NVE, SW_RESCALE, SW_BERENDSEN = 0, 1, 2
+SW_THERMO_WIDTH = 12
+SW_Q_NATOMS, SW_Q_NREPLICAS, SW_Q_NBR_CAPACITY, SW_Q_REBUILDS = 0, 1, 2, 3
+SW_Q_CELL_CAPACITY, SW_Q_DEVICE_BYTES, SW_Q_STEPS = 5, 6, 7
+
+# symbols declared in include/sw.h
+EXPORTS = ("sw_params_mw", "sw_create", "sw_destroy", "sw_build_neighbors", "sw_get_neighbors",
+           "sw_forces", "sw_step", "sw_grad", "sw_adjoint", "sw_set_tuning", "sw_get_tuning",
+           "sw_query", "sw_status_string", "sw_last_hip_error")
+
+
+class sw_params(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_double) for n in
+                ("lambda_", "epsilon", "sigma", "A", "B", "p", "q", "gamma", "a", "cos_theta0")]
+
+
+class sw_tuning(ctypes.Structure):
+    _fields_ = [("lanes_per_atom", ctypes.c_int), ("graph_steps", ctypes.c_int),
+                ("persistent", ctypes.c_int), ("rebuild_every", ctypes.c_int)]
+
+
+class SWError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        self.code = code
+        super().__init__(f"{where}: {status_string(code)} ({code})")
+
+
+def library_path() -> pathlib.Path:
+    return _LIB_PATH
+
+
+def lib():
+    """Load libsw.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not _LIB_PATH.exists():
+            raise RuntimeError(f"{_LIB_PATH} is missing: build it with paper_0809_2811_amd.build.build()")
+        L = ctypes.CDLL(str(_LIB_PATH))
+        vp, ip, dp, fp = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_void_p
+        P = ctypes.POINTER
+        L.sw_params_mw.argtypes = [P(sw_params)]; L.sw_params_mw.restype = None
+        L.sw_create.argtypes = [P(vp), ip, P(ctypes.c_longlong), P(ctypes.c_double), dp, dp, ip]
+        L.sw_destroy.argtypes = [vp]; L.sw_destroy.restype = None
+        L.sw_build_neighbors.argtypes = [vp, fp, vp]
+        L.sw_get_neighbors.argtypes = [vp, P(ctypes.c_int), P(ctypes.c_int), ip]
+        L.sw_forces.argtypes = [vp, fp, P(sw_params), fp, vp, vp, vp]
+        L.sw_step.argtypes = [vp, fp, fp, fp, P(sw_params), dp, dp, ip, ip, P(ctypes.c_double), dp, vp, ip, vp]
+        L.sw_grad.argtypes = [vp, fp, fp, P(sw_params), fp, vp, vp, vp]
+        L.sw_adjoint.argtypes = [vp, fp, fp, P(sw_params), dp, dp, ip, ip, dp, dp, fp, fp, vp, fp, fp, vp,
+                                 fp, fp, vp]
+        L.sw_set_tuning.argtypes = [vp, P(sw_tuning)]
+        L.sw_get_tuning.argtypes = [vp, P(sw_tuning)]
+        L.sw_query.argtypes = [vp, ip, P(ctypes.c_longlong)]
+        L.sw_status_string.argtypes = [ip]; L.sw_status_string.restype = ctypes.c_char_p
+        L.sw_last_hip_error.argtypes = [vp]
+        _lib = L
+    return _lib
+
+
+def status_string(code: int) -> str:
+    return lib().sw_status_string(int(code)).decode()
+
+
+def _check(code: int, where: str):
+    if code != SW_OK:
+        raise SWError(code, where)
+
+
+def params_mw(**over) -> sw_params:
+    """mW parameter block (Sec. II.A / II.D) from the library, with overrides
+    given as lambda_, epsilon, sigma, A, B, p, q, gamma, a, cos_theta0."""
+    p = sw_params()
+    lib().sw_params_mw(ctypes.byref(p))
+    for k, val in over.items():
+        setattr(p, k, float(val))
+    return p
+
+
+def params_from_array(arr) -> sw_params:
+    """From the 10-vector (lambda, epsilon, sigma, A, B, p, q, gamma, a, cos_theta0)."""
+    a = [float(x) for x in arr]
+    return sw_params(*a)
+
+
+# ------------------------------------------------------------------ tensors
+def _torch():
+    import torch
+    return torch
+
+
+def _stream():
+    torch = _torch()
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _atoms(t, n, name, writable=False):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or t.dtype != torch.float32 or not t.is_cuda:
+        raise TypeError(f"{name}: expected a float32 CUDA tensor")
+    if tuple(t.shape) != (n, 4) or not t.is_contiguous():
+        raise ValueError(f"{name}: expected a contiguous [{n}, 4] tensor, got {tuple(t.shape)}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _doubles(t, shape, name):
+    torch = _torch()
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or t.dtype != torch.float64 or not t.is_cuda:
+        raise TypeError(f"{name}: expected a float64 CUDA tensor")
+    if tuple(t.shape) != tuple(shape) or not t.is_contiguous():
+        raise ValueError(f"{name}: expected a contiguous {tuple(shape)} tensor, got {tuple(t.shape)}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+# ------------------------------------------------------------------ entry points
+def sw_create(offsets: Sequence[int], boxes, cutoff: float, skin: float, nbr_capacity: int = 48) -> int:
+    off = np.ascontiguousarray(offsets, dtype=np.int64)
+    box = np.ascontiguousarray(boxes, dtype=np.float64).reshape(-1)
+    R = len(off) - 1
+    if R < 1 or box.size != 3 * R:
+        raise ValueError("offsets must have R+1 entries and boxes R*3")
+    h = ctypes.c_void_p()
+    _check(lib().sw_create(ctypes.byref(h), R, off.ctypes.data_as(ctypes.POINTER(ctypes.c_longlong)),
+                           box.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), float(cutoff), float(skin),
+                           int(nbr_capacity)), "sw_create")
+    return h.value
+
+
+def sw_destroy(ctx: int):
+    lib().sw_destroy(ctypes.c_void_p(ctx))
+
+
+def sw_build_neighbors(ctx: int, x, n: int):
+    _check(lib().sw_build_neighbors(ctypes.c_void_p(ctx), _atoms(x, n, "x"), _stream()), "sw_build_neighbors")
+
+
+def sw_get_neighbors(ctx: int, n: int, max_per_row: int):
+    counts = np.zeros(n, dtype=np.int32)
+    rows = np.zeros((n, max_per_row), dtype=np.int32)
+    ip = ctypes.POINTER(ctypes.c_int)
+    _check(lib().sw_get_neighbors(ctypes.c_void_p(ctx), counts.ctypes.data_as(ip), rows.ctypes.data_as(ip),
+                                  int(max_per_row)), "sw_get_neighbors")
+    return counts, rows
+
+
+def sw_forces(ctx: int, x, params: sw_params, f, energy=None, virial=None, n: Optional[int] = None,
+              R: Optional[int] = None):
+    n = x.shape[0] if n is None else n
+    R = (energy.shape[0] if energy is not None else virial.shape[0] if virial is not None else 1) if R is None else R
+    _check(lib().sw_forces(ctypes.c_void_p(ctx), _atoms(x, n, "x"), ctypes.byref(params), _atoms(f, n, "f"),
+                           _doubles(energy, (R, 2), "energy"), _doubles(virial, (R, 6), "virial"), _stream()),
+           "sw_forces")
+
+
+def sw_step(ctx: int, x, v, f, params: sw_params, mass: float, dt: float, nsteps: int, thermostat: int = SW_NVE,
+            T0=None, tau_fs: float = 1000.0, thermo=None, thermo_every: int = 1, R: int = 1):
+    n = x.shape[0]
+    t0 = None
+    if T0 is not None:
+        t0 = np.ascontiguousarray(np.broadcast_to(np.asarray(T0, dtype=np.float64), (R,)))
+    rows = (nsteps // thermo_every) if thermo is not None else 0
+    _check(lib().sw_step(ctypes.c_void_p(ctx), _atoms(x, n, "x"), _atoms(v, n, "v"), _atoms(f, n, "f"),
+                         ctypes.byref(params), float(mass), float(dt), int(nsteps), int(thermostat),
+                         None if t0 is None else t0.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                         float(tau_fs), _doubles(thermo, (rows, R, SW_THERMO_WIDTH), "thermo"), int(thermo_every),
+                         _stream()), "sw_step")
+
+
+def sw_grad(ctx: int, x, w, params: sw_params, hvp, wdF=None, dU=None, R: int = 1):
+    n = x.shape[0]
+    _check(lib().sw_grad(ctypes.c_void_p(ctx), _atoms(x, n, "x"), _atoms(w, n, "w"), ctypes.byref(params),
+                         _atoms(hvp, n, "hvp"), _doubles(wdF, (R, 3), "wdF"), _doubles(dU, (R, 3), "dU"),
+                         _stream()), "sw_grad")
+
+
+def sw_adjoint(ctx: int, x0, v0, params: sw_params, mass: float, dt: float, nsteps: int, ckpt_every: int,
+               aU: float, a3: float, xbar_S, vbar_S, loss, xbar0, vbar0, thbar, xS=None, vS=None, R: int = 1):
+    n = x0.shape[0]
+    opt = lambda t, name: None if t is None else _atoms(t, n, name)  # noqa: E731
+    _check(lib().sw_adjoint(ctypes.c_void_p(ctx), _atoms(x0, n, "x0"), _atoms(v0, n, "v0"), ctypes.byref(params),
+                            float(mass), float(dt), int(nsteps), int(ckpt_every), float(aU), float(a3),
+                            opt(xbar_S, "xbar_S"), opt(vbar_S, "vbar_S"), _doubles(loss, (R,), "loss"),
+                            _atoms(xbar0, n, "xbar0"), _atoms(vbar0, n, "vbar0"), _doubles(thbar, (R, 3), "thbar"),
+                            opt(xS, "xS"), opt(vS, "vS"), _stream()), "sw_adjoint")
+
+
+def sw_set_tuning(ctx: int, lanes_per_atom=8, graph_steps=0, persistent=0, rebuild_every=0):
+    t = sw_tuning(int(lanes_per_atom), int(graph_steps), int(persistent), int(rebuild_every))
+    _check(lib().sw_set_tuning(ctypes.c_void_p(ctx), ctypes.byref(t)), "sw_set_tuning")
+
+
+def sw_get_tuning(ctx: int) -> dict:
+    t = sw_tuning()
+    _check(lib().sw_get_tuning(ctypes.c_void_p(ctx), ctypes.byref(t)), "sw_get_tuning")
+    return dict(lanes_per_atom=t.lanes_per_atom, graph_steps=t.graph_steps, persistent=t.persistent,
+                rebuild_every=t.rebuild_every)
+
+
+def sw_query(ctx: int, what: int) -> int:
+    out = ctypes.c_longlong()
+    _check(lib().sw_query(ctypes.c_void_p(ctx), int(what), ctypes.byref(out)), "sw_query")
+    return out.value
+
+
+# ------------------------------------------------------------------ convenience
+class Context:
+    """Owns one sw_ctx.  offsets: int[R+1]; boxes: [R,3] (A)."""
+
+    def __init__(self, offsets, boxes, cutoff: Optional[float] = None, skin: float = 1.0,
+                 nbr_capacity: int = 48, tuning: Optional[dict] = None):
+        if cutoff is None:
+            p = params_mw()
+            cutoff = p.a * p.sigma
+        self.offsets = np.asarray(offsets, dtype=np.int64)
+        self.boxes = np.asarray(boxes, dtype=np.float64).reshape(-1, 3)
+        self.R = len(self.offsets) - 1
+        self.n = int(self.offsets[-1])
+        self.cutoff, self.skin = float(cutoff), float(skin)
+        self.handle = sw_create(self.offsets, self.boxes, cutoff, skin, nbr_capacity)
+        if tuning:
+            self.set_tuning(**tuning)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            sw_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_tuning(self, **kw):
+        cur = sw_get_tuning(self.handle)
+        cur.update(kw)
+        sw_set_tuning(self.handle, **cur)
+
+    def tuning(self) -> dict:
+        return sw_get_tuning(self.handle)
+
+    def build_neighbors(self, x):
+        sw_build_neighbors(self.handle, x, self.n)
+
+    def neighbors(self, max_per_row: int = 256):
+        return sw_get_neighbors(self.handle, self.n, max_per_row)
+
+    def forces(self, x, params: Optional[sw_params] = None):
+        torch = _torch()
+        params = params_mw() if params is None else params
+        f = torch.empty_like(x)
+        e = torch.empty((self.R, 2), dtype=torch.float64, device=x.device)
+        w = torch.empty((self.R, 6), dtype=torch.float64, device=x.device)
+        sw_forces(self.handle, x, params, f, e, w, n=self.n, R=self.R)
+        return f, e, w
+
+    def step(self, x, v, nsteps: int, dt: float = 10.0, mass: float = 18.015, params: Optional[sw_params] = None,
+             thermostat: int = SW_NVE, T0=None, tau_fs: float = 1000.0, thermo_every: int = 0, f=None):
+        """Advance (x, v) in place; returns (f, thermo or None)."""
+        torch = _torch()
+        params = params_mw() if params is None else params
+        f = torch.empty_like(x) if f is None else f
+        thermo = None
+        if thermo_every > 0 and nsteps >= thermo_every:
+            thermo = torch.empty((nsteps // thermo_every, self.R, SW_THERMO_WIDTH), dtype=torch.float64,
+                                 device=x.device)
+        sw_step(self.handle, x, v, f, params, mass, dt, nsteps, thermostat, T0, tau_fs, thermo,
+                max(thermo_every, 1), R=self.R)
+        return f, thermo
+
+    def grad(self, x, w, params: Optional[sw_params] = None):
+        torch = _torch()
+        params = params_mw() if params is None else params
+        hvp = torch.empty_like(x)
+        wdF = torch.empty((self.R, 3), dtype=torch.float64, device=x.device)
+        dU = torch.empty((self.R, 3), dtype=torch.float64, device=x.device)
+        sw_grad(self.handle, x, w, params, hvp, wdF, dU, R=self.R)
+        return hvp, wdF, dU
+
+    def query(self, what: int) -> int:
+        return sw_query(self.handle, what)

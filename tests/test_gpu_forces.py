@@ -1,0 +1,179 @@
+"""GPU parity of sw_forces / sw_build_neighbors against the FP64 oracle.
+
+Both sides see the same FP32-rounded positions (the oracle upcasts them).
+Bars (stated for the force path): max_i |dF_i| / RMS |F| <= 1e-5, energies
+|dE| / |E| <= 1e-5, virial components within 1e-5 of the largest |W_ab|.
+Neighbour rows are integer data and must match exactly as sets.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_0809_2811_amd import synth
+from tests.gpu_util import RC, f32, force_error, from_dev, liquid, oracle_virial6, to_dev
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+
+
+def gpu_forces(x, L, lpa=8, skin=0.5, cap=48, offsets=None, boxes=None, P=None):
+    from paper_0809_2811_amd import sw
+    offsets = [0, len(x)] if offsets is None else offsets
+    boxes = [L] if boxes is None else boxes
+    ctx = sw.Context(offsets, boxes, cutoff=RC, skin=skin, nbr_capacity=cap, tuning=dict(lanes_per_atom=lpa))
+    f, e, w = ctx.forces(to_dev(x), P)
+    out = dict(F=from_dev(f), E=e.cpu().numpy(), W=w.cpu().numpy(), ctx=ctx)
+    return out
+
+
+def check(x, L, g, tol=TOL):
+    o = oracle.forces(x, L)
+    err = force_error(g["F"], o["F"])
+    assert err <= tol, f"force error {err:.3e}"
+    etot = o["E2"] + o["E3"]
+    assert abs(g["E"][0, 0] - o["E2"]) <= tol * abs(etot)
+    assert abs(g["E"][0, 1] - o["E3"]) <= tol * abs(etot)
+    W = oracle_virial6(o)
+    assert np.abs(g["W"][0] - W).max() <= tol * np.abs(W).max()
+    return err
+
+
+@pytest.mark.parametrize("lpa", [4, 8, 16])
+def test_ice_workload_forces(lpa):
+    d = synth.config(0)
+    x = f32(d["x"])
+    check(x, d["box"], gpu_forces(x, d["box"], lpa=lpa))
+
+
+@pytest.mark.parametrize("lpa", [4, 8, 16])
+def test_liquid_forces_512(lpa):
+    x, _, L = liquid(1, sigma=0.0)
+    x = f32(x)
+    check(x, L, gpu_forces(x, L, lpa=lpa))
+
+
+def test_liquid_forces_4096():
+    x, _, L = liquid(2)
+    x = f32(x)
+    check(x, L, gpu_forces(x, L, lpa=8, skin=1.0))
+
+
+def test_liquid_forces_full_large_box():
+    """262144 atoms (the large-box workload, 198.7 A edge) in full."""
+    x, _, L = liquid(8)
+    x = f32(x)
+    assert len(x) == 262144 and abs(L[0] - 198.674) < 0.01
+    check(x, L, gpu_forces(x, L, lpa=8, skin=0.5))
+
+
+def test_perfect_lattice_closed_form():
+    x, L = synth.diamond_lattice(4, 4, 4, 6.36)
+    x = f32(x)
+    g = gpu_forces(x, L)
+    n = len(x)
+    e_atom = (g["E"][0, 0] + g["E"][0, 1]) / n
+    assert abs(e_atom - (-12.277162226681)) < 1e-5 * 12.28
+    assert abs(g["E"][0, 1]) / n < 1e-5
+    assert np.abs(g["F"]).max() < 1e-3
+
+
+def test_ragged_and_tiny_boxes():
+    """Replica sizes that are not multiples of the 64-atom tile, edges of 3 cells."""
+    d = synth.lattice_at_density((3, 3, 4), 1.0, sigma=0.3, seed=3)    # 288 atoms
+    x = f32(d["x"])
+    check(x, d["box"], gpu_forces(x, d["box"], skin=0.0))
+    d = synth.lattice_at_density(3, 0.95, sigma=0.3, seed=4)           # 216 atoms, 3 cells per edge
+    x = f32(d["x"])
+    check(x, d["box"], gpu_forces(x, d["box"], skin=0.3))
+
+
+def test_several_replicas_in_one_context():
+    boxes, xs = [], []
+    for k, (cells, rho) in enumerate([((4, 4, 4), 1.0), ((3, 4, 5), 0.93), ((5, 5, 5), 1.05)]):
+        d = synth.lattice_at_density(cells, rho, sigma=0.3, seed=20 + k)
+        xs.append(f32(d["x"]))
+        boxes.append(d["box"])
+    offsets = np.cumsum([0] + [len(x) for x in xs])
+    g = gpu_forces(np.concatenate(xs), None, offsets=offsets, boxes=boxes)
+    for r, (x, L) in enumerate(zip(xs, boxes)):
+        o = oracle.forces(x, L)
+        Fg = g["F"][offsets[r]:offsets[r + 1]]
+        assert force_error(Fg, o["F"]) <= TOL
+        etot = o["E2"] + o["E3"]
+        assert abs(g["E"][r, 0] - o["E2"]) <= TOL * abs(etot)
+        assert abs(g["E"][r, 1] - o["E3"]) <= TOL * abs(etot)
+        W = oracle_virial6(o)
+        assert np.abs(g["W"][r] - W).max() <= TOL * np.abs(W).max()
+
+
+def test_neighbour_rows_equal_oracle_sets():
+    from paper_0809_2811_amd import sw
+    x, _, L = liquid(1, sigma=0.0)
+    x = f32(x)
+    skin = 0.5
+    ctx = sw.Context([0, len(x)], [L], cutoff=RC, skin=skin, nbr_capacity=48)
+    ctx.build_neighbors(to_dev(x))
+    counts, rows = ctx.neighbors(64)
+    rl = RC + skin
+    ref = oracle.neighbour_lists(x, L, rl)
+    for i in range(len(x)):
+        got = rows[i, :counts[i]]
+        if not np.array_equal(got, ref[i]):
+            # only pairs within 1e-4 A of the row radius may differ
+            diff = np.setxor1d(got, ref[i])
+            d = x[diff] - x[i]
+            d -= L * np.round(d / L)
+            assert np.all(np.abs(np.linalg.norm(d, axis=1) - rl) < 1e-4), (i, diff)
+
+
+def test_rows_reused_then_rebuilt():
+    """sw_forces reuses rows while atoms stay within half the skin, rebuilds beyond."""
+    from paper_0809_2811_amd import sw
+    x, _, L = liquid(1, sigma=0.0)
+    x = f32(x)
+    ctx = sw.Context([0, len(x)], [L], cutoff=RC, skin=0.6, nbr_capacity=48)
+    ctx.forces(to_dev(x))
+    r0 = ctx.query(sw.SW_Q_REBUILDS)
+    rng = np.random.default_rng(0)
+    x1 = f32(synth.wrap(x + rng.normal(0, 0.05, x.shape), L))     # small moves: reuse
+    f, e, w = ctx.forces(to_dev(x1))
+    assert ctx.query(sw.SW_Q_REBUILDS) == r0
+    assert force_error(from_dev(f), oracle.forces(x1, L)["F"]) <= TOL
+    x2 = f32(synth.wrap(x + rng.normal(0, 0.4, x.shape), L))      # large moves: rebuild
+    f, e, w = ctx.forces(to_dev(x2))
+    assert ctx.query(sw.SW_Q_REBUILDS) == r0 + 1
+    assert force_error(from_dev(f), oracle.forces(x2, L)["F"]) <= TOL
+
+
+def test_capacity_growth_keeps_results_exact():
+    from paper_0809_2811_amd import sw
+    x, _, L = liquid(1, sigma=0.0)
+    x = f32(x)
+    ctx = sw.Context([0, len(x)], [L], cutoff=RC, skin=0.5, nbr_capacity=4)
+    f, e, w = ctx.forces(to_dev(x))
+    assert ctx.query(sw.SW_Q_NBR_CAPACITY) > 4
+    assert force_error(from_dev(f), oracle.forces(x, L)["F"]) <= TOL
+
+
+def test_overlap_is_reported():
+    from paper_0809_2811_amd import sw
+    x, _, L = liquid(1, sigma=0.0)
+    x = f32(x).copy()
+    x[1] = x[0] + np.array([0.3, 0.0, 0.0])
+    ctx = sw.Context([0, len(x)], [L], cutoff=RC, skin=0.5)
+    with pytest.raises(sw.SWError) as err:
+        ctx.forces(to_dev(x))
+    assert err.value.code == sw.SW_EOVERLAP
+
+
+def test_parameters_other_than_mw():
+    """Silicon's lambda = 21 (Sec. II.D) and a scaled sigma, against the oracle."""
+    from paper_0809_2811_amd import sw
+    x, _, L = liquid(1, sigma=0.0)
+    x = f32(x)
+    for over in (dict(lam=21.0), dict(sig=2.30), dict(eps=5.0, lam=26.2)):
+        P = oracle.params(**over)
+        g = gpu_forces(x, L, P=sw.params_from_array(P))
+        o = oracle.forces(x, L, P)
+        assert force_error(g["F"], o["F"]) <= TOL

@@ -1,0 +1,135 @@
+"""GPU parity of sw_step (velocity Verlet, thermostats) against the oracle.
+
+Trajectories are chaotic, so trajectory parity is short-horizon (10 steps)
+from identical FP32-rounded states; longer runs are checked through NVE
+drift (the paper's 1/10000 criterion, read as a windowed drift) and through
+exact properties (determinism, replica independence, thermostat targets).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_0809_2811_amd import synth
+from tests.gpu_util import RC, f32, force_error, from_dev, liquid, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def make_ctx(x, L, skin=0.5, lpa=8, offsets=None, boxes=None, **tune):
+    from paper_0809_2811_amd import sw
+    offsets = [0, len(x)] if offsets is None else offsets
+    boxes = [L] if boxes is None else boxes
+    t = dict(lanes_per_atom=lpa)
+    t.update(tune)
+    return sw.Context(offsets, boxes, cutoff=RC, skin=skin, nbr_capacity=48, tuning=t)
+
+
+def run_gpu(x, v, L, nsteps, thermo_every=1, **kw):
+    from paper_0809_2811_amd import sw
+    skin = kw.pop("skin", 0.5)
+    lpa = kw.pop("lpa", 8)
+    ctx = make_ctx(x, L, skin=skin, lpa=lpa)
+    xd, vd = to_dev(x), to_dev(v)
+    f, th = ctx.step(xd, vd, nsteps, thermo_every=thermo_every, **kw)
+    return from_dev(xd), from_dev(vd), from_dev(f), (None if th is None else th.cpu().numpy()[:, 0, :]), ctx
+
+
+def min_image(d, L):
+    return d - L * np.round(d / L)
+
+
+@pytest.mark.parametrize("which", ["ice", "liquid"])
+def test_ten_steps_match_oracle(which):
+    if which == "ice":
+        d = synth.config(0)
+        x, v, L = d["x"], d["v"], d["box"]
+    else:
+        x, v, L = liquid(1, sigma=0.0)
+    x, v = f32(x), f32(v)
+    xg, vg, fg, thg, _ = run_gpu(x, v, L, 10)
+    xo, vo, fo, tho = oracle.vv(x, v, L, 10, dt=10.0)
+    assert np.abs(min_image(xg - xo, L)).max() < 1e-4
+    assert np.abs(vg - vo).max() < 1e-5 * np.abs(vo).max() * 10
+    assert force_error(fg, fo) < 1e-4
+    etot = np.abs(tho[:, 0] + tho[:, 1]).max()
+    for k in range(12):
+        assert np.abs(thg[:, k] - tho[:, k]).max() <= 2e-5 * max(etot, np.abs(tho[:, k]).max()), k
+
+
+def test_zero_steps_returns_forces():
+    x, v, L = liquid(1, sigma=0.0)
+    x, v = f32(x), f32(v)
+    xg, vg, fg, _, _ = run_gpu(x, v, L, 0, thermo_every=0)
+    assert force_error(fg, oracle.forces(x, L)["F"]) <= 1e-5
+    assert np.array_equal(vg, v)
+    assert np.abs(min_image(xg - x, L)).max() < 1e-5
+
+
+def windowed_drift(e, frac=0.2):
+    w = max(1, int(len(e) * frac))
+    return abs(e[-w:].mean() - e[:w].mean()) / abs(e[0])
+
+
+def test_nve_drift_ice_workload():
+    d = synth.config(0)
+    _, _, _, th, _ = run_gpu(f32(d["x"]), f32(d["v"]), d["box"], 100)
+    e = th[:, 0] + th[:, 1] + th[:, 2]
+    assert windowed_drift(e) < 1e-4
+
+
+def test_nve_drift_liquid_4096():
+    x, v, L = liquid(2)
+    _, _, _, th, ctx = run_gpu(f32(x), f32(v), L, 2000, thermo_every=10, skin=1.0)
+    e = th[:, 0] + th[:, 1] + th[:, 2]
+    assert windowed_drift(e) < 1e-4
+    from paper_0809_2811_amd import sw
+    assert ctx.query(sw.SW_Q_REBUILDS) > 1
+
+
+def test_rescale_thermostat_hits_target():
+    from paper_0809_2811_amd import sw
+    x, v, L = liquid(1, sigma=0.0)
+    xg, vg, _, th, _ = run_gpu(f32(x), f32(v), L, 3, thermostat=sw.SW_RESCALE, T0=400.0)
+    assert abs(oracle.temperature(vg) - 400.0) < 1e-3
+
+
+def test_berendsen_matches_oracle():
+    from paper_0809_2811_amd import sw
+    x, v, L = liquid(1, sigma=0.0)
+    x, v = f32(x), f32(v)
+    xg, vg, _, thg, _ = run_gpu(x, v, L, 5, thermostat=sw.SW_BERENDSEN, T0=320.0, tau_fs=200.0)
+    xo, vo, _, tho = oracle.vv(x, v, L, 5, dt=10.0, thermostat=2, T0=320.0, tau=200.0)
+    assert np.abs(vg - vo).max() < 1e-4 * np.abs(vo).max()
+    assert np.abs(thg[:, 2] - tho[:, 2]).max() < 1e-5 * tho[:, 2].max()
+
+
+def test_step_is_deterministic():
+    x, v, L = liquid(2)
+    a = run_gpu(f32(x), f32(v), L, 50, thermo_every=10)
+    b = run_gpu(f32(x), f32(v), L, 50, thermo_every=10)
+    for k in range(4):
+        assert np.array_equal(a[k], b[k])
+
+
+def test_replicas_evolve_independently():
+    """Each replica of a batched context equals the same replica run alone."""
+    from paper_0809_2811_amd import sw
+    specs = [((4, 4, 4), 1.0, 300.0), ((3, 4, 5), 0.93, 250.0), ((4, 5, 5), 1.05, 220.0)]
+    xs, vs, boxes = [], [], []
+    for k, (cells, rho, T) in enumerate(specs):
+        d = synth.lattice_at_density(cells, rho, sigma=0.2, temperature=T, seed=40 + k)
+        xs.append(f32(d["x"])); vs.append(f32(d["v"])); boxes.append(d["box"])
+    offsets = np.cumsum([0] + [len(x) for x in xs])
+    ctx = make_ctx(None if False else np.concatenate(xs), None, offsets=offsets, boxes=boxes)
+    xd, vd = to_dev(np.concatenate(xs)), to_dev(np.concatenate(vs))
+    T0 = [s[2] for s in specs]
+    f, th = ctx.step(xd, vd, 30, thermostat=sw.SW_BERENDSEN, T0=T0, tau_fs=100.0, thermo_every=5)
+    xb, vb = from_dev(xd), from_dev(vd)
+    for r in range(3):
+        c1 = make_ctx(xs[r], boxes[r])
+        x1, v1 = to_dev(xs[r]), to_dev(vs[r])
+        f1, th1 = c1.step(x1, v1, 30, thermostat=sw.SW_BERENDSEN, T0=[T0[r]], tau_fs=100.0, thermo_every=5)
+        sl = slice(offsets[r], offsets[r + 1])
+        assert np.array_equal(from_dev(x1), xb[sl])
+        assert np.array_equal(from_dev(v1), vb[sl])
+        assert np.array_equal(th1.cpu().numpy()[:, 0], th.cpu().numpy()[:, r])
