@@ -1,0 +1,207 @@
+"""Throughput benchmark of the mW Stillinger-Weber engine on one MI355X.
+
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--forms large,batched,adjoint|none]
+
+Main line: the 4096-atom liquid workload - 8x8x8 diamond cells scaled to
+1.00 g/cm^3, melted for 2000 velocity-Verlet steps (10 fs) with velocities
+rescaled to 400 K, then 500 steps rescaled to 298 K, then W untimed and K
+timed NVE steps.  A "step" is one full velocity-Verlet step of the whole path
+(neighbour rows rebuilt on the device when the displacement check fires,
+moments, forces, integration, thermo sums every 100 steps).  Inputs are
+resident in HBM before the timed region starts.
+
+Prints one JSON line.  The dominant kernel's duration comes from HIP events
+recorded by the library around sampled launches inside the timed region.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "atom-steps/s (mW SW force+step) plain vs batched; adjoint cost per step; % roofline"
+RC = 1.8 * 2.3925
+PEAK_FP32_VALU = 78.6e12   # 256 CU x 64 lanes x 2 flop (FMA) x 2.4 GHz, non-packed FP32
+PEAK_HBM = 8.0e12
+
+# Algorithmic work of the force kernel (k_forces, NVE mode), counted from its
+# source: per active directed pair (r < a sigma) 120 flop incl. 4
+# transcendentals; per row entry beyond a sigma 14 flop (distance test);
+# per atom 30 flop (group reduction, two half-kicks, drift).  Bytes per atom:
+# own position, moments, row length and row, force, velocity, new position,
+# binning slot: 16+48+4+4*row+16+32+16+8.
+FLOP_PER_ACTIVE = 120.0
+FLOP_PER_INACTIVE = 14.0
+FLOP_PER_ATOM = 30.0
+# Moments kernel: 44 flop incl. 3 transcendentals per active pair, 14 per
+# inactive entry, 20 per atom.
+MOM_FLOP_PER_ACTIVE = 44.0
+
+
+def number_density(rho_gcc=1.0, mass=18.015):
+    return rho_gcc / mass * 6.02214076e23 * 1e-24
+
+
+def expected_counts(rho_gcc, skin):
+    n = number_density(rho_gcc)
+    act = 4.0 / 3.0 * np.pi * RC ** 3 * n
+    row = 4.0 / 3.0 * np.pi * (RC + skin) ** 3 * n
+    return act, row
+
+
+def force_kernel_work(n_atoms, rho_gcc, skin):
+    act, row = expected_counts(rho_gcc, skin)
+    flop = n_atoms * (act * FLOP_PER_ACTIVE + (row - act) * FLOP_PER_INACTIVE + FLOP_PER_ATOM)
+    bytes_ = n_atoms * (16 + 48 + 4 + 4 * row + 16 + 32 + 16 + 8)
+    return flop, bytes_
+
+
+def sync():
+    import torch
+    torch.cuda.synchronize()
+
+
+def prepare_liquid(cfg, skin, tuning):
+    """Lattice -> melt at 400 K (2000 steps) -> 298 K (500 steps) on the GPU."""
+    import torch
+    from paper_0809_2811_amd import sw, synth
+    ctx = sw.Context([0, len(cfg["x"])], [cfg["box"]], cutoff=RC, skin=skin, nbr_capacity=64, tuning=tuning)
+    x = torch.from_numpy(synth.to_float4(cfg["x"])).cuda()
+    v = torch.from_numpy(synth.to_float4(cfg["v"])).cuda()
+    ctx.step(x, v, cfg["melt_steps"], thermostat=sw.SW_RESCALE, T0=cfg["melt_T"])
+    ctx.step(x, v, 500, thermostat=sw.SW_RESCALE, T0=cfg["T"])
+    return ctx, x, v
+
+
+def timed_nve(ctx, x, v, steps, thermo_every=100, timing=50):
+    from paper_0809_2811_amd import sw
+    ctx.set_tuning(timing=timing)
+    r0 = ctx.query(sw.SW_Q_REBUILDS)
+    sync()
+    t0 = time.perf_counter()
+    f, th = ctx.step(x, v, steps, thermo_every=thermo_every if steps >= thermo_every else 0)
+    sync()
+    dt = time.perf_counter() - t0
+    out = dict(seconds=dt, rebuilds=ctx.query(sw.SW_Q_REBUILDS) - r0)
+    ns = ctx.query(sw.SW_Q_TIMED_STEPS)
+    if ns > 0:
+        out["forces_us"] = ctx.query(sw.SW_Q_TIME_FORCES_NS) / ns / 1e3
+        out["moments_us"] = ctx.query(sw.SW_Q_TIME_MOMENTS_NS) / ns / 1e3
+        out["timed_launches"] = ns
+    if th is not None:
+        e = th[:, 0, 0] + th[:, 0, 1] + th[:, 0, 2]
+        e = e.cpu().numpy()
+        out["etot_first_last"] = [float(e[0]), float(e[-1])]
+    ctx.set_tuning(timing=0)
+    return out
+
+
+def roofline(n_atoms, rho, skin, kernel_us):
+    flop, bytes_ = force_kernel_work(n_atoms, rho, skin)
+    achieved = flop / (kernel_us * 1e-6)
+    return {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32_VALU / 1e12, "unit": "TFLOP/s",
+            "frac": achieved / PEAK_FP32_VALU, "traffic": None, "kernel": "k_forces (NVE mode)",
+            "kernel_us": kernel_us, "flop_per_launch": flop, "alg_bytes_per_launch": bytes_,
+            "hbm_frac_alg": bytes_ / (kernel_us * 1e-6) / PEAK_HBM}
+
+
+def cpu_baseline(target_s=15.0):
+    """The FP64 oracle (single thread) on a 4096-atom 298 K liquid: the
+    oracle-made 512-atom liquid tiled 2x2x2 and perturbed by 0.02 A."""
+    import oracle
+    from paper_0809_2811_amd import synth
+    x, v, L = synth.load_state(os.path.join(ROOT, "tests", "golden", "liquid512_298K.npz"))
+    x, v, L = synth.tile(x, v, L, 2, sigma=0.02, seed=5)
+    n = len(x)
+    t0 = time.perf_counter()
+    x1, v1, _, _ = oracle.vv(x, v, L, 10, dt=10.0)
+    per_step = (time.perf_counter() - t0) / 10
+    steps = max(10, int(target_s / per_step))
+    t0 = time.perf_counter()
+    oracle.vv(x1, v1, L, steps, dt=10.0)
+    dt = time.perf_counter() - t0
+    return {"value": n * steps / dt, "unit": "atom-steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"{n}-atom 298 K liquid (oracle-made 512-atom liquid tiled 2x2x2), {steps} FP64 NVE "
+                      f"velocity-Verlet steps at 10 fs, single thread, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10000)
+    ap.add_argument("--warmup", type=int, default=500)
+    ap.add_argument("--skin", type=float, default=1.0)
+    ap.add_argument("--lpa", type=int, default=0, help="lanes per atom (0 = tuned default)")
+    ap.add_argument("--forms", default="large", help="comma list of large,batched,adjoint or none")
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs on one GPU only: this engine has no multi-GPU path (see DESIGN.md for how "
+              "it would shard); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_0809_2811_amd import synth, tune
+    torch.cuda.init()
+
+    cfg = synth.config(1)
+    n = len(cfg["x"])
+    tuning = tune.best(n, 1.0, args.skin)
+    if args.lpa:
+        tuning["lanes_per_atom"] = args.lpa
+    ctx, x, v = prepare_liquid(cfg, args.skin, tuning)
+    if args.warmup > 0:
+        ctx.step(x, v, args.warmup)
+    res = timed_nve(ctx, x, v, args.steps)
+    value = n * args.steps / res["seconds"]
+    line = {
+        "metric": METRIC, "value": value, "unit": "atom-steps/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": res["seconds"] * 1e3 / args.steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "liquid4096_nve: 4096 mW atoms (8^3 diamond cells at 1.00 g/cm^3), melted "
+                               "2000 steps at 400 K + 500 steps at 298 K, NVE velocity Verlet dt=10 fs",
+                   "n_atoms": n, "skin_A": args.skin, "tuning": tuning, "rebuilds": res["rebuilds"],
+                   "thermo_every": 100},
+    }
+    if "forces_us" in res:
+        line["roofline"] = roofline(n, 1.0, args.skin, res["forces_us"])
+        line["roofline"]["moments_us"] = res["moments_us"]
+    forms = [f for f in args.forms.split(",") if f and f != "none"]
+    line["forms"] = {}
+    if "large" in forms:
+        line["forms"]["large_box"] = bench_large()
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(line), flush=True)
+
+
+def bench_large(steps=1000, skin=0.5):
+    """262144 atoms (32^3 cells, 1.00 g/cm^3), 298 K liquid, 1000 NVE steps,
+    rows rebuilt at least every 10 steps and whenever the skin check fires."""
+    from paper_0809_2811_amd import synth, tune
+    cfg = synth.config(2)
+    n = len(cfg["x"])
+    tuning = tune.best(n, 1.0, skin)
+    tuning["rebuild_every"] = 10
+    ctx, x, v = prepare_liquid(cfg, skin, tuning)
+    ctx.step(x, v, 50)
+    res = timed_nve(ctx, x, v, steps)
+    out = {"value": n * steps / res["seconds"], "unit": "atom-steps/s", "steps": steps,
+           "ms_per_step": res["seconds"] * 1e3 / steps, "n_atoms": n, "skin_A": skin,
+           "rebuilds": res["rebuilds"], "tuning": tuning,
+           "workload": "large_box: 262144 atoms, 298 K liquid, NVE dt=10 fs, 0.5 A skin, rows rebuilt at "
+                       "least every 10 steps"}
+    if "forces_us" in res:
+        out["roofline"] = roofline(n, 1.0, skin, res["forces_us"])
+        out["roofline"]["moments_us"] = res["moments_us"]
+    return out
+
+
+if __name__ == "__main__":
+    main()

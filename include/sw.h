@@ -179,6 +179,9 @@ typedef struct sw_tuning {
   int persistent;       /* 1: sw_step runs as one cooperative persistent launch */
   int rebuild_every;    /* also rebuild rows at least this often (0 = only on
                            displacement)                                        */
+  int timing;           /* > 0: every timing-th step of sw_step, bracket the
+                           moments and force launches with HIP events and add
+                           their durations to the SW_Q_TIME_* counters          */
 } sw_tuning;
 int sw_set_tuning(sw_ctx* ctx, const sw_tuning* t);
 int sw_get_tuning(const sw_ctx* ctx, sw_tuning* t);
@@ -191,7 +194,10 @@ enum {
   SW_Q_REBUILDS = 3,      /* row rebuilds since creation               */
   SW_Q_CELL_CAPACITY = 5,
   SW_Q_DEVICE_BYTES = 6,  /* device memory owned by the context        */
-  SW_Q_STEPS = 7          /* integration steps since creation          */
+  SW_Q_STEPS = 7,         /* integration steps since creation          */
+  SW_Q_TIME_MOMENTS_NS = 8, /* summed event time of sampled moments launches */
+  SW_Q_TIME_FORCES_NS = 9,  /* summed event time of sampled force launches   */
+  SW_Q_TIMED_STEPS = 10     /* number of sampled steps (reset by sw_set_tuning) */
 };
 int sw_query(sw_ctx* ctx, int what, long long* out);
 

@@ -25,7 +25,10 @@ struct sw_ctx {
   std::vector<RepInfo> reps;
   int ctot = 0;
   std::vector<int> tile_rep, cell_rank;
-  sw_tuning tune{8, 0, 0, 0};
+  sw_tuning tune{8, 0, 0, 0, 0};
+  std::vector<hipEvent_t> tev;     // sampled launch timing: 3 events per sample
+  double t_mom_ms = 0.0, t_for_ms = 0.0;
+  long long t_samples = 0;
   Dev d{};
   RepInfo* d_reps = nullptr;
   int* d_tile_rep = nullptr;
@@ -81,7 +84,7 @@ void free_list(std::vector<void*>& list) {
 int lpa_for(const sw_ctx* c) {
   int lpa = c->tune.lanes_per_atom;
   // rebuild staging needs 2 * (256 / lpa) * cap ints of LDS; keep it <= 64 KiB
-  while (lpa < 16 && 2 * (kBlock / lpa) * c->cap * 4 + 4 * (kBlock / lpa) > 65536) lpa *= 2;
+  while (lpa < 16 && 2 * (kBlock / lpa) * c->cap * 4 + 57 * 4 * (kBlock / lpa) > 65536) lpa *= 2;
   return lpa;
 }
 
@@ -109,7 +112,7 @@ hipError_t alloc_all(sw_ctx* c) {
   SWA(c->d.partial, (np / 16 + 1) * kNQ);
   SWA(c->d.thermo_cur, (size_t)c->R * kNQ);
   SWA(c->d.arrive, (size_t)c->R);
-  SWA(c->d.dmax, 2);
+  SWA(c->d.dflag, 2 * (size_t)c->R);
   SWA(c->d.flags, F_NFLAGS);
   SWA(c->d_reps, (size_t)c->R);
   SWA(c->d_tile_rep, c->tile_rep.size());
@@ -134,7 +137,7 @@ hipError_t alloc_all(sw_ctx* c) {
   if ((e = hipMemcpy(c->d_cell_rank, c->cell_rank.data(), sizeof(int) * c->ctot, hipMemcpyHostToDevice)) != hipSuccess) return e;
   if ((e = hipMemset(c->d.arrive, 0, sizeof(int) * c->R)) != hipSuccess) return e;
   if ((e = hipMemset(c->d.flags, 0, sizeof(int) * F_NFLAGS)) != hipSuccess) return e;
-  if ((e = hipMemset(c->d.dmax, 0, sizeof(unsigned) * 2)) != hipSuccess) return e;
+  if ((e = hipMemset(c->d.dflag, 0, sizeof(int) * 2 * c->R)) != hipSuccess) return e;
   if ((e = hipMemset(c->d.thermo_cur, 0, sizeof(double) * kNQ * c->R)) != hipSuccess) return e;
   return hipSuccess;
 }
@@ -176,7 +179,7 @@ hipError_t reset_flags(sw_ctx* c, hipStream_t s) {
   // keep the cumulative rebuild counter (slot F_REBUILDS)
   hipError_t e = launch_fill_i32(c->d.flags, 0, F_REBUILDS, s);
   if (e != hipSuccess) return e;
-  return launch_fill_i32((int*)c->d.dmax, 0, 2, s);
+  return launch_fill_i32(c->d.dflag, 0, 2 * c->R, s);
 }
 
 struct Flags { int nbr_over, nbr_need, cell_over, overlap; };
@@ -222,7 +225,7 @@ hipError_t sort_in(sw_ctx* c, const float* x, const float* v, hipStream_t s) {
                              c->d_uq, c->d_key, c->d_scnt, c->d_sstart, c->d_scur, c->d_order, s);
   if (e != hipSuccess) return e;
   if ((e = launch_fill_i32(c->d.gcnt[0], 0, c->ctot, s)) != hipSuccess) return e;
-  if ((e = launch_bin(c->d, 0, 0, s)) != hipSuccess) return e;
+  if ((e = launch_bin(c->d, 0, 0, 0.f, s)) != hipSuccess) return e;
   c->have_order = true;
   return hipSuccess;
 }
@@ -349,6 +352,7 @@ int sw_create(sw_ctx** out, int n_replicas, const long long* h_offsets, const do
 void sw_destroy(sw_ctx* ctx) {
   if (!ctx) return;
   (void)hipDeviceSynchronize();
+  for (hipEvent_t e : ctx->tev) (void)hipEventDestroy(e);
   free_list(ctx->grow_allocs);
   free_list(ctx->allocs);
   delete ctx;
@@ -357,8 +361,11 @@ void sw_destroy(sw_ctx* ctx) {
 int sw_set_tuning(sw_ctx* ctx, const sw_tuning* t) {
   if (!ctx || !t) return SW_EINVAL;
   if (t->lanes_per_atom != 4 && t->lanes_per_atom != 8 && t->lanes_per_atom != 16) return SW_EUNSUPPORTED;
-  if (t->graph_steps < 0 || t->rebuild_every < 0 || (t->persistent != 0 && t->persistent != 1)) return SW_EINVAL;
+  if (t->graph_steps < 0 || t->rebuild_every < 0 || t->timing < 0 || (t->persistent != 0 && t->persistent != 1))
+    return SW_EINVAL;
   ctx->tune = *t;
+  ctx->t_mom_ms = ctx->t_for_ms = 0.0;
+  ctx->t_samples = 0;
   return SW_OK;
 }
 
@@ -430,7 +437,7 @@ int sw_forces(sw_ctx* ctx, const float* x, const sw_params* params, float* f, do
     } else {
       if ((e = launch_gather_ids(ctx->d, (const float4*)x, 0, s)) != hipSuccess) return fail_hip(ctx, e);
       if ((e = launch_fill_i32(ctx->d.gcnt[0], 0, ctx->ctot, s)) != hipSuccess) return fail_hip(ctx, e);
-      if ((e = launch_bin(ctx->d, 0, 1, s)) != hipSuccess) return fail_hip(ctx, e);
+      if ((e = launch_bin(ctx->d, 0, 1, ph.half_skin, s)) != hipSuccess) return fail_hip(ctx, e);
     }
     const int lpa = lpa_for(ctx);
     if ((e = launch_moments(ctx->d, ph, lpa, 0, force_rebuild, 1, s)) != hipSuccess) return fail_hip(ctx, e);
@@ -473,7 +480,15 @@ int sw_step(sw_ctx* ctx, float* x, float* v, float* f, const sw_params* params, 
       return fail_hip(ctx, e);
   }
   const int lpa = lpa_for(ctx);
+  const int period = ctx->tune.timing;
+  const int max_samples = period > 0 ? std::min(256, nsteps / period) : 0;
+  while ((int)ctx->tev.size() < 3 * max_samples) {
+    hipEvent_t ev;
+    if ((e = hipEventCreate(&ev)) != hipSuccess) return fail_hip(ctx, e);
+    ctx->tev.push_back(ev);
+  }
   for (int attempt = 0; attempt < 6; ++attempt) {
+    int samples = 0;
     if ((e = reset_flags(ctx, s)) != hipSuccess) return fail_hip(ctx, e);
     if ((e = sort_in(ctx, x, v, s)) != hipSuccess) return fail_hip(ctx, e);
     if ((e = launch_moments(ctx->d, ph, lpa, 0, 1, 0, s)) != hipSuccess) return fail_hip(ctx, e);
@@ -486,14 +501,22 @@ int sw_step(sw_ctx* ctx, float* x, float* v, float* f, const sw_params* params, 
         const bool rec = thermo && (t % thermo_every == 0);
         double* row = rec ? thermo + (size_t)(t / thermo_every - 1) * ctx->R * kNQ : nullptr;
         const int force_rb = ctx->tune.rebuild_every > 0 && (t % ctx->tune.rebuild_every == 0);
+        const bool timed = samples < max_samples && !rec && t % period == 0;
+        hipEvent_t* ev = timed ? &ctx->tev[3 * samples] : nullptr;
+        if (timed && (e = hipEventRecord(ev[0], s)) != hipSuccess) return fail_hip(ctx, e);
         if ((e = launch_moments(ctx->d, ph, lpa, par, force_rb, rec, s)) != hipSuccess) return fail_hip(ctx, e);
+        if (timed && (e = hipEventRecord(ev[1], s)) != hipSuccess) return fail_hip(ctx, e);
         if (thermostat == SW_NVE) {
           const int mode = t == nsteps ? MODE_NVE_LAST : MODE_NVE;
           if ((e = launch_forces(ctx->d, ph, lpa, mode, rec, par, row, s)) != hipSuccess) return fail_hip(ctx, e);
         } else {
           if ((e = launch_forces(ctx->d, ph, lpa, MODE_KICK, rec, par, row, s)) != hipSuccess) return fail_hip(ctx, e);
-          if ((e = launch_thermostat(ctx->d, ph, par, t == nsteps, s)) != hipSuccess) return fail_hip(ctx, e);
         }
+        if (timed && (e = hipEventRecord(ev[2], s)) != hipSuccess) return fail_hip(ctx, e);
+        if (timed) ++samples;
+        if (thermostat != SW_NVE &&
+            (e = launch_thermostat(ctx->d, ph, par, t == nsteps, s)) != hipSuccess)
+          return fail_hip(ctx, e);
       }
     }
     Flags fl;
@@ -506,6 +529,14 @@ int sw_step(sw_ctx* ctx, float* x, float* v, float* f, const sw_params* params, 
     if ((e = launch_scatter_out(ctx->d, par_final, (float4*)x, (float4*)v, (float4*)f, s)) != hipSuccess)
       return fail_hip(ctx, e);
     if ((e = hipStreamSynchronize(s)) != hipSuccess) return fail_hip(ctx, e);
+    for (int k = 0; k < samples; ++k) {
+      float a = 0.f, b = 0.f;
+      if ((e = hipEventElapsedTime(&a, ctx->tev[3 * k], ctx->tev[3 * k + 1])) != hipSuccess) return fail_hip(ctx, e);
+      if ((e = hipEventElapsedTime(&b, ctx->tev[3 * k + 1], ctx->tev[3 * k + 2])) != hipSuccess) return fail_hip(ctx, e);
+      ctx->t_mom_ms += a;
+      ctx->t_for_ms += b;
+    }
+    ctx->t_samples += samples;
     ctx->steps += nsteps;
     return fl.overlap ? SW_EOVERLAP : SW_OK;
   }
@@ -521,6 +552,9 @@ int sw_query(sw_ctx* ctx, int what, long long* out) {
     case SW_Q_CELL_CAPACITY: *out = ctx->cc; return SW_OK;
     case SW_Q_DEVICE_BYTES: *out = (long long)ctx->bytes; return SW_OK;
     case SW_Q_STEPS: *out = ctx->steps; return SW_OK;
+    case SW_Q_TIME_MOMENTS_NS: *out = (long long)(ctx->t_mom_ms * 1e6); return SW_OK;
+    case SW_Q_TIME_FORCES_NS: *out = (long long)(ctx->t_for_ms * 1e6); return SW_OK;
+    case SW_Q_TIMED_STEPS: *out = ctx->t_samples; return SW_OK;
     case SW_Q_REBUILDS: {
       int h[F_NFLAGS];
       hipError_t e = hipDeviceSynchronize();

@@ -12,7 +12,8 @@
 //   nl[Npad][cap]     int     neighbour rows (internal indices, ascending)
 //   nn[Npad]          int     row lengths
 //   mom[Npad][3]      float4  per-centre three-body moments and energies
-//   gcnt[2][Ctot], gmem[2][Ctot][cc]   binning cells (ping-pong)
+//   gcnt[2][Ctot], gmem[2][Ctot][cc]   binning cells (ping-pong), positions with
+//                                      the internal index in .w
 #pragma once
 #include <hip/hip_runtime.h>
 #include <cstdint>
@@ -56,11 +57,11 @@ struct Dev {
   int* nn;
   float4* mom;
   int* gcnt[2];
-  int* gmem[2];
+  uint4* gmem[2];      // [2][Ctot][cc] binned positions, .w = internal index
   double* partial;     // [nblocks][kNQ]
   double* thermo_cur;  // [R][kNQ]
   int* arrive;         // [R]
-  unsigned* dmax;      // [2] largest displacement since the build (float bits, A)
+  int* dflag;          // [2][R] set when an atom of the replica moved > half skin since its build
   int* flags;          // [F_NFLAGS]
   const RepInfo* reps;
   const int* tile_rep; // [Npad / 64] replica of each 64-atom tile
@@ -93,7 +94,7 @@ hipError_t launch_sort(const Dev& d, const float4* x_user, const float4* v_user,
                        const long long* uoff, int R, const int* cell_rank, uint4* uq, int* key,
                        int* cnt, int* start, int* cursor, int* order, hipStream_t s);
 hipError_t launch_gather_ids(const Dev& d, const float4* x_user, int par, hipStream_t s);
-hipError_t launch_bin(const Dev& d, int par, int check_disp, hipStream_t s);
+hipError_t launch_bin(const Dev& d, int par, int check_disp, float half_skin, hipStream_t s);
 hipError_t launch_moments(const Dev& d, const Phys& p, int lpa, int par, int force_rebuild,
                           int energy, hipStream_t s);
 hipError_t launch_forces(const Dev& d, const Phys& p, int lpa, int mode, int vir, int par,

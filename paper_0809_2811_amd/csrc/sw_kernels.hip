@@ -70,10 +70,11 @@ __device__ __forceinline__ float rsq(float x) { return __builtin_amdgcn_rsqf(x);
 __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ float ex2(float x) { return __builtin_amdgcn_exp2f(x); }
 
-// Drift by dt*v in fraction units, bin into grid `gp`, return the distance
-// from the row-build reference.  Flags steps longer than a quarter edge.
-__device__ __forceinline__ float drift_bin(const Dev& d, const Phys& p, const RepInfo& R, int i,
-                                           uint4 u, const float4& v, int gp) {
+// Drift by dt*v in fraction units, bin into grid `gp`, and raise the
+// replica's rebuild flag if the atom is now more than half the skin away from
+// its row-build position.  Flags steps longer than a quarter edge.
+__device__ __forceinline__ void drift_bin(const Dev& d, const Phys& p, const RepInfo& R, int rep, int i,
+                                          uint4 u, const float4& v, int gp) {
   const float mx = p.dt * v.x * R.inv_scale[0];
   const float my = p.dt * v.y * R.inv_scale[1];
   const float mz = p.dt * v.z * R.inv_scale[2];
@@ -85,10 +86,10 @@ __device__ __forceinline__ float drift_bin(const Dev& d, const Phys& p, const Re
   d.u[gp][i] = u;
   const int c = R.cell_off + cell_of(u, R.nc[0], R.nc[1], R.nc[2]);
   const int slot = atomicAdd(&d.gcnt[gp][c], 1);
-  if (slot < d.cc) d.gmem[gp][(size_t)c * d.cc + slot] = i;
+  if (slot < d.cc) d.gmem[gp][(size_t)c * d.cc + slot] = make_uint4(u.x, u.y, u.z, (unsigned)i);
   else atomicOr(&d.flags[F_CELL_OVER], 1);
   const float3 dd = disp(d.uref[i], u, R.scale[0], R.scale[1], R.scale[2]);
-  return sqrtf(dd.x * dd.x + dd.y * dd.y + dd.z * dd.z);
+  if (dd.x * dd.x + dd.y * dd.y + dd.z * dd.z > p.half_skin * p.half_skin) d.dflag[gp * d.R + rep] = 1;
 }
 
 // ----------------------------------------------------------------- sorting
@@ -201,82 +202,116 @@ __global__ __launch_bounds__(kBlock) void k_gather_ids(Dev d, const float4* __re
 }
 
 // Bin positions u[par] into grid `par` (counts must be zero) and, if asked,
-// record the largest displacement from the row-build reference.
-__global__ __launch_bounds__(kBlock) void k_bin(Dev d, int par, int check) {
+// raise the replica's rebuild flag for atoms beyond half_skin of their
+// row-build position.
+__global__ __launch_bounds__(kBlock) void k_bin(Dev d, int par, int check, float half_skin) {
   const int i = blockIdx.x * kBlock + threadIdx.x;
-  float dist = 0.f;
   if (i < d.npad) {
-    const RepInfo& R = d.reps[d.tile_rep[i >> 6]];
+    const int rep = d.tile_rep[i >> 6];
+    const RepInfo& R = d.reps[rep];
     if (i < R.iend) {
       const uint4 u = d.u[par][i];
       const int c = R.cell_off + cell_of(u, R.nc[0], R.nc[1], R.nc[2]);
       const int slot = atomicAdd(&d.gcnt[par][c], 1);
-      if (slot < d.cc) d.gmem[par][(size_t)c * d.cc + slot] = i;
+      if (slot < d.cc) d.gmem[par][(size_t)c * d.cc + slot] = make_uint4(u.x, u.y, u.z, (unsigned)i);
       else atomicOr(&d.flags[F_CELL_OVER], 1);
       if (check) {
         const float3 dd = disp(d.uref[i], u, R.scale[0], R.scale[1], R.scale[2]);
-        dist = sqrtf(dd.x * dd.x + dd.y * dd.y + dd.z * dd.z);
+        if (dd.x * dd.x + dd.y * dd.y + dd.z * dd.z > half_skin * half_skin) d.dflag[par * d.R + rep] = 1;
       }
     }
   }
-  dist = wave_max(dist);
-  if (check && (threadIdx.x & 63) == 0 && dist > 0.f) atomicMax(&d.dmax[par], __float_as_uint(dist));
 }
 
 // ----------------------------------------------------------------- moments
-// One group of LPA lanes per atom.  When the displacement flag (or the
-// caller) asks for it, the group first rebuilds the atom's neighbour row from
-// the 27 surrounding binning cells, then accumulates T, V, S (and P, E2 on
-// energy steps) over the active neighbours r < a sigma.
+// One group of LPA lanes per atom.  When the replica's displacement flag (or
+// the caller) asks for it, the group first rebuilds the atom's row from the
+// 27 surrounding binning cells (each cell stores positions with the atom
+// index in .w, so a cell is one contiguous read), keeping every atom within
+// cutoff + skin, sorted by index.  Then the group accumulates T, V, S (and
+// P, E2 on energy steps) over the active neighbours r < a sigma.
 template <int LPA, bool ENERGY>
 __global__ __launch_bounds__(kBlock) void k_moments(Dev d, Phys p, int par, int force_rebuild) {
   constexpr int APB = kBlock / LPA;
-  extern __shared__ int lds[];
+  extern __shared__ int lds[];             // [APB][cap] candidates, [APB][cap] sorted, [APB] counts,
+                                           // [APB][56] cell prefix and ids
   const int bid = xcd_remap(blockIdx.x, gridDim.x);
   const int g = threadIdx.x / LPA, lane = threadIdx.x % LPA;
   const int i = bid * APB + g;
-  const RepInfo& R = d.reps[d.tile_rep[(bid * APB) >> 6]];
+  const int rep = d.tile_rep[(bid * APB) >> 6];
+  const RepInfo& R = d.reps[rep];
   const float sc0 = R.scale[0], sc1 = R.scale[1], sc2 = R.scale[2];
 
-  if (blockIdx.x == 0 && threadIdx.x == 0) d.dmax[par ^ 1] = 0u;
+  for (int r = blockIdx.x * kBlock + threadIdx.x; r < d.R; r += gridDim.x * kBlock) d.dflag[(par ^ 1) * d.R + r] = 0;
   for (int c = blockIdx.x * kBlock + threadIdx.x; c < d.ctot; c += gridDim.x * kBlock) d.gcnt[par ^ 1][c] = 0;
 
-  const bool rebuild = force_rebuild || (__uint_as_float(d.dmax[par]) > p.half_skin);
+  // each replica rebuilds on its own displacement record
+  const bool rebuild = force_rebuild || d.dflag[par * d.R + rep] != 0;
   const bool real = i < R.iend;
   const uint4 ui = d.u[par][i];
   const int cap = d.cap;
   int nn = 0;
   const int* row = d.nl + (size_t)i * cap;
 
-  if (rebuild) {
+  if (rebuild) {                           // block-uniform
     int* cand = lds + g * cap;
     int* srt = lds + APB * cap + g * cap;
     int* cnt = lds + 2 * APB * cap;
+    int* pre = lds + 2 * APB * cap + APB + g * 56;   // [28] prefix of cell counts
+    int* cid = pre + 28;                             // [27] cell ids
     if (lane == 0) cnt[g] = 0;
-    __syncthreads();
+    const int n0 = R.nc[0], n1 = R.nc[1], n2 = R.nc[2];
+    const int cx = (int)__umulhi(ui.x, (unsigned)n0);
+    const int cy = (int)__umulhi(ui.y, (unsigned)n1);
+    const int cz = (int)__umulhi(ui.z, (unsigned)n2);
+    const int* gc = d.gcnt[par];
+    const uint4* gm = d.gmem[par];
     if (real) {
-      const int n0 = R.nc[0], n1 = R.nc[1], n2 = R.nc[2];
-      const int cx = (int)__umulhi(ui.x, (unsigned)n0);
-      const int cy = (int)__umulhi(ui.y, (unsigned)n1);
-      const int cz = (int)__umulhi(ui.z, (unsigned)n2);
-      const int* gc = d.gcnt[par];
-      const int* gm = d.gmem[par];
-      const uint4* up = d.u[par];
-      for (int c = lane; c < 27; c += LPA) {
+      for (int c = lane; c < 27; c += LPA) {   // independent count loads
         int xx = cx + c / 9 - 1, yy = cy + (c / 3) % 3 - 1, zz = cz + c % 3 - 1;
         xx = xx < 0 ? xx + n0 : (xx >= n0 ? xx - n0 : xx);
         yy = yy < 0 ? yy + n1 : (yy >= n1 ? yy - n1 : yy);
         zz = zz < 0 ? zz + n2 : (zz >= n2 ? zz - n2 : zz);
         const int cell = R.cell_off + (xx * n1 + yy) * n2 + zz;
-        const int m = min(gc[cell], d.cc);
-        const int* mem = gm + (size_t)cell * d.cc;
-        for (int k = 0; k < m; ++k) {
-          const int j = mem[k];
-          if (j == i) continue;
-          const float3 dd = disp(ui, up[j], sc0, sc1, sc2);
-          if (dd.x * dd.x + dd.y * dd.y + dd.z * dd.z < p.rl2) {
-            const int s = atomicAdd(&cnt[g], 1);
-            if (s < cap) cand[s] = j;
+        cid[c] = cell;
+        pre[c + 1] = min(gc[cell], d.cc);
+      }
+    }
+    __syncthreads();
+    if (real && lane == 0) {
+      int run = 0;
+      pre[0] = 0;
+      for (int c = 0; c < 27; ++c) {
+        run += pre[c + 1];
+        pre[c + 1] = run;
+      }
+    }
+    __syncthreads();
+    if (real) {
+      const int ncand = pre[27];
+      const float rl2 = p.rl2;
+      // candidate slots k = lane + LPA*t, four per pass with independent loads
+      for (int k0 = lane; k0 < ncand; k0 += 4 * LPA) {
+        uint4 e[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const int k = k0 + t * LPA;
+          e[t] = make_uint4(ui.x, ui.y, ui.z, (unsigned)i);
+          if (k < ncand) {
+            int c = 0;
+#pragma unroll
+            for (int step = 16; step >= 1; step >>= 1)
+              if (c + step < 27 && pre[c + step] <= k) c += step;
+            e[t] = gm[(size_t)cid[c] * d.cc + (k - pre[c])];
+          }
+        }
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const int j = (int)e[t].w;
+          const float3 dd = disp(ui, e[t], sc0, sc1, sc2);
+          if (j != i && dd.x * dd.x + dd.y * dd.y + dd.z * dd.z < rl2) {
+            const int sl = atomicAdd(&cnt[g], 1);
+            if (sl < cap) cand[sl] = j;
           }
         }
       }
@@ -304,17 +339,17 @@ __global__ __launch_bounds__(kBlock) void k_moments(Dev d, Phys p, int par, int 
     __syncthreads();
     nn = real ? total : 0;
     row = srt;
-    if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(&d.flags[F_REBUILDS], 1);
+    if (bid * APB == R.ioff && threadIdx.x == 0) atomicAdd(&d.flags[F_REBUILDS], 1);
   } else {
     nn = real ? d.nn[i] : 0;
   }
 
   float T0 = 0.f, T1 = 0.f, T2 = 0.f, T3 = 0.f, T4 = 0.f, T5 = 0.f;
   float V0 = 0.f, V1 = 0.f, V2 = 0.f, S = 0.f, P = 0.f, E2 = 0.f;
-  const uint4* up = d.u[par];
+  const uint4* upm = d.u[par];
   for (int s = lane; s < nn; s += LPA) {
     const int j = row[s];
-    const float3 dd = disp(ui, up[j], sc0, sc1, sc2);
+    const float3 dd = disp(ui, upm[j], sc0, sc1, sc2);
     const float r2 = dd.x * dd.x + dd.y * dd.y + dd.z * dd.z;
     if (r2 < p.rc2) {
       const float ir = rsq(r2);
@@ -354,14 +389,11 @@ __global__ __launch_bounds__(kBlock) void k_moments(Dev d, Phys p, int par, int 
 }
 
 // ----------------------------------------------------------------- forces
-// Block partial sums of the thermo quantities, then the last block of each
-// replica (arrival counter) adds the replica's partials in block order.
+// Block partial sums of the thermo quantities (fixed order within the block).
+// The per-replica sums are taken by k_reduce_thermo after the kernel ends.
 template <int APB>
-__device__ void reduce_thermo(const Dev& d, int bid, int rep, const RepInfo& R, const double* q, bool writer,
-                              int g, double* ring_row) {
+__device__ void block_partials(const Dev& d, int bid, const double* q, bool writer, int g) {
   __shared__ double red[APB * kNQ];
-  __shared__ double tree[kBlock];
-  __shared__ int is_last;
   if (writer) {
 #pragma unroll
     for (int k = 0; k < kNQ; ++k) red[g * kNQ + k] = q[k];
@@ -370,34 +402,8 @@ __device__ void reduce_thermo(const Dev& d, int bid, int rep, const RepInfo& R, 
   if (threadIdx.x < kNQ) {
     double acc = 0.0;
     for (int a = 0; a < APB; ++a) acc += red[a * kNQ + threadIdx.x];
-    d.partial[(size_t)bid * kNQ + threadIdx.x] = acc;
+    d.partial[(size_t)threadIdx.x * (d.npad / APB) + bid] = acc;
   }
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const int nblk = (R.ipad_end - R.ioff) / APB;
-    is_last = atomicAdd(&d.arrive[rep], 1) == nblk - 1;
-  }
-  __syncthreads();
-  if (!is_last) return;
-  __threadfence();
-  const int b0 = R.ioff / APB, b1 = R.ipad_end / APB;
-  for (int k = 0; k < kNQ; ++k) {
-    double acc = 0.0;
-    for (int b = b0 + (int)threadIdx.x; b < b1; b += kBlock) acc += __ldg(&d.partial[(size_t)b * kNQ + k]);
-    tree[threadIdx.x] = acc;
-    __syncthreads();
-    for (int s = kBlock / 2; s > 0; s >>= 1) {
-      if ((int)threadIdx.x < s) tree[threadIdx.x] += tree[threadIdx.x + s];
-      __syncthreads();
-    }
-    if (threadIdx.x == 0) {
-      d.thermo_cur[rep * kNQ + k] = tree[0];
-      if (ring_row) ring_row[rep * kNQ + k] = tree[0];
-    }
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) d.arrive[rep] = 0;
 }
 
 // Force on each atom from its neighbours (pair term + its own centre's
@@ -408,7 +414,7 @@ __device__ void reduce_thermo(const Dev& d, int bid, int rep, const RepInfo& R, 
 //   NVE_LAST v += dt/2 a (full step: KE)
 //   KICK     as NVE_LAST, the thermostat kernel follows
 template <int LPA, int MODE, bool VIR>
-__global__ __launch_bounds__(kBlock) void k_forces(Dev d, Phys p, int par, double* ring_row) {
+__global__ __launch_bounds__(kBlock) void k_forces(Dev d, Phys p, int par) {
   constexpr int APB = kBlock / LPA;
   const int bid = xcd_remap(blockIdx.x, gridDim.x);
   const int g = threadIdx.x / LPA, lane = threadIdx.x % LPA;
@@ -501,7 +507,6 @@ __global__ __launch_bounds__(kBlock) void k_forces(Dev d, Phys p, int par, doubl
   double q[kNQ];
 #pragma unroll
   for (int k = 0; k < kNQ; ++k) q[k] = 0.0;
-  float dist = 0.f;
   if (real && lane == 0) {
     const float4 F = make_float4(fx, fy, fz, 0.f);
     d.f[i] = F;
@@ -520,22 +525,43 @@ __global__ __launch_bounds__(kBlock) void k_forces(Dev d, Phys p, int par, doubl
       if (MODE == MODE_NVE) {
         v.x += p.hdt_cm * F.x; v.y += p.hdt_cm * F.y; v.z += p.hdt_cm * F.z;
       }
-      if (MODE == MODE_START || MODE == MODE_NVE) dist = drift_bin(d, p, R, i, ui, v, par ^ 1);
+      if (MODE == MODE_START || MODE == MODE_NVE) drift_bin(d, p, R, rep, i, ui, v, par ^ 1);
       d.v[i] = v;
     }
   }
-  if (MODE == MODE_START || MODE == MODE_NVE) {
-    dist = wave_max(dist);
-    if ((threadIdx.x & 63) == 0 && dist > 0.f) atomicMax(&d.dmax[par ^ 1], __float_as_uint(dist));
+  if (kReduce) block_partials<APB>(d, bid, q, lane == 0, g);
+}
+
+// Per-replica sums of the block partials: one block per (replica, quantity),
+// threads stride over the replica's blocks, then a fixed tree.
+__global__ __launch_bounds__(kBlock) void k_reduce_thermo(Dev d, int apb, double* ring_row) {
+  __shared__ double tree[kBlock];
+  const int nbt = d.npad / apb;
+  for (int task = blockIdx.x; task < d.R * kNQ; task += gridDim.x) {
+    const int rep = task / kNQ, k = task % kNQ;
+    const RepInfo& R = d.reps[rep];
+    const int b0 = R.ioff / apb, b1 = R.ipad_end / apb;
+    const double* src = d.partial + (size_t)k * nbt;
+    double acc = 0.0;
+    for (int b = b0 + (int)threadIdx.x; b < b1; b += kBlock) acc += src[b];
+    tree[threadIdx.x] = acc;
+    __syncthreads();
+    for (int st = kBlock / 2; st > 0; st >>= 1) {
+      if ((int)threadIdx.x < st) tree[threadIdx.x] += tree[threadIdx.x + st];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+      d.thermo_cur[rep * kNQ + k] = tree[0];
+      if (ring_row) ring_row[rep * kNQ + k] = tree[0];
+    }
+    __syncthreads();
   }
-  if (kReduce) reduce_thermo<APB>(d, bid, rep, R, q, lane == 0, g, ring_row);
 }
 
 // Thermostat on the full-step velocities, then (unless last) the next
 // half-kick and drift.
 __global__ __launch_bounds__(kBlock) void k_thermostat(Dev d, Phys p, int par, int last) {
   const int i = blockIdx.x * kBlock + threadIdx.x;
-  float dist = 0.f;
   if (i < d.npad) {
     const int rep = d.tile_rep[i >> 6];
     const RepInfo& R = d.reps[rep];
@@ -552,14 +578,10 @@ __global__ __launch_bounds__(kBlock) void k_thermostat(Dev d, Phys p, int par, i
       if (!last) {
         const float4 F = d.f[i];
         v.x += p.hdt_cm * F.x; v.y += p.hdt_cm * F.y; v.z += p.hdt_cm * F.z;
-        dist = drift_bin(d, p, R, i, d.u[par][i], v, par ^ 1);
+        drift_bin(d, p, R, rep, i, d.u[par][i], v, par ^ 1);
       }
       d.v[i] = v;
     }
-  }
-  if (!last) {
-    dist = wave_max(dist);
-    if ((threadIdx.x & 63) == 0 && dist > 0.f) atomicMax(&d.dmax[par ^ 1], __float_as_uint(dist));
   }
 }
 
@@ -612,7 +634,7 @@ inline unsigned nblk(long long n, int b) { return (unsigned)((n + b - 1) / b); }
 template <int LPA>
 hipError_t moments_lpa(const Dev& d, const Phys& p, int par, int force_rebuild, int energy, hipStream_t s) {
   constexpr int APB = kBlock / LPA;
-  const size_t lds = sizeof(int) * (2 * (size_t)APB * d.cap + APB);
+  const size_t lds = sizeof(int) * (2 * (size_t)APB * d.cap + APB + 56 * (size_t)APB);
   const unsigned grid = (unsigned)(d.npad / APB);
   if (energy) hipLaunchKernelGGL((k_moments<LPA, true>), dim3(grid), dim3(kBlock), lds, s, d, p, par, force_rebuild);
   else hipLaunchKernelGGL((k_moments<LPA, false>), dim3(grid), dim3(kBlock), lds, s, d, p, par, force_rebuild);
@@ -623,8 +645,10 @@ template <int LPA, int MODE>
 hipError_t forces_mode(const Dev& d, const Phys& p, int vir, int par, double* ring_row, hipStream_t s) {
   constexpr int APB = kBlock / LPA;
   const unsigned grid = (unsigned)(d.npad / APB);
-  if (vir) hipLaunchKernelGGL((k_forces<LPA, MODE, true>), dim3(grid), dim3(kBlock), 0, s, d, p, par, ring_row);
-  else hipLaunchKernelGGL((k_forces<LPA, MODE, false>), dim3(grid), dim3(kBlock), 0, s, d, p, par, ring_row);
+  if (vir) hipLaunchKernelGGL((k_forces<LPA, MODE, true>), dim3(grid), dim3(kBlock), 0, s, d, p, par);
+  else hipLaunchKernelGGL((k_forces<LPA, MODE, false>), dim3(grid), dim3(kBlock), 0, s, d, p, par);
+  if (vir || MODE == MODE_KICK)
+    hipLaunchKernelGGL(k_reduce_thermo, dim3((unsigned)min(d.R * kNQ, 4096)), dim3(kBlock), 0, s, d, APB, ring_row);
   return hipGetLastError();
 }
 
@@ -663,8 +687,8 @@ hipError_t launch_gather_ids(const Dev& d, const float4* x_user, int par, hipStr
   return hipGetLastError();
 }
 
-hipError_t launch_bin(const Dev& d, int par, int check_disp, hipStream_t s) {
-  hipLaunchKernelGGL(k_bin, dim3(nblk(d.npad, kBlock)), dim3(kBlock), 0, s, d, par, check_disp);
+hipError_t launch_bin(const Dev& d, int par, int check_disp, float half_skin, hipStream_t s) {
+  hipLaunchKernelGGL(k_bin, dim3(nblk(d.npad, kBlock)), dim3(kBlock), 0, s, d, par, check_disp, half_skin);
   return hipGetLastError();
 }
 

@@ -32,6 +32,7 @@ SW_NVE, SW_RESCALE, SW_BERENDSEN = 0, 1, 2
 SW_THERMO_WIDTH = 12
 SW_Q_NATOMS, SW_Q_NREPLICAS, SW_Q_NBR_CAPACITY, SW_Q_REBUILDS = 0, 1, 2, 3
 SW_Q_CELL_CAPACITY, SW_Q_DEVICE_BYTES, SW_Q_STEPS = 5, 6, 7
+SW_Q_TIME_MOMENTS_NS, SW_Q_TIME_FORCES_NS, SW_Q_TIMED_STEPS = 8, 9, 10
 
 # symbols declared in include/sw.h
 EXPORTS = ("sw_params_mw", "sw_create", "sw_destroy", "sw_build_neighbors", "sw_get_neighbors",
@@ -46,7 +47,7 @@ class sw_params(ctypes.Structure):
 
 class sw_tuning(ctypes.Structure):
     _fields_ = [("lanes_per_atom", ctypes.c_int), ("graph_steps", ctypes.c_int),
-                ("persistent", ctypes.c_int), ("rebuild_every", ctypes.c_int)]
+                ("persistent", ctypes.c_int), ("rebuild_every", ctypes.c_int), ("timing", ctypes.c_int)]
 
 
 class SWError(RuntimeError):
@@ -63,6 +64,9 @@ def lib():
     """Load libsw.so; raises if it has not been built."""
     global _lib
     if _lib is None:
+        # torch ships its own libamdhip64.so.7; load it first so that libsw
+        # binds to the same HIP runtime instead of a second copy.
+        import torch  # noqa: F401
         if not _LIB_PATH.exists():
             raise RuntimeError(f"{_LIB_PATH} is missing: build it with paper_0809_2811_amd.build.build()")
         L = ctypes.CDLL(str(_LIB_PATH))
@@ -215,8 +219,8 @@ def sw_adjoint(ctx: int, x0, v0, params: sw_params, mass: float, dt: float, nste
                             opt(xS, "xS"), opt(vS, "vS"), _stream()), "sw_adjoint")
 
 
-def sw_set_tuning(ctx: int, lanes_per_atom=8, graph_steps=0, persistent=0, rebuild_every=0):
-    t = sw_tuning(int(lanes_per_atom), int(graph_steps), int(persistent), int(rebuild_every))
+def sw_set_tuning(ctx: int, lanes_per_atom=8, graph_steps=0, persistent=0, rebuild_every=0, timing=0):
+    t = sw_tuning(int(lanes_per_atom), int(graph_steps), int(persistent), int(rebuild_every), int(timing))
     _check(lib().sw_set_tuning(ctypes.c_void_p(ctx), ctypes.byref(t)), "sw_set_tuning")
 
 
@@ -224,7 +228,7 @@ def sw_get_tuning(ctx: int) -> dict:
     t = sw_tuning()
     _check(lib().sw_get_tuning(ctypes.c_void_p(ctx), ctypes.byref(t)), "sw_get_tuning")
     return dict(lanes_per_atom=t.lanes_per_atom, graph_steps=t.graph_steps, persistent=t.persistent,
-                rebuild_every=t.rebuild_every)
+                rebuild_every=t.rebuild_every, timing=t.timing)
 
 
 def sw_query(ctx: int, what: int) -> int:

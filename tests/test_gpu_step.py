@@ -120,7 +120,7 @@ def test_replicas_evolve_independently():
         d = synth.lattice_at_density(cells, rho, sigma=0.2, temperature=T, seed=40 + k)
         xs.append(f32(d["x"])); vs.append(f32(d["v"])); boxes.append(d["box"])
     offsets = np.cumsum([0] + [len(x) for x in xs])
-    ctx = make_ctx(None if False else np.concatenate(xs), None, offsets=offsets, boxes=boxes)
+    ctx = make_ctx(np.concatenate(xs), None, offsets=offsets, boxes=boxes)
     xd, vd = to_dev(np.concatenate(xs)), to_dev(np.concatenate(vs))
     T0 = [s[2] for s in specs]
     f, th = ctx.step(xd, vd, 30, thermostat=sw.SW_BERENDSEN, T0=T0, tau_fs=100.0, thermo_every=5)
