@@ -26,7 +26,7 @@ struct sw_ctx {
   int ctot = 0;
   std::vector<int> tile_rep, cell_rank;
   sw_tuning tune{8, 0, 0, 0, 0};
-  std::vector<hipEvent_t> tev;     // sampled launch timing: 3 events per sample
+  std::vector<hipEvent_t> tev;     // sampled launch timing: 4 events per sample
   double t_mom_ms = 0.0, t_for_ms = 0.0;
   long long t_samples = 0;
   Dev d{};
@@ -482,7 +482,7 @@ int sw_step(sw_ctx* ctx, float* x, float* v, float* f, const sw_params* params, 
   const int lpa = lpa_for(ctx);
   const int period = ctx->tune.timing;
   const int max_samples = period > 0 ? std::min(256, nsteps / period) : 0;
-  while ((int)ctx->tev.size() < 3 * max_samples) {
+  while ((int)ctx->tev.size() < 4 * max_samples) {
     hipEvent_t ev;
     if ((e = hipEventCreate(&ev)) != hipSuccess) return fail_hip(ctx, e);
     ctx->tev.push_back(ev);
@@ -502,18 +502,20 @@ int sw_step(sw_ctx* ctx, float* x, float* v, float* f, const sw_params* params, 
         double* row = rec ? thermo + (size_t)(t / thermo_every - 1) * ctx->R * kNQ : nullptr;
         const int force_rb = ctx->tune.rebuild_every > 0 && (t % ctx->tune.rebuild_every == 0);
         const bool timed = samples < max_samples && !rec && t % period == 0;
-        hipEvent_t* ev = timed ? &ctx->tev[3 * samples] : nullptr;
-        if (timed && (e = hipEventRecord(ev[0], s)) != hipSuccess) return fail_hip(ctx, e);
-        if ((e = launch_moments(ctx->d, ph, lpa, par, force_rb, rec, s)) != hipSuccess) return fail_hip(ctx, e);
-        if (timed && (e = hipEventRecord(ev[1], s)) != hipSuccess) return fail_hip(ctx, e);
+        KTimer tm_m, tm_f;
+        if (timed) {
+          tm_m = KTimer{ctx->tev[4 * samples], ctx->tev[4 * samples + 1]};
+          tm_f = KTimer{ctx->tev[4 * samples + 2], ctx->tev[4 * samples + 3]};
+          ++samples;
+        }
+        if ((e = launch_moments(ctx->d, ph, lpa, par, force_rb, rec, s, tm_m)) != hipSuccess) return fail_hip(ctx, e);
         if (thermostat == SW_NVE) {
           const int mode = t == nsteps ? MODE_NVE_LAST : MODE_NVE;
-          if ((e = launch_forces(ctx->d, ph, lpa, mode, rec, par, row, s)) != hipSuccess) return fail_hip(ctx, e);
+          if ((e = launch_forces(ctx->d, ph, lpa, mode, rec, par, row, s, tm_f)) != hipSuccess) return fail_hip(ctx, e);
         } else {
-          if ((e = launch_forces(ctx->d, ph, lpa, MODE_KICK, rec, par, row, s)) != hipSuccess) return fail_hip(ctx, e);
+          if ((e = launch_forces(ctx->d, ph, lpa, MODE_KICK, rec, par, row, s, tm_f)) != hipSuccess)
+            return fail_hip(ctx, e);
         }
-        if (timed && (e = hipEventRecord(ev[2], s)) != hipSuccess) return fail_hip(ctx, e);
-        if (timed) ++samples;
         if (thermostat != SW_NVE &&
             (e = launch_thermostat(ctx->d, ph, par, t == nsteps, s)) != hipSuccess)
           return fail_hip(ctx, e);
@@ -531,8 +533,8 @@ int sw_step(sw_ctx* ctx, float* x, float* v, float* f, const sw_params* params, 
     if ((e = hipStreamSynchronize(s)) != hipSuccess) return fail_hip(ctx, e);
     for (int k = 0; k < samples; ++k) {
       float a = 0.f, b = 0.f;
-      if ((e = hipEventElapsedTime(&a, ctx->tev[3 * k], ctx->tev[3 * k + 1])) != hipSuccess) return fail_hip(ctx, e);
-      if ((e = hipEventElapsedTime(&b, ctx->tev[3 * k + 1], ctx->tev[3 * k + 2])) != hipSuccess) return fail_hip(ctx, e);
+      if ((e = hipEventElapsedTime(&a, ctx->tev[4 * k], ctx->tev[4 * k + 1])) != hipSuccess) return fail_hip(ctx, e);
+      if ((e = hipEventElapsedTime(&b, ctx->tev[4 * k + 2], ctx->tev[4 * k + 3])) != hipSuccess) return fail_hip(ctx, e);
       ctx->t_mom_ms += a;
       ctx->t_for_ms += b;
     }

@@ -89,6 +89,11 @@ struct Phys {
 // Kernel modes of the force kernel.
 enum { MODE_FORCES = 0, MODE_START = 1, MODE_NVE = 2, MODE_NVE_LAST = 3, MODE_KICK = 4 };
 
+// Optional start/stop events recorded at a launch's dispatch.
+struct KTimer {
+  hipEvent_t start = nullptr, stop = nullptr;
+};
+
 // Host launchers (sw_kernels.hip).  Each returns a hipError_t.
 hipError_t launch_sort(const Dev& d, const float4* x_user, const float4* v_user, long long n_user,
                        const long long* uoff, int R, const int* cell_rank, uint4* uq, int* key,
@@ -96,9 +101,9 @@ hipError_t launch_sort(const Dev& d, const float4* x_user, const float4* v_user,
 hipError_t launch_gather_ids(const Dev& d, const float4* x_user, int par, hipStream_t s);
 hipError_t launch_bin(const Dev& d, int par, int check_disp, float half_skin, hipStream_t s);
 hipError_t launch_moments(const Dev& d, const Phys& p, int lpa, int par, int force_rebuild,
-                          int energy, hipStream_t s);
+                          int energy, hipStream_t s, const KTimer& tm = KTimer());
 hipError_t launch_forces(const Dev& d, const Phys& p, int lpa, int mode, int vir, int par,
-                         double* ring_row, hipStream_t s);
+                         double* ring_row, hipStream_t s, const KTimer& tm = KTimer());
 hipError_t launch_thermostat(const Dev& d, const Phys& p, int par, int last, hipStream_t s);
 hipError_t launch_scatter_out(const Dev& d, int par, float4* x_user, float4* v_user,
                               float4* f_user, hipStream_t s);

@@ -23,6 +23,8 @@
 
 #include "sw_internal.h"
 
+#include <hip/hip_ext.h>
+
 namespace swk {
 namespace {
 
@@ -631,35 +633,48 @@ __global__ void k_fill_f32(float* p, float value, long long n) {
 
 inline unsigned nblk(long long n, int b) { return (unsigned)((n + b - 1) / b); }
 
+// Launches go through hipExtLaunchKernelGGL so that sampled launches can
+// carry start/stop events recorded at the dispatch itself.
 template <int LPA>
-hipError_t moments_lpa(const Dev& d, const Phys& p, int par, int force_rebuild, int energy, hipStream_t s) {
+hipError_t moments_lpa(const Dev& d, const Phys& p, int par, int force_rebuild, int energy, hipStream_t s,
+                       const KTimer& tm) {
   constexpr int APB = kBlock / LPA;
-  const size_t lds = sizeof(int) * (2 * (size_t)APB * d.cap + APB + 56 * (size_t)APB);
+  const uint32_t lds = (uint32_t)(sizeof(int) * (2 * (size_t)APB * d.cap + APB + 56 * (size_t)APB));
   const unsigned grid = (unsigned)(d.npad / APB);
-  if (energy) hipLaunchKernelGGL((k_moments<LPA, true>), dim3(grid), dim3(kBlock), lds, s, d, p, par, force_rebuild);
-  else hipLaunchKernelGGL((k_moments<LPA, false>), dim3(grid), dim3(kBlock), lds, s, d, p, par, force_rebuild);
+  if (energy)
+    hipExtLaunchKernelGGL((k_moments<LPA, true>), dim3(grid), dim3(kBlock), lds, s, tm.start, tm.stop, 0u, d, p,
+                          par, force_rebuild);
+  else
+    hipExtLaunchKernelGGL((k_moments<LPA, false>), dim3(grid), dim3(kBlock), lds, s, tm.start, tm.stop, 0u, d, p,
+                          par, force_rebuild);
   return hipGetLastError();
 }
 
 template <int LPA, int MODE>
-hipError_t forces_mode(const Dev& d, const Phys& p, int vir, int par, double* ring_row, hipStream_t s) {
+hipError_t forces_mode(const Dev& d, const Phys& p, int vir, int par, double* ring_row, hipStream_t s,
+                       const KTimer& tm) {
   constexpr int APB = kBlock / LPA;
   const unsigned grid = (unsigned)(d.npad / APB);
-  if (vir) hipLaunchKernelGGL((k_forces<LPA, MODE, true>), dim3(grid), dim3(kBlock), 0, s, d, p, par);
-  else hipLaunchKernelGGL((k_forces<LPA, MODE, false>), dim3(grid), dim3(kBlock), 0, s, d, p, par);
+  if (vir)
+    hipExtLaunchKernelGGL((k_forces<LPA, MODE, true>), dim3(grid), dim3(kBlock), 0u, s, tm.start, tm.stop, 0u, d, p,
+                          par);
+  else
+    hipExtLaunchKernelGGL((k_forces<LPA, MODE, false>), dim3(grid), dim3(kBlock), 0u, s, tm.start, tm.stop, 0u, d,
+                          p, par);
   if (vir || MODE == MODE_KICK)
     hipLaunchKernelGGL(k_reduce_thermo, dim3((unsigned)min(d.R * kNQ, 4096)), dim3(kBlock), 0, s, d, APB, ring_row);
   return hipGetLastError();
 }
 
 template <int LPA>
-hipError_t forces_lpa(const Dev& d, const Phys& p, int mode, int vir, int par, double* ring_row, hipStream_t s) {
+hipError_t forces_lpa(const Dev& d, const Phys& p, int mode, int vir, int par, double* ring_row, hipStream_t s,
+                      const KTimer& tm) {
   switch (mode) {
-    case MODE_FORCES: return forces_mode<LPA, MODE_FORCES>(d, p, 1, par, ring_row, s);
-    case MODE_START: return forces_mode<LPA, MODE_START>(d, p, 0, par, ring_row, s);
-    case MODE_NVE: return forces_mode<LPA, MODE_NVE>(d, p, vir, par, ring_row, s);
-    case MODE_NVE_LAST: return forces_mode<LPA, MODE_NVE_LAST>(d, p, vir, par, ring_row, s);
-    case MODE_KICK: return forces_mode<LPA, MODE_KICK>(d, p, vir, par, ring_row, s);
+    case MODE_FORCES: return forces_mode<LPA, MODE_FORCES>(d, p, 1, par, ring_row, s, tm);
+    case MODE_START: return forces_mode<LPA, MODE_START>(d, p, 0, par, ring_row, s, tm);
+    case MODE_NVE: return forces_mode<LPA, MODE_NVE>(d, p, vir, par, ring_row, s, tm);
+    case MODE_NVE_LAST: return forces_mode<LPA, MODE_NVE_LAST>(d, p, vir, par, ring_row, s, tm);
+    case MODE_KICK: return forces_mode<LPA, MODE_KICK>(d, p, vir, par, ring_row, s, tm);
   }
   return hipErrorInvalidValue;
 }
@@ -693,21 +708,21 @@ hipError_t launch_bin(const Dev& d, int par, int check_disp, float half_skin, hi
 }
 
 hipError_t launch_moments(const Dev& d, const Phys& p, int lpa, int par, int force_rebuild, int energy,
-                          hipStream_t s) {
+                          hipStream_t s, const KTimer& tm) {
   switch (lpa) {
-    case 4: return moments_lpa<4>(d, p, par, force_rebuild, energy, s);
-    case 8: return moments_lpa<8>(d, p, par, force_rebuild, energy, s);
-    case 16: return moments_lpa<16>(d, p, par, force_rebuild, energy, s);
+    case 4: return moments_lpa<4>(d, p, par, force_rebuild, energy, s, tm);
+    case 8: return moments_lpa<8>(d, p, par, force_rebuild, energy, s, tm);
+    case 16: return moments_lpa<16>(d, p, par, force_rebuild, energy, s, tm);
   }
   return hipErrorInvalidValue;
 }
 
 hipError_t launch_forces(const Dev& d, const Phys& p, int lpa, int mode, int vir, int par, double* ring_row,
-                         hipStream_t s) {
+                         hipStream_t s, const KTimer& tm) {
   switch (lpa) {
-    case 4: return forces_lpa<4>(d, p, mode, vir, par, ring_row, s);
-    case 8: return forces_lpa<8>(d, p, mode, vir, par, ring_row, s);
-    case 16: return forces_lpa<16>(d, p, mode, vir, par, ring_row, s);
+    case 4: return forces_lpa<4>(d, p, mode, vir, par, ring_row, s, tm);
+    case 8: return forces_lpa<8>(d, p, mode, vir, par, ring_row, s, tm);
+    case 16: return forces_lpa<16>(d, p, mode, vir, par, ring_row, s, tm);
   }
   return hipErrorInvalidValue;
 }
