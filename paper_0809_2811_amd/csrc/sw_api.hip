@@ -4,7 +4,7 @@
 // memory, checks arguments and enqueues launches.
 
 #include "sw.h"
-#include "sw_internal.h"
+#include "sw_ctx.h"
 
 #include <algorithm>
 #include <cmath>
@@ -14,39 +14,7 @@
 
 using namespace swk;
 
-struct sw_ctx {
-  int R = 0;
-  long long N = 0;
-  int npad = 0;
-  std::vector<long long> uoff;
-  std::vector<double> box;
-  double cutoff = 0.0, skin = 0.0;
-  int cap = 0, cc = 32;
-  std::vector<RepInfo> reps;
-  int ctot = 0;
-  std::vector<int> tile_rep, cell_rank;
-  sw_tuning tune{8, 0, 0, 0, 0};
-  std::vector<hipEvent_t> tev;     // sampled launch timing: 4 events per sample
-  double t_mom_ms = 0.0, t_for_ms = 0.0;
-  long long t_samples = 0;
-  Dev d{};
-  RepInfo* d_reps = nullptr;
-  int* d_tile_rep = nullptr;
-  long long* d_uoff = nullptr;
-  int* d_cell_rank = nullptr;
-  double* d_T0 = nullptr;
-  uint4* d_uq = nullptr;
-  int *d_key = nullptr, *d_scnt = nullptr, *d_sstart = nullptr, *d_scur = nullptr, *d_order = nullptr;
-  Tan t{};
-  bool have_order = false;
-  long long steps = 0;
-  int last_hip = 0;
-  size_t bytes = 0;
-  std::vector<void*> allocs;       // everything freed by free_all
-  std::vector<void*> grow_allocs;  // capacity-dependent buffers
-};
-
-namespace {
+namespace swh {
 
 constexpr int kMaxCap = 512;
 constexpr double kLog2e = 1.4426950408889634;
@@ -123,6 +91,7 @@ hipError_t alloc_all(sw_ctx* c) {
   SWA(c->d_scnt, (size_t)c->ctot); SWA(c->d_sstart, (size_t)c->ctot); SWA(c->d_scur, (size_t)c->ctot);
   SWA(c->t.w, np); SWA(c->t.mdot, 3 * np); SWA(c->t.fdot, np); SWA(c->t.f3, np);
   SWA(c->t.tpartial, (np / 16 + 1) * kTQ);
+  SWA(c->t.tsum, (size_t)c->R * kTQ);
 #undef SWA
   if ((e = alloc_capacity(c)) != hipSuccess) return e;
   c->d.reps = c->d_reps;
@@ -182,8 +151,6 @@ hipError_t reset_flags(sw_ctx* c, hipStream_t s) {
   return launch_fill_i32(c->d.dflag, 0, 2 * c->R, s);
 }
 
-struct Flags { int nbr_over, nbr_need, cell_over, overlap; };
-
 hipError_t read_flags(sw_ctx* c, hipStream_t s, Flags* f) {
   int h[F_NFLAGS];
   hipError_t e = hipMemcpyAsync(h, c->d.flags, sizeof h, hipMemcpyDeviceToHost, s);
@@ -232,7 +199,9 @@ hipError_t sort_in(sw_ctx* c, const float* x, const float* v, hipStream_t s) {
 
 bool valid_ptr(const void* p) { return p != nullptr; }
 
-}  // namespace
+}  // namespace swh
+
+using namespace swh;
 
 extern "C" {
 

@@ -1,0 +1,56 @@
+// Host-side context of libsw, shared by sw_api.hip and sw_tangent.hip.
+#pragma once
+#include "sw.h"
+#include "sw_internal.h"
+
+#include <vector>
+
+using swk::RepInfo;
+using swk::Dev;
+using swk::Tan;
+
+struct sw_ctx {
+  int R = 0;
+  long long N = 0;
+  int npad = 0;
+  std::vector<long long> uoff;
+  std::vector<double> box;
+  double cutoff = 0.0, skin = 0.0;
+  int cap = 0, cc = 32;
+  std::vector<RepInfo> reps;
+  int ctot = 0;
+  std::vector<int> tile_rep, cell_rank;
+  sw_tuning tune{8, 0, 0, 0, 0};
+  std::vector<hipEvent_t> tev;     // sampled launch timing: 4 events per sample
+  double t_mom_ms = 0.0, t_for_ms = 0.0;
+  long long t_samples = 0;
+  Dev d{};
+  RepInfo* d_reps = nullptr;
+  int* d_tile_rep = nullptr;
+  long long* d_uoff = nullptr;
+  int* d_cell_rank = nullptr;
+  double* d_T0 = nullptr;
+  uint4* d_uq = nullptr;
+  int *d_key = nullptr, *d_scnt = nullptr, *d_sstart = nullptr, *d_scur = nullptr, *d_order = nullptr;
+  Tan t{};
+  bool have_order = false;
+  long long steps = 0;
+  int last_hip = 0;
+  size_t bytes = 0;
+  std::vector<void*> allocs;       // everything freed by free_all
+  std::vector<void*> grow_allocs;  // capacity-dependent buffers
+};
+
+
+namespace swh {
+using namespace swk;
+int fail_hip(sw_ctx* c, hipError_t e);
+int lpa_for(const sw_ctx* c);
+int make_phys(const sw_ctx* c, const sw_params* P, double mass, double dt, Phys* o);
+hipError_t reset_flags(sw_ctx* c, hipStream_t s);
+struct Flags { int nbr_over, nbr_need, cell_over, overlap; };
+hipError_t read_flags(sw_ctx* c, hipStream_t s, Flags* f);
+int grow(sw_ctx* c, const Flags& f);
+hipError_t sort_in(sw_ctx* c, const float* x, const float* v, hipStream_t s);
+bool valid_ptr(const void* p);
+}  // namespace swh

@@ -112,16 +112,32 @@ hipError_t launch_fill_i32(int* p, int value, long long n, hipStream_t s);
 hipError_t launch_fill_f32(float* p, float value, long long n, hipStream_t s);
 
 // Tangent (forward-mode) kernels for sw_grad / sw_adjoint.
+constexpr int kTQ = 7;  // per replica: E2, E3, W2 trace, W3 trace, w.F, w.F3, d(W trace) along w
 struct Tan {
-  float4* w;        // [Npad] tangent direction (A)
-  float4* mdot;     // [Npad][3] tangent of the moments
-  float4* fdot;     // [Npad] tangent of the forces
-  float4* f3;       // [Npad] three-body part of the forces
-  double* tpartial; // [nblocks][kTQ]
+  float4* w;         // [Npad] tangent direction (A), internal order
+  float4* mdot;      // [Npad][3] tangent of the moments
+  float4* fdot;      // [Npad] tangent of the forces: (dF/dx) w
+  float4* f3;        // [Npad] three-body part of the forces
+  double* tpartial;  // [kTQ][nblocks]
+  double* tsum;      // [R][kTQ]
 };
-constexpr int kTQ = 8;  // E2, E3, W2tr, W3tr, wdotF, wdotF3, wdotWdot(tangent of W trace), pad
-hipError_t launch_tan_moments(const Dev& d, const Tan& t, const Phys& p, int par, hipStream_t s);
-hipError_t launch_tan_forces(const Dev& d, const Tan& t, const Phys& p, int par, double* out_rows,
-                             hipStream_t s);
+// Per-frame adjoint update fused into the tangent force kernel.
+struct Adj {
+  float4* xb;        // [Npad] position adjoint, updated in place
+  float4* vb_next;   // [Npad] next direction vb + dt xb (unused on the last frame)
+  float coef_cm;     // frame weight (dt or dt/2) * 4.184e-4 / mass
+  float dt;
+  float aU, a3;      // loss weights
+  int S;             // trajectory steps (loss normalisation 1 / (n_r (S + 1)))
+  int last;          // last frame: do not form the next direction
+};
+hipError_t launch_tan_moments(const Dev& d, const Tan& t, const Phys& p, int lpa, const float4* w, int par,
+                              hipStream_t s);
+hipError_t launch_tan_forces(const Dev& d, const Tan& t, const Phys& p, int lpa, const float4* w, int par,
+                             const Adj* adj, hipStream_t s);
+hipError_t launch_gather_vec(const Dev& d, const float4* user, float4* internal, hipStream_t s);
+hipError_t launch_scatter_vec(const Dev& d, const float4* internal, float4* user, hipStream_t s);
+hipError_t launch_copy_u(const Dev& d, const uint4* src, uint4* dst, hipStream_t s);
+hipError_t launch_copy_v(const Dev& d, const float4* src, float4* dst, hipStream_t s);
 
 }  // namespace swk

@@ -22,55 +22,12 @@
 // of a difference is its two's-complement value, exact for any box size.
 
 #include "sw_internal.h"
+#include "sw_device.h"
 
 #include <hip/hip_ext.h>
 
 namespace swk {
 namespace {
-
-__device__ __forceinline__ int xcd_remap(int bid, int G) {
-  // Blocks are dealt round-robin to the 8 XCDs; give each XCD a contiguous
-  // range of (spatially sorted) tiles so neighbour gathers share its L2.
-  const int xcd = bid & 7, local = bid >> 3;
-  const int per = G >> 3, rem = G & 7;
-  return xcd * per + min(xcd, rem) + local;
-}
-
-__device__ __forceinline__ float3 disp(const uint4& a, const uint4& b, const float sc0, const float sc1,
-                                       const float sc2) {
-  return make_float3((float)(int)(b.x - a.x) * sc0, (float)(int)(b.y - a.y) * sc1,
-                     (float)(int)(b.z - a.z) * sc2);
-}
-
-__device__ __forceinline__ int cell_of(const uint4& u, const int nc0, const int nc1, const int nc2) {
-  const int cx = (int)__umulhi(u.x, (unsigned)nc0);
-  const int cy = (int)__umulhi(u.y, (unsigned)nc1);
-  const int cz = (int)__umulhi(u.z, (unsigned)nc2);
-  return (cx * nc1 + cy) * nc2 + cz;
-}
-
-__device__ __forceinline__ unsigned quantize(float x, double inv_L) {
-  double fr = (double)x * inv_L;
-  fr -= floor(fr);
-  return (unsigned)(unsigned long long)(fr * kTwo32);  // 2^32 wraps to 0
-}
-
-template <int W>
-__device__ __forceinline__ float group_sum(float v) {
-#pragma unroll
-  for (int m = W / 2; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
-  return v;
-}
-
-__device__ __forceinline__ float wave_max(float v) {
-#pragma unroll
-  for (int m = 32; m >= 1; m >>= 1) v = fmaxf(v, __shfl_xor(v, m, 64));
-  return v;
-}
-
-__device__ __forceinline__ float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
-__device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
-__device__ __forceinline__ float ex2(float x) { return __builtin_amdgcn_exp2f(x); }
 
 // Drift by dt*v in fraction units, bin into grid `gp`, and raise the
 // replica's rebuild flag if the atom is now more than half the skin away from
@@ -671,7 +628,7 @@ hipError_t forces_lpa(const Dev& d, const Phys& p, int mode, int vir, int par, d
                       const KTimer& tm) {
   switch (mode) {
     case MODE_FORCES: return forces_mode<LPA, MODE_FORCES>(d, p, 1, par, ring_row, s, tm);
-    case MODE_START: return forces_mode<LPA, MODE_START>(d, p, 0, par, ring_row, s, tm);
+    case MODE_START: return forces_mode<LPA, MODE_START>(d, p, vir, par, ring_row, s, tm);
     case MODE_NVE: return forces_mode<LPA, MODE_NVE>(d, p, vir, par, ring_row, s, tm);
     case MODE_NVE_LAST: return forces_mode<LPA, MODE_NVE_LAST>(d, p, vir, par, ring_row, s, tm);
     case MODE_KICK: return forces_mode<LPA, MODE_KICK>(d, p, vir, par, ring_row, s, tm);

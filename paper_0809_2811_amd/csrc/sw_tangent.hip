@@ -1,17 +1,618 @@
-// Forward-mode tangent kernels (sw_grad) and the checkpointed discrete adjoint
-// of NVE velocity Verlet (sw_adjoint).
-#include "sw.h"
-#include "sw_internal.h"
+// Forward-mode tangent kernels and the checkpointed discrete adjoint of NVE
+// velocity Verlet.
+//
+// A tangent pass carries (value, derivative) pairs through the same
+// moments/forces arithmetic as the force kernels, with every leg vector
+// moving as d_ij + eps (w_j - w_i).  One pass along w gives:
+//   (dF/dx) w  (= -H w; H is symmetric, so this is also the transposed product),
+//   F, the three-body part F3, the virial traces W2, W3 and their derivative
+//   along w.
+// The parameter derivatives follow from the reduced form of the model
+// (Sec. II.A: E depends on sigma and epsilon only through eps E*(x/sigma)):
+//   dF/deps = F/eps,  dF/dlambda = F3/lambda,  dF/dsigma = -(1/sigma) dW/dx,
+//   dU/deps = U/eps,  dU/dlambda = U3/lambda,  dU/dsigma = W/sigma,
+// with W the virial trace.
+//
+// The adjoint of the velocity-Verlet map (a = 4.184e-4 F / m, J = da/dx):
+//   xb = xbar_S; vb = vbar_S; frame(S, dt/2)
+//   for s = S-1 .. 0:  vb += dt xb;  frame(s, s > 0 ? dt : dt/2)
+//   frame(s, c):  xb += c J(x_s) vb + dl_s/dx_s,  thbar += c vb . da/dtheta + dl_s/dtheta
+// One tangent pass along vb at x_s gives every term of a frame.  Positions
+// are recomputed per checkpoint segment; a segment always starts with a fresh
+// row build and force pass and ends on a full-step velocity, so the recompute
+// repeats the forward kernels exactly.
+#include "sw_ctx.h"
+#include "sw_device.h"
+
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+namespace swk {
+namespace {
+
+struct D {
+  float v, d;
+};
+__device__ __forceinline__ D operator+(D a, D b) { return {a.v + b.v, a.d + b.d}; }
+__device__ __forceinline__ D operator-(D a, D b) { return {a.v - b.v, a.d - b.d}; }
+__device__ __forceinline__ D operator*(D a, D b) { return {a.v * b.v, a.d * b.v + a.v * b.d}; }
+__device__ __forceinline__ D operator*(float s, D a) { return {s * a.v, s * a.d}; }
+__device__ __forceinline__ D operator+(D a, float s) { return {a.v + s, a.d}; }
+__device__ __forceinline__ D operator-(D a, float s) { return {a.v - s, a.d}; }
+__device__ __forceinline__ D neg(D a) { return {-a.v, -a.d}; }
+__device__ __forceinline__ D rsqD(D a) {
+  const float r = rsq(a.v);
+  return {r, -0.5f * r * r * r * a.d};
+}
+__device__ __forceinline__ D rcpD(D a) {
+  const float r = rcp(a.v);
+  return {r, -r * r * a.d};
+}
+__device__ __forceinline__ D ex2D(D a) {
+  const float e = ex2(a.v);
+  return {e, e * 0.69314718055994531f * a.d};
+}
+
+struct Geo {
+  D ux, uy, uz, r, ir, idr, eg;
+};
+
+// Leg geometry of one neighbour as dual numbers.
+__device__ __forceinline__ Geo geometry(const float3& dd, const float3& dt, const Phys& p) {
+  const D dx{dd.x, dt.x}, dy{dd.y, dt.y}, dz{dd.z, dt.z};
+  const D r2 = dx * dx + dy * dy + dz * dz;
+  Geo G;
+  G.ir = rsqD(r2);
+  G.r = r2 * G.ir;
+  G.ux = dx * G.ir; G.uy = dy * G.ir; G.uz = dz * G.ir;
+  G.idr = rcpD(G.r - p.rc);
+  G.eg = ex2D(p.gsig_l2e * G.idr);
+  return G;
+}
+
+__device__ __forceinline__ float3 sub3(const float4& a, const float4& b) {
+  return make_float3(a.x - b.x, a.y - b.y, a.z - b.z);
+}
+
+// Tangent of the per-centre moments T, V, S along w.
+template <int LPA>
+__global__ __launch_bounds__(kBlock) void k_tan_moments(Dev d, Tan t, Phys p, const float4* __restrict__ w,
+                                                        int par) {
+  constexpr int APB = kBlock / LPA;
+  const int bid = xcd_remap(blockIdx.x, gridDim.x);
+  const int g = threadIdx.x / LPA, lane = threadIdx.x % LPA;
+  const int i = bid * APB + g;
+  const RepInfo& R = d.reps[d.tile_rep[(bid * APB) >> 6]];
+  const bool real = i < R.iend;
+  const uint4 ui = d.u[par][i];
+  const float4 wi = w[i];
+  const int nn = real ? d.nn[i] : 0;
+  const int* row = d.nl + (size_t)i * d.cap;
+  float T0 = 0.f, T1 = 0.f, T2 = 0.f, T3 = 0.f, T4 = 0.f, T5 = 0.f, V0 = 0.f, V1 = 0.f, V2 = 0.f, S = 0.f;
+  for (int s = lane; s < nn; s += LPA) {
+    const int j = row[s];
+    const float3 dd = disp(ui, d.u[par][j], R.scale[0], R.scale[1], R.scale[2]);
+    if (dd.x * dd.x + dd.y * dd.y + dd.z * dd.z < p.rc2) {
+      const Geo G = geometry(dd, sub3(w[j], wi), p);
+      const D ex = G.eg * G.ux, ey = G.eg * G.uy, ez = G.eg * G.uz;
+      T0 += (ex * G.ux).d; T1 += (ey * G.uy).d; T2 += (ez * G.uz).d;
+      T3 += (ex * G.uy).d; T4 += (ex * G.uz).d; T5 += (ey * G.uz).d;
+      V0 += ex.d; V1 += ey.d; V2 += ez.d; S += G.eg.d;
+    }
+  }
+  T0 = group_sum<LPA>(T0); T1 = group_sum<LPA>(T1); T2 = group_sum<LPA>(T2);
+  T3 = group_sum<LPA>(T3); T4 = group_sum<LPA>(T4); T5 = group_sum<LPA>(T5);
+  V0 = group_sum<LPA>(V0); V1 = group_sum<LPA>(V1); V2 = group_sum<LPA>(V2);
+  S = group_sum<LPA>(S);
+  if (real && lane == 0) {
+    float4* m = t.mdot + 3 * (size_t)i;
+    m[0] = make_float4(T0, T1, T2, T3);
+    m[1] = make_float4(T4, T5, V0, V1);
+    m[2] = make_float4(V2, S, 0.f, 0.f);
+  }
+}
+
+// Forces and their tangent along w, virial traces and their tangent; with
+// ADJ the per-atom adjoint update of one frame.
+template <int LPA, bool ADJ>
+__global__ __launch_bounds__(kBlock) void k_tan_forces(Dev d, Tan t, Phys p, const float4* __restrict__ w, int par,
+                                                       Adj a) {
+  constexpr int APB = kBlock / LPA;
+  __shared__ double red[APB * kTQ];
+  const int bid = xcd_remap(blockIdx.x, gridDim.x);
+  const int g = threadIdx.x / LPA, lane = threadIdx.x % LPA;
+  const int i = bid * APB + g;
+  const RepInfo& R = d.reps[d.tile_rep[(bid * APB) >> 6]];
+  const bool real = i < R.iend;
+  const uint4 ui = d.u[par][i];
+  const float4 wi = w[i];
+  const float c0 = p.c0, c02 = p.c0 * p.c0;
+  D Tm[6], Vm[3], Sm{0.f, 0.f};
+  float E2i = 0.f, E3i = 0.f;
+  for (int k = 0; k < 6; ++k) Tm[k] = D{0.f, 0.f};
+  for (int k = 0; k < 3; ++k) Vm[k] = D{0.f, 0.f};
+  int nn = 0;
+  if (real) {
+    const float4* m = d.mom + 3 * (size_t)i;
+    const float4* md = t.mdot + 3 * (size_t)i;
+    const float4 a0 = m[0], a1 = m[1], a2 = m[2], b0 = md[0], b1 = md[1], b2 = md[2];
+    Tm[0] = {a0.x, b0.x}; Tm[1] = {a0.y, b0.y}; Tm[2] = {a0.z, b0.z}; Tm[3] = {a0.w, b0.w};
+    Tm[4] = {a1.x, b1.x}; Tm[5] = {a1.y, b1.y}; Vm[0] = {a1.z, b1.z}; Vm[1] = {a1.w, b1.w};
+    Vm[2] = {a2.x, b2.x}; Sm = {a2.y, b2.y};
+    E2i = a2.z; E3i = a2.w;
+    nn = d.nn[i];
+  }
+  const int* row = d.nl + (size_t)i * d.cap;
+  D fx{0.f, 0.f}, fy{0.f, 0.f}, fz{0.f, 0.f}, w2{0.f, 0.f}, w3{0.f, 0.f};
+  float gx = 0.f, gy = 0.f, gz = 0.f;   // three-body force
+  for (int s = lane; s < nn; s += LPA) {
+    const int j = row[s];
+    const float3 dd = disp(ui, d.u[par][j], R.scale[0], R.scale[1], R.scale[2]);
+    if (dd.x * dd.x + dd.y * dd.y + dd.z * dd.z < p.rc2) {
+      const Geo G = geometry(dd, sub3(w[j], wi), p);
+      const D idr2 = G.idr * G.idr;
+      const D e1 = ex2D(p.sig_l2e * G.idr);
+      const D sr = p.sig * G.ir, s2 = sr * sr, s4 = s2 * s2;
+      const D poly = (p.B * s4) - 1.f;
+      const D dphi = p.Aeps * (e1 * ((-4.f * p.B) * (s4 * G.ir) - p.sig * (poly * idr2)));
+      const D gg = (-p.gsig) * idr2;
+      const float4* mj = d.mom + 3 * (size_t)j;
+      const float4* mdj = t.mdot + 3 * (size_t)j;
+      const float4 na = mj[0], nb = mj[1], nc = mj[2], da = mdj[0], db = mdj[1], dc = mdj[2];
+      const D Ts0 = Tm[0] + D{na.x, da.x}, Ts1 = Tm[1] + D{na.y, da.y}, Ts2 = Tm[2] + D{na.z, da.z};
+      const D Ts3 = Tm[3] + D{na.w, da.w}, Ts4 = Tm[4] + D{nb.x, db.x}, Ts5 = Tm[5] + D{nb.y, db.y};
+      const D Dv0 = Vm[0] - D{nb.z, db.z}, Dv1 = Vm[1] - D{nb.w, db.w}, Dv2 = Vm[2] - D{nc.x, dc.x};
+      const D Ss = Sm + D{nc.y, dc.y};
+      const D y0x = Ts0 * G.ux + Ts3 * G.uy + Ts4 * G.uz;
+      const D y0y = Ts3 * G.ux + Ts1 * G.uy + Ts5 * G.uz;
+      const D y0z = Ts4 * G.ux + Ts5 * G.uy + Ts2 * G.uz;
+      const D uTu = G.ux * y0x + G.uy * y0y + G.uz * y0z;
+      const D uDv = G.ux * Dv0 + G.uy * Dv1 + G.uz * Dv2;
+      const D q = uTu - (2.f * c0) * uDv + c02 * Ss - (2.f * p.qc) * G.eg;
+      const D uy_ = uTu - c0 * uDv;
+      const D px = (y0x - c0 * Dv0) - uy_ * G.ux;
+      const D py = (y0y - c0 * Dv1) - uy_ * G.uy;
+      const D pz = (y0z - c0 * Dv2) - uy_ * G.uz;
+      const D le = p.lameps * G.eg;
+      const D b3 = le * gg * q;
+      const D a2 = 2.f * (le * G.ir);
+      const D a1 = dphi + b3;
+      fx = fx + a1 * G.ux + a2 * px;
+      fy = fy + a1 * G.uy + a2 * py;
+      fz = fz + a1 * G.uz + a2 * pz;
+      gx += b3.v * G.ux.v + a2.v * px.v;
+      gy += b3.v * G.uy.v + a2.v * py.v;
+      gz += b3.v * G.uz.v + a2.v * pz.v;
+      // virial traces: half the pair leg, and the own centre's legs (the
+      // tangential part of a leg force has no trace)
+      const D ymx = Tm[0] * G.ux + Tm[3] * G.uy + Tm[4] * G.uz - c0 * Vm[0];
+      const D ymy = Tm[3] * G.ux + Tm[1] * G.uy + Tm[5] * G.uz - c0 * Vm[1];
+      const D ymz = Tm[4] * G.ux + Tm[5] * G.uy + Tm[2] * G.uz - c0 * Vm[2];
+      const D uym = G.ux * ymx + G.uy * ymy + G.uz * ymz;
+      const D uVm = G.ux * Vm[0] + G.uy * Vm[1] + G.uz * Vm[2];
+      const D qown = uym - c0 * uVm + c02 * Sm - p.qc * G.eg;
+      w2 = w2 - 0.5f * (G.r * dphi);
+      w3 = w3 - le * (G.r * (gg * qown));
+    }
+  }
+  fx.v = group_sum<LPA>(fx.v); fx.d = group_sum<LPA>(fx.d);
+  fy.v = group_sum<LPA>(fy.v); fy.d = group_sum<LPA>(fy.d);
+  fz.v = group_sum<LPA>(fz.v); fz.d = group_sum<LPA>(fz.d);
+  gx = group_sum<LPA>(gx); gy = group_sum<LPA>(gy); gz = group_sum<LPA>(gz);
+  w2.v = group_sum<LPA>(w2.v); w2.d = group_sum<LPA>(w2.d);
+  w3.v = group_sum<LPA>(w3.v); w3.d = group_sum<LPA>(w3.d);
+  if (lane == 0) {
+    double q[kTQ] = {0, 0, 0, 0, 0, 0, 0};
+    if (real) {
+      d.f[i] = make_float4(fx.v, fy.v, fz.v, 0.f);
+      t.fdot[i] = make_float4(fx.d, fy.d, fz.d, 0.f);
+      t.f3[i] = make_float4(gx, gy, gz, 0.f);
+      q[0] = E2i; q[1] = E3i; q[2] = w2.v; q[3] = w3.v;
+      q[4] = (double)wi.x * fx.v + (double)wi.y * fy.v + (double)wi.z * fz.v;
+      q[5] = (double)wi.x * gx + (double)wi.y * gy + (double)wi.z * gz;
+      q[6] = (double)w2.d + (double)w3.d;
+      if (ADJ) {
+        const float norm = (float)(1.0 / ((double)R.n * (a.S + 1)));
+        float4 xb = a.xb[i];
+        xb.x += a.coef_cm * fx.d - (a.aU * fx.v + a.a3 * gx) * norm;
+        xb.y += a.coef_cm * fy.d - (a.aU * fy.v + a.a3 * gy) * norm;
+        xb.z += a.coef_cm * fz.d - (a.aU * fz.v + a.a3 * gz) * norm;
+        xb.w = 0.f;
+        a.xb[i] = xb;
+        if (!a.last)
+          a.vb_next[i] = make_float4(wi.x + a.dt * xb.x, wi.y + a.dt * xb.y, wi.z + a.dt * xb.z, 0.f);
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < kTQ; ++k) red[g * kTQ + k] = q[k];
+  }
+  __syncthreads();
+  if (threadIdx.x < kTQ) {
+    double acc = 0.0;
+    for (int k = 0; k < APB; ++k) acc += red[k * kTQ + threadIdx.x];
+    t.tpartial[(size_t)threadIdx.x * (d.npad / APB) + bid] = acc;
+  }
+}
+
+// Per-replica sums of the tangent partials, one block per (replica, quantity).
+__global__ __launch_bounds__(kBlock) void k_reduce_tan(Dev d, Tan t, int apb) {
+  __shared__ double tree[kBlock];
+  const int nbt = d.npad / apb;
+  for (int task = blockIdx.x; task < d.R * kTQ; task += gridDim.x) {
+    const int rep = task / kTQ, k = task % kTQ;
+    const RepInfo& R = d.reps[rep];
+    const double* src = t.tpartial + (size_t)k * nbt;
+    double acc = 0.0;
+    for (int b = R.ioff / apb + (int)threadIdx.x; b < R.ipad_end / apb; b += kBlock) acc += src[b];
+    tree[threadIdx.x] = acc;
+    __syncthreads();
+    for (int st = kBlock / 2; st > 0; st >>= 1) {
+      if ((int)threadIdx.x < st) tree[threadIdx.x] += tree[threadIdx.x + st];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) t.tsum[rep * kTQ + k] = tree[0];
+    __syncthreads();
+  }
+}
+
+// sw_grad outputs, or the per-frame parameter adjoint (frame weight coef_cm,
+// loss weights aU, a3 with the 1/(n (S+1)) normalisation).
+__global__ void k_param_terms(Tan t, int R, const RepInfo* reps, double lam, double eps, double sig, double* wdF,
+                              double* dU, double* thbar, double coef_cm, double aU, double a3, int S) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= R) return;
+  const double* q = t.tsum + r * kTQ;
+  const double E2 = q[0], E3 = q[1], W2 = q[2], W3 = q[3], wF = q[4], wF3 = q[5], Wd = q[6];
+  const double g[3] = {wF3 / lam, wF / eps, -Wd / sig};   // w . dF/d(lambda, eps, sigma)
+  const double u[3] = {E3 / lam, (E2 + E3) / eps, (W2 + W3) / sig};
+  const double u3[3] = {E3 / lam, E3 / eps, W3 / sig};
+  if (wdF) for (int k = 0; k < 3; ++k) wdF[3 * r + k] = g[k];
+  if (dU) for (int k = 0; k < 3; ++k) dU[3 * r + k] = u[k];
+  if (thbar) {
+    const double norm = 1.0 / ((double)reps[r].n * (S + 1));
+    for (int k = 0; k < 3; ++k) thbar[3 * r + k] += coef_cm * g[k] + norm * (aU * u[k] + a3 * u3[k]);
+  }
+}
+
+// Frame loss from recorded thermo rows [S+1][R][kNQ].
+__global__ void k_loss(const double* th, int S, int R, const RepInfo* reps, double aU, double a3, double* loss) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= R) return;
+  double acc = 0.0;
+  for (int s = 0; s <= S; ++s) {
+    const double* row = th + ((size_t)s * R + r) * kNQ;
+    acc += aU * (row[0] + row[1]) + a3 * row[1];
+  }
+  loss[r] = acc / ((double)reps[r].n * (S + 1));
+}
+
+__global__ void k_gather_vec(Dev d, const float4* __restrict__ user, float4* __restrict__ internal) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= d.npad) return;
+  const int k = d.ids[i];
+  float4 a = k >= 0 && user ? user[k] : make_float4(0.f, 0.f, 0.f, 0.f);
+  a.w = 0.f;
+  internal[i] = a;
+}
+
+__global__ void k_scatter_vec(Dev d, const float4* __restrict__ internal, float4* __restrict__ user) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= d.npad) return;
+  const int k = d.ids[i];
+  if (k < 0) return;
+  float4 a = internal[i];
+  a.w = 0.f;
+  user[k] = a;
+}
+
+template <class T>
+__global__ void k_copy(const T* __restrict__ src, T* __restrict__ dst, int n) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i < n) dst[i] = src[i];
+}
+
+inline unsigned nb(long long n) { return (unsigned)((n + kBlock - 1) / kBlock); }
+
+template <int LPA>
+hipError_t tan_launch(const Dev& d, const Tan& t, const Phys& p, const float4* w, int par, const Adj* adj,
+                      hipStream_t s, bool moments) {
+  constexpr int APB = kBlock / LPA;
+  const unsigned grid = (unsigned)(d.npad / APB);
+  if (moments) {
+    hipLaunchKernelGGL((k_tan_moments<LPA>), dim3(grid), dim3(kBlock), 0, s, d, t, p, w, par);
+  } else {
+    Adj a = adj ? *adj : Adj{};
+    if (adj) hipLaunchKernelGGL((k_tan_forces<LPA, true>), dim3(grid), dim3(kBlock), 0, s, d, t, p, w, par, a);
+    else hipLaunchKernelGGL((k_tan_forces<LPA, false>), dim3(grid), dim3(kBlock), 0, s, d, t, p, w, par, a);
+    hipLaunchKernelGGL(k_reduce_tan, dim3((unsigned)std::min(d.R * kTQ, 4096)), dim3(kBlock), 0, s, d, t, APB);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_tan_moments(const Dev& d, const Tan& t, const Phys& p, int lpa, const float4* w, int par,
+                              hipStream_t s) {
+  switch (lpa) {
+    case 4: return tan_launch<4>(d, t, p, w, par, nullptr, s, true);
+    case 8: return tan_launch<8>(d, t, p, w, par, nullptr, s, true);
+    case 16: return tan_launch<16>(d, t, p, w, par, nullptr, s, true);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_tan_forces(const Dev& d, const Tan& t, const Phys& p, int lpa, const float4* w, int par,
+                             const Adj* adj, hipStream_t s) {
+  switch (lpa) {
+    case 4: return tan_launch<4>(d, t, p, w, par, adj, s, false);
+    case 8: return tan_launch<8>(d, t, p, w, par, adj, s, false);
+    case 16: return tan_launch<16>(d, t, p, w, par, adj, s, false);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_gather_vec(const Dev& d, const float4* user, float4* internal, hipStream_t s) {
+  hipLaunchKernelGGL(k_gather_vec, dim3(nb(d.npad)), dim3(kBlock), 0, s, d, user, internal);
+  return hipGetLastError();
+}
+
+hipError_t launch_scatter_vec(const Dev& d, const float4* internal, float4* user, hipStream_t s) {
+  hipLaunchKernelGGL(k_scatter_vec, dim3(nb(d.npad)), dim3(kBlock), 0, s, d, internal, user);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy_u(const Dev& d, const uint4* src, uint4* dst, hipStream_t s) {
+  hipLaunchKernelGGL((k_copy<uint4>), dim3(nb(d.npad)), dim3(kBlock), 0, s, src, dst, d.npad);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy_v(const Dev& d, const float4* src, float4* dst, hipStream_t s) {
+  hipLaunchKernelGGL((k_copy<float4>), dim3(nb(d.npad)), dim3(kBlock), 0, s, src, dst, d.npad);
+  return hipGetLastError();
+}
+
+}  // namespace swk
+
+using namespace swk;
+using namespace swh;
+
+namespace {
+
+// Device buffers of one sw_adjoint call.
+struct AdjBuffers {
+  std::vector<void*> list;
+  template <class T>
+  hipError_t get(T** p, size_t n) {
+    hipError_t e = hipMalloc((void**)p, std::max<size_t>(n, 1) * sizeof(T));
+    if (e == hipSuccess) list.push_back((void*)*p);
+    return e;
+  }
+  ~AdjBuffers() {
+    for (void* p : list) (void)hipFree(p);
+  }
+};
+
+// Positions x_c (in u[0]), full-step velocities and the rows in force at
+// x_c -> len steps of NVE velocity Verlet.  The first segment of a
+// trajectory builds its rows; later segments continue with the rows they
+// inherit, so the step sequence, and every rebuild decision, is the same for
+// any checkpoint interval.  Ends on the full-step velocity.  If th is given,
+// rows c..c+len of the thermo table get E2, E3, ... of every frame.  If seg
+// is given, seg[k] receives the positions of frame c+k.  Leaves the end
+// positions in u[0].
+hipError_t run_segment(sw_ctx* c, const Phys& ph, int lpa, int len, bool first, double* th, uint4* seg,
+                       hipStream_t s) {
+  const Dev& d = c->d;
+  const size_t rowsz = (size_t)c->R * kNQ;
+  const int rec = th != nullptr;
+  hipError_t e;
+  if ((e = launch_fill_i32(d.gcnt[0], 0, c->ctot, s)) != hipSuccess) return e;
+  if ((e = launch_fill_i32(d.dflag, 0, 2 * c->R, s)) != hipSuccess) return e;
+  if ((e = launch_bin(d, 0, 0, 0.f, s)) != hipSuccess) return e;
+  if ((e = launch_moments(d, ph, lpa, 0, first ? 1 : 0, rec, s)) != hipSuccess) return e;
+  if (seg && (e = launch_copy_u(d, d.u[0], seg, s)) != hipSuccess) return e;
+  if (len == 0) return launch_forces(d, ph, lpa, MODE_FORCES, 1, 0, th, s);
+  if ((e = launch_forces(d, ph, lpa, MODE_START, rec, 0, th, s)) != hipSuccess) return e;
+  for (int t = 1; t <= len; ++t) {
+    const int par = t & 1;
+    if ((e = launch_moments(d, ph, lpa, par, 0, rec, s)) != hipSuccess) return e;
+    if (seg && (e = launch_copy_u(d, d.u[par], seg + (size_t)t * d.npad, s)) != hipSuccess) return e;
+    const int mode = t == len ? MODE_NVE_LAST : MODE_NVE;
+    if ((e = launch_forces(d, ph, lpa, mode, rec, par, rec ? th + (size_t)t * rowsz : nullptr, s)) != hipSuccess)
+      return e;
+  }
+  if (len & 1) return launch_copy_u(d, d.u[1], d.u[0], s);
+  return hipSuccess;
+}
+
+// Checkpoint of the integrator state at a segment start: positions,
+// velocities and the row state (rows, lengths, build positions).
+struct Ckpt {
+  uint4* u;
+  float4* v;
+  int* nl;
+  int* nn;
+  uint4* uref;
+};
+
+hipError_t save_ckpt(sw_ctx* c, const Ckpt& k, hipStream_t s) {
+  const size_t np = c->npad;
+  hipError_t e;
+  if ((e = launch_copy_u(c->d, c->d.u[0], k.u, s)) != hipSuccess) return e;
+  if ((e = launch_copy_v(c->d, c->d.v, k.v, s)) != hipSuccess) return e;
+  if ((e = launch_copy_u(c->d, c->d.uref, k.uref, s)) != hipSuccess) return e;
+  if ((e = hipMemcpyAsync(k.nn, c->d.nn, sizeof(int) * np, hipMemcpyDeviceToDevice, s)) != hipSuccess) return e;
+  return hipMemcpyAsync(k.nl, c->d.nl, sizeof(int) * np * c->cap, hipMemcpyDeviceToDevice, s);
+}
+
+hipError_t load_ckpt(sw_ctx* c, const Ckpt& k, hipStream_t s) {
+  const size_t np = c->npad;
+  hipError_t e;
+  if ((e = launch_copy_u(c->d, k.u, c->d.u[0], s)) != hipSuccess) return e;
+  if ((e = launch_copy_v(c->d, k.v, c->d.v, s)) != hipSuccess) return e;
+  if ((e = launch_copy_u(c->d, k.uref, c->d.uref, s)) != hipSuccess) return e;
+  if ((e = hipMemcpyAsync(c->d.nn, k.nn, sizeof(int) * np, hipMemcpyDeviceToDevice, s)) != hipSuccess) return e;
+  return hipMemcpyAsync(c->d.nl, k.nl, sizeof(int) * np * c->cap, hipMemcpyDeviceToDevice, s);
+}
+
+// Tangent pass at positions u[0] along w (rows rebuilt first).
+hipError_t tangent_pass(sw_ctx* c, const Phys& ph, int lpa, const float4* w, const Adj* adj, hipStream_t s,
+                        bool rebuild) {
+  const Dev& d = c->d;
+  hipError_t e;
+  if ((e = launch_fill_i32(d.gcnt[0], 0, c->ctot, s)) != hipSuccess) return e;
+  if ((e = launch_fill_i32(d.dflag, 0, 2 * c->R, s)) != hipSuccess) return e;
+  if ((e = launch_bin(d, 0, rebuild ? 0 : 1, ph.half_skin, s)) != hipSuccess) return e;
+  if ((e = launch_moments(d, ph, lpa, 0, rebuild ? 1 : 0, 1, s)) != hipSuccess) return e;
+  if ((e = launch_tan_moments(d, c->t, ph, lpa, w, 0, s)) != hipSuccess) return e;
+  return launch_tan_forces(d, c->t, ph, lpa, w, 0, adj, s);
+}
+
+}  // namespace
 
 extern "C" {
 
-int sw_grad(sw_ctx*, const float*, const float*, const sw_params*, float*, double*, double*, void*) {
-  return SW_EUNSUPPORTED;
+int sw_grad(sw_ctx* ctx, const float* x, const float* w, const sw_params* params, float* hvp, double* wdF,
+            double* dU, void* stream) {
+  if (!ctx || !x || !w || !hvp) return SW_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  Phys ph;
+  int st = make_phys(ctx, params, 1.0, 1.0, &ph);
+  if (st != SW_OK) return st;
+  const int lpa = lpa_for(ctx);
+  for (int attempt = 0; attempt < 6; ++attempt) {
+    hipError_t e;
+    if ((e = reset_flags(ctx, s)) != hipSuccess) return fail_hip(ctx, e);
+    bool rebuild = false;
+    if (!ctx->have_order) {
+      if ((e = sort_in(ctx, x, nullptr, s)) != hipSuccess) return fail_hip(ctx, e);
+      rebuild = true;
+    } else if ((e = launch_gather_ids(ctx->d, (const float4*)x, 0, s)) != hipSuccess) {
+      return fail_hip(ctx, e);
+    }
+    if ((e = launch_gather_vec(ctx->d, (const float4*)w, ctx->t.w, s)) != hipSuccess) return fail_hip(ctx, e);
+    if ((e = tangent_pass(ctx, ph, lpa, ctx->t.w, nullptr, s, rebuild)) != hipSuccess) return fail_hip(ctx, e);
+    Flags fl;
+    if ((e = read_flags(ctx, s, &fl)) != hipSuccess) return fail_hip(ctx, e);
+    if (fl.nbr_over || fl.cell_over) {
+      if ((st = grow(ctx, fl)) != SW_OK) return st;
+      continue;
+    }
+    if ((e = launch_scatter_vec(ctx->d, ctx->t.fdot, (float4*)hvp, s)) != hipSuccess) return fail_hip(ctx, e);
+    if (wdF || dU) {
+      hipLaunchKernelGGL(k_param_terms, dim3((ctx->R + 63) / 64), dim3(64), 0, s, ctx->t, ctx->R, ctx->d_reps,
+                         params->lambda, params->epsilon, params->sigma, wdF, dU, (double*)nullptr, 0.0, 0.0, 0.0,
+                         0);
+      if ((e = hipGetLastError()) != hipSuccess) return fail_hip(ctx, e);
+    }
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) return fail_hip(ctx, e);
+    return fl.overlap ? SW_EOVERLAP : SW_OK;
+  }
+  return SW_ENBR_OVERFLOW;
 }
 
-int sw_adjoint(sw_ctx*, const float*, const float*, const sw_params*, double, double, int, int, double,
-               double, const float*, const float*, double*, float*, float*, double*, float*, float*, void*) {
-  return SW_EUNSUPPORTED;
+int sw_adjoint(sw_ctx* ctx, const float* x0, const float* v0, const sw_params* params, double mass, double dt,
+               int nsteps, int ckpt_every, double aU, double a3, const float* xbar_S, const float* vbar_S,
+               double* loss, float* xbar0, float* vbar0, double* thbar, float* xS, float* vS, void* stream) {
+  if (!ctx || !x0 || !v0 || !loss || !xbar0 || !vbar0 || !thbar) return SW_EINVAL;
+  if (!(mass > 0.0) || !(dt > 0.0) || nsteps < 0 || ckpt_every <= 0 || !std::isfinite(aU) || !std::isfinite(a3))
+    return SW_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  Phys ph;
+  int st = make_phys(ctx, params, mass, dt, &ph);
+  if (st != SW_OK) return st;
+  const int lpa = lpa_for(ctx);
+  const int S = nsteps, K = ckpt_every;
+  const int nseg = S == 0 ? 1 : (S + K - 1) / K;
+  const size_t np = ctx->npad;
+  const double c_m = kAcc / mass;
+  for (int attempt = 0; attempt < 6; ++attempt) {
+    AdjBuffers B;
+    uint4 *ck_u = nullptr, *ck_uref = nullptr, *seg = nullptr;
+    float4 *ck_v = nullptr, *xb = nullptr, *vb[2] = {nullptr, nullptr};
+    int *ck_nl = nullptr, *ck_nn = nullptr;
+    double *th = nullptr, *thb = nullptr;
+    hipError_t e;
+    if ((e = B.get(&ck_u, np * nseg)) != hipSuccess || (e = B.get(&ck_v, np * nseg)) != hipSuccess ||
+        (e = B.get(&ck_uref, np * nseg)) != hipSuccess || (e = B.get(&ck_nn, np * nseg)) != hipSuccess ||
+        (e = B.get(&ck_nl, np * ctx->cap * nseg)) != hipSuccess ||
+        (e = B.get(&seg, np * (K + 1))) != hipSuccess || (e = B.get(&xb, np)) != hipSuccess ||
+        (e = B.get(&vb[0], np)) != hipSuccess || (e = B.get(&vb[1], np)) != hipSuccess ||
+        (e = B.get(&th, (size_t)(S + 1) * ctx->R * kNQ)) != hipSuccess ||
+        (e = B.get(&thb, (size_t)ctx->R * 3)) != hipSuccess)
+      return e == hipErrorOutOfMemory ? SW_ENOMEM : fail_hip(ctx, e);
+    if ((e = reset_flags(ctx, s)) != hipSuccess) return fail_hip(ctx, e);
+    if ((e = sort_in(ctx, x0, v0, s)) != hipSuccess) return fail_hip(ctx, e);
+    // forward, with checkpoints of (x, v) at every segment start
+    auto ckpt = [&](int j) {
+      return Ckpt{ck_u + (size_t)j * np, ck_v + (size_t)j * np, ck_nl + (size_t)j * np * ctx->cap,
+                  ck_nn + (size_t)j * np, ck_uref + (size_t)j * np};
+    };
+    for (int j = 0; j < nseg; ++j) {
+      const int c = j * K, len = std::min(K, S - c);
+      if (j > 0 && (e = save_ckpt(ctx, ckpt(j), s)) != hipSuccess) return fail_hip(ctx, e);
+      if (j == 0) {   // rows of the first segment are built by run_segment itself
+        if ((e = launch_copy_u(ctx->d, ctx->d.u[0], ck_u, s)) != hipSuccess) return fail_hip(ctx, e);
+        if ((e = launch_copy_v(ctx->d, ctx->d.v, ck_v, s)) != hipSuccess) return fail_hip(ctx, e);
+      }
+      if ((e = run_segment(ctx, ph, lpa, len, j == 0, th + (size_t)c * ctx->R * kNQ, nullptr, s)) != hipSuccess)
+        return fail_hip(ctx, e);
+    }
+    Flags fl;
+    if ((e = read_flags(ctx, s, &fl)) != hipSuccess) return fail_hip(ctx, e);
+    if (fl.nbr_over || fl.cell_over) {
+      if ((st = grow(ctx, fl)) != SW_OK) return st;
+      continue;
+    }
+    hipLaunchKernelGGL(k_loss, dim3((ctx->R + 63) / 64), dim3(64), 0, s, th, S, ctx->R, ctx->d_reps, aU, a3, loss);
+    if (xS && (e = launch_scatter_out(ctx->d, 0, (float4*)xS, nullptr, nullptr, s)) != hipSuccess)
+      return fail_hip(ctx, e);
+    if (vS && (e = launch_scatter_out(ctx->d, 0, nullptr, (float4*)vS, nullptr, s)) != hipSuccess)
+      return fail_hip(ctx, e);
+    // reverse sweep
+    int cur = 0;
+    if ((e = launch_gather_vec(ctx->d, (const float4*)xbar_S, xb, s)) != hipSuccess) return fail_hip(ctx, e);
+    if ((e = launch_gather_vec(ctx->d, (const float4*)vbar_S, vb[0], s)) != hipSuccess) return fail_hip(ctx, e);
+    if ((e = hipMemsetAsync(thb, 0, sizeof(double) * 3 * ctx->R, s)) != hipSuccess) return fail_hip(ctx, e);
+    for (int j = nseg - 1; j >= 0; --j) {
+      const int c = j * K, len = std::min(K, S - c);
+      if (j > 0) {
+        if ((e = load_ckpt(ctx, ckpt(j), s)) != hipSuccess) return fail_hip(ctx, e);
+      } else {
+        if ((e = launch_copy_u(ctx->d, ck_u, ctx->d.u[0], s)) != hipSuccess) return fail_hip(ctx, e);
+        if ((e = launch_copy_v(ctx->d, ck_v, ctx->d.v, s)) != hipSuccess) return fail_hip(ctx, e);
+      }
+      // same kernel variants as the forward pass (which recorded energies), so
+      // the recomputed positions are the forward's bit for bit
+      if ((e = run_segment(ctx, ph, lpa, len, j == 0, th + (size_t)c * ctx->R * kNQ, seg, s)) != hipSuccess)
+        return fail_hip(ctx, e);
+      const int s_lo = j == 0 ? 0 : c + 1;
+      for (int sf = c + len; sf >= s_lo; --sf) {
+        if ((e = launch_copy_u(ctx->d, seg + (size_t)(sf - c) * np, ctx->d.u[0], s)) != hipSuccess)
+          return fail_hip(ctx, e);
+        const double coef = (sf == S || sf == 0) ? 0.5 * dt : dt;
+        Adj a{xb, vb[cur ^ 1], (float)(coef * c_m), (float)dt, (float)aU, (float)a3, S, sf == 0};
+        if ((e = tangent_pass(ctx, ph, lpa, vb[cur], &a, s, true)) != hipSuccess) return fail_hip(ctx, e);
+        hipLaunchKernelGGL(k_param_terms, dim3((ctx->R + 63) / 64), dim3(64), 0, s, ctx->t, ctx->R, ctx->d_reps,
+                           params->lambda, params->epsilon, params->sigma, (double*)nullptr, (double*)nullptr, thb,
+                           coef * c_m, aU, a3, S);
+        if (sf > 0) cur ^= 1;
+      }
+    }
+    if ((e = launch_scatter_vec(ctx->d, xb, (float4*)xbar0, s)) != hipSuccess) return fail_hip(ctx, e);
+    if ((e = launch_scatter_vec(ctx->d, vb[cur], (float4*)vbar0, s)) != hipSuccess) return fail_hip(ctx, e);
+    if ((e = hipMemcpyAsync(thbar, thb, sizeof(double) * 3 * ctx->R, hipMemcpyDeviceToDevice, s)) != hipSuccess)
+      return fail_hip(ctx, e);
+    if ((e = read_flags(ctx, s, &fl)) != hipSuccess) return fail_hip(ctx, e);
+    if (fl.nbr_over || fl.cell_over) {
+      if ((st = grow(ctx, fl)) != SW_OK) return st;
+      continue;
+    }
+    ctx->steps += 2 * (long long)S;
+    return fl.overlap ? SW_EOVERLAP : SW_OK;
+  }
+  return SW_ENBR_OVERFLOW;
 }
 
 }  // extern "C"

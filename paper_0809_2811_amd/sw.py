@@ -312,5 +312,19 @@ class Context:
         sw_grad(self.handle, x, w, params, hvp, wdF, dU, R=self.R)
         return hvp, wdF, dU
 
+    def adjoint(self, x0, v0, nsteps: int, dt: float = 10.0, mass: float = 18.015, ckpt_every: int = 20,
+                aU: float = 1.0, a3: float = 1.0, params: Optional[sw_params] = None, xbar_S=None, vbar_S=None):
+        """Loss, dL/dx0, dL/dv0, dL/d(lambda, eps, sigma) and the final state of
+        an NVE trajectory (see sw_adjoint in include/sw.h)."""
+        torch = _torch()
+        params = params_mw() if params is None else params
+        loss = torch.empty(self.R, dtype=torch.float64, device=x0.device)
+        thbar = torch.empty((self.R, 3), dtype=torch.float64, device=x0.device)
+        xbar0, vbar0 = torch.empty_like(x0), torch.empty_like(x0)
+        xS, vS = torch.empty_like(x0), torch.empty_like(x0)
+        sw_adjoint(self.handle, x0, v0, params, mass, dt, nsteps, ckpt_every, aU, a3, xbar_S, vbar_S, loss,
+                   xbar0, vbar0, thbar, xS, vS, R=self.R)
+        return dict(loss=loss, xbar0=xbar0, vbar0=vbar0, thbar=thbar, xS=xS, vS=vS)
+
     def query(self, what: int) -> int:
         return sw_query(self.handle, what)

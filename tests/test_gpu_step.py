@@ -133,3 +133,13 @@ def test_replicas_evolve_independently():
         assert np.array_equal(from_dev(x1), xb[sl])
         assert np.array_equal(from_dev(v1), vb[sl])
         assert np.array_equal(th1.cpu().numpy()[:, 0], th.cpu().numpy()[:, r])
+
+
+def test_thermo_recording_does_not_change_the_trajectory():
+    """Steps that also sum energies and the virial use other kernel variants;
+    the trajectory must not depend on how often thermo rows are recorded."""
+    x, v, L = liquid(1, sigma=0.0)
+    x, v = f32(x), f32(v)
+    a = run_gpu(x, v, L, 30, thermo_every=1)
+    b = run_gpu(x, v, L, 30, thermo_every=0)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
