@@ -139,7 +139,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=500)
     ap.add_argument("--skin", type=float, default=1.0)
     ap.add_argument("--lpa", type=int, default=0, help="lanes per atom (0 = tuned default)")
-    ap.add_argument("--forms", default="large", help="comma list of large,batched,adjoint or none")
+    ap.add_argument("--forms", default="large,batched,adjoint", help="comma list of large,batched,adjoint or none")
     ap.add_argument("--no-cpu", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -176,6 +176,10 @@ def main():
     line["forms"] = {}
     if "large" in forms:
         line["forms"]["large_box"] = bench_large()
+    if "batched" in forms:
+        line["forms"]["batched"] = bench_batched()
+    if "adjoint" in forms:
+        line["forms"]["adjoint"] = bench_adjoint(line["ms_per_step"])
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline()
     print(json.dumps(line), flush=True)
@@ -201,6 +205,85 @@ def bench_large(steps=1000, skin=0.5):
         out["roofline"] = roofline(n, 1.0, skin, res["forces_us"])
         out["roofline"]["moments_us"] = res["moments_us"]
     return out
+
+
+def bench_batched(steps=5000, melt_steps=1000, skin=1.0, sequential_steps=500):
+    """64 uneven replicas (512-8192 atoms, 0.92-1.05 g/cm^3, 200-320 K) in one
+    context: melted together at 400 K (rescale, untimed), then `steps`
+    Berendsen steps (tau 1 ps) at each replica's temperature, thermo every
+    100 steps.  Timed with one launch per phase and with the persistent
+    cooperative kernel; and, for comparison, the replicas one after another
+    through single-replica contexts (plain engine)."""
+    import torch
+    from paper_0809_2811_amd import sw, synth, tune
+    tab = synth.replica_table()
+    off, boxes, T = tab["offsets"], tab["boxes"], tab["temperatures"]
+    n = int(off[-1])
+    base = tune.best(n // len(boxes), 1.0, skin)
+    x0 = torch.from_numpy(synth.to_float4(tab["x"])).cuda()
+    v0 = torch.from_numpy(synth.to_float4(tab["v"])).cuda()
+    ctx = sw.Context(off, boxes, cutoff=RC, skin=skin, nbr_capacity=64, tuning=base)
+    ctx.step(x0, v0, melt_steps, thermostat=sw.SW_RESCALE, T0=[400.0] * len(boxes))
+    out = {"workload": f"batched: {len(boxes)} replicas, {n} atoms total (512-8192 each, 0.92-1.05 g/cm^3), "
+                       f"melted {melt_steps} steps at 400 K, then Berendsen (tau 1 ps) at 200-320 K, dt=10 fs",
+           "n_atoms": n, "n_replicas": len(boxes), "steps": steps, "unit": "atom-steps/s", "skin_A": skin}
+    for name, persistent in (("per_phase", 0), ("persistent", 1)):
+        ctx.set_tuning(persistent=persistent)
+        x, v = x0.clone(), v0.clone()
+        ctx.step(x, v, 50, thermostat=sw.SW_BERENDSEN, T0=T, tau_fs=1000.0)
+        sync()
+        t0 = time.perf_counter()
+        ctx.step(x, v, steps, thermostat=sw.SW_BERENDSEN, T0=T, tau_fs=1000.0, thermo_every=100)
+        sync()
+        dt = time.perf_counter() - t0
+        out[name] = {"value": n * steps / dt, "ms_per_step": dt * 1e3 / steps}
+    ctx.set_tuning(persistent=0)
+    # the same replicas one after another, each in its own context
+    xs, vs = x0.clone(), v0.clone()
+    total = 0.0
+    for r in range(len(boxes)):
+        a, b = int(off[r]), int(off[r + 1])
+        c1 = sw.Context([0, b - a], [boxes[r]], cutoff=RC, skin=skin, nbr_capacity=64,
+                        tuning=tune.best(b - a, 1.0, skin))
+        xr, vr = xs[a:b].contiguous(), vs[a:b].contiguous()
+        c1.step(xr, vr, 20, thermostat=sw.SW_BERENDSEN, T0=[T[r]], tau_fs=1000.0)
+        sync()
+        t0 = time.perf_counter()
+        c1.step(xr, vr, sequential_steps, thermostat=sw.SW_BERENDSEN, T0=[T[r]], tau_fs=1000.0)
+        sync()
+        total += time.perf_counter() - t0
+    out["one_at_a_time"] = {"value": n * sequential_steps / total, "ms_per_step": total * 1e3 / sequential_steps,
+                            "steps": sequential_steps}
+    best = max(out["per_phase"]["value"], out["persistent"]["value"])
+    out["value"] = best
+    out["speedup_vs_one_at_a_time"] = best / out["one_at_a_time"]["value"]
+    return out
+
+
+def bench_adjoint(plain_ms_per_step, steps=200, ckpt=20, skin=1.0):
+    """Differentiable trajectory: 4096-atom 298 K liquid (same preparation as
+    the main line), 200 NVE steps, checkpoints every 20; one call computes
+    the loss, dL/dx0, dL/dv0 and dL/d(lambda, eps, sigma)."""
+    from paper_0809_2811_amd import synth, tune
+    cfg = synth.config(4)
+    n = len(cfg["x"])
+    tuning = tune.best(n, 1.0, skin)
+    ctx, x, v = prepare_liquid(cfg, skin, tuning)
+    ctx.adjoint(x, v, 20, ckpt_every=ckpt)
+    sync()
+    t0 = time.perf_counter()
+    reps = 3
+    for _ in range(reps):
+        res = ctx.adjoint(x, v, steps, ckpt_every=ckpt)
+    sync()
+    dt = (time.perf_counter() - t0) / reps
+    ms = dt * 1e3 / steps
+    th = res["thbar"].cpu().numpy()[0]
+    return {"workload": f"adjoint: {n}-atom 298 K liquid, {steps}-step NVE trajectory, checkpoints every {ckpt}, "
+                        "loss = mean PE/atom + mean three-body energy/atom",
+            "seconds_per_trajectory": dt, "ms_per_step": ms, "value": n * steps / dt, "unit": "atom-steps/s",
+            "ratio_to_plain_step": ms / plain_ms_per_step, "loss": float(res["loss"].cpu()[0]),
+            "dL_dtheta": [float(t) for t in th]}
 
 
 if __name__ == "__main__":

@@ -65,7 +65,8 @@ typedef enum sw_status {
   SW_EHIP = -6,            /* a HIP runtime call failed (see sw_last_hip_error)         */
   SW_ENOMEM = -7,          /* device allocation failed                                 */
   SW_EUNSUPPORTED = -8,    /* parameter or option outside what the kernels implement  */
-  SW_ESTATE = -9           /* call needs state the context does not have              */
+  SW_ESTATE = -9,          /* call needs state the context does not have              */
+  SW_ETIMEOUT = -10        /* a grid barrier of the persistent launch waited too long  */
 } sw_status;
 
 /* Opaque context: replica layout, cell grids, neighbour rows, workspaces. */
@@ -176,7 +177,9 @@ int sw_adjoint(sw_ctx* ctx, const float* x0, const float* v0, const sw_params* p
 typedef struct sw_tuning {
   int lanes_per_atom;   /* 4, 8 or 16 lanes of a wavefront share one atom      */
   int graph_steps;      /* steps per captured hipGraph (0 = plain launches)    */
-  int persistent;       /* 1: sw_step runs as one cooperative persistent launch */
+  int persistent;       /* 0: one launch per phase; 1: sw_step's steps run in one
+                           cooperative persistent launch at full occupancy;
+                           k > 1: the same with at most k blocks per CU         */
   int rebuild_every;    /* also rebuild rows at least this often (0 = only on
                            displacement)                                        */
   int timing;           /* > 0: every timing-th step of sw_step, bracket the

@@ -82,6 +82,7 @@ hipError_t alloc_all(sw_ctx* c) {
   SWA(c->d.arrive, (size_t)c->R);
   SWA(c->d.dflag, 2 * (size_t)c->R);
   SWA(c->d.flags, F_NFLAGS);
+  SWA(c->d_bar, 1);
   SWA(c->d_reps, (size_t)c->R);
   SWA(c->d_tile_rep, c->tile_rep.size());
   SWA(c->d_uoff, (size_t)c->R + 1);
@@ -160,6 +161,7 @@ hipError_t read_flags(sw_ctx* c, hipStream_t s, Flags* f) {
   f->nbr_need = h[F_NBR_NEED];
   f->cell_over = h[F_CELL_OVER];
   f->overlap = h[F_OVERLAP];
+  f->abort = h[F_ABORT];
   return hipSuccess;
 }
 
@@ -231,6 +233,7 @@ const char* sw_status_string(int s) {
     case SW_ENOMEM: return "device memory exhausted";
     case SW_EUNSUPPORTED: return "unsupported parameter or option";
     case SW_ESTATE: return "context has no neighbour rows yet";
+    case SW_ETIMEOUT: return "a grid barrier of the persistent launch waited too long";
   }
   return "unknown status";
 }
@@ -330,8 +333,7 @@ void sw_destroy(sw_ctx* ctx) {
 int sw_set_tuning(sw_ctx* ctx, const sw_tuning* t) {
   if (!ctx || !t) return SW_EINVAL;
   if (t->lanes_per_atom != 4 && t->lanes_per_atom != 8 && t->lanes_per_atom != 16) return SW_EUNSUPPORTED;
-  if (t->graph_steps < 0 || t->rebuild_every < 0 || t->timing < 0 || (t->persistent != 0 && t->persistent != 1))
-    return SW_EINVAL;
+  if (t->graph_steps < 0 || t->rebuild_every < 0 || t->timing < 0 || t->persistent < 0) return SW_EINVAL;
   ctx->tune = *t;
   ctx->t_mom_ms = ctx->t_for_ms = 0.0;
   ctx->t_samples = 0;
@@ -465,7 +467,15 @@ int sw_step(sw_ctx* ctx, float* x, float* v, float* f, const sw_params* params, 
       if ((e = launch_forces(ctx->d, ph, lpa, MODE_FORCES, 1, 0, nullptr, s)) != hipSuccess) return fail_hip(ctx, e);
     } else {
       if ((e = launch_forces(ctx->d, ph, lpa, MODE_START, 0, 0, nullptr, s)) != hipSuccess) return fail_hip(ctx, e);
-      for (int t = 1; t <= nsteps; ++t) {
+      const bool persistent = ctx->tune.persistent > 0;
+      if (persistent) {
+        PArgs pa{1, nsteps, nsteps, thermo ? thermo_every : 0, ctx->tune.rebuild_every, thermo, ctx->d_bar,
+                 ctx->d.flags + F_ABORT};
+        if ((e = launch_persistent(ctx->d, ph, lpa, pa, ctx->tune.persistent > 1 ? ctx->tune.persistent : 0, s,
+                                   &ctx->last_grid)) != hipSuccess)
+          return fail_hip(ctx, e);
+      }
+      for (int t = 1; t <= (persistent ? 0 : nsteps); ++t) {
         const int par = t & 1;
         const bool rec = thermo && (t % thermo_every == 0);
         double* row = rec ? thermo + (size_t)(t / thermo_every - 1) * ctx->R * kNQ : nullptr;
@@ -492,6 +502,7 @@ int sw_step(sw_ctx* ctx, float* x, float* v, float* f, const sw_params* params, 
     }
     Flags fl;
     if ((e = read_flags(ctx, s, &fl)) != hipSuccess) return fail_hip(ctx, e);
+    if (fl.abort) return SW_ETIMEOUT;
     if (fl.nbr_over || fl.cell_over) {
       if ((st = grow(ctx, fl)) != SW_OK) return st;
       continue;

@@ -33,6 +33,8 @@ struct sw_ctx {
   uint4* d_uq = nullptr;
   int *d_key = nullptr, *d_scnt = nullptr, *d_sstart = nullptr, *d_scur = nullptr, *d_order = nullptr;
   Tan t{};
+  unsigned* d_bar = nullptr;       // grid barrier counter of the persistent launch
+  int last_grid = 0;               // blocks of the last persistent launch
   bool have_order = false;
   long long steps = 0;
   int last_hip = 0;
@@ -48,7 +50,7 @@ int fail_hip(sw_ctx* c, hipError_t e);
 int lpa_for(const sw_ctx* c);
 int make_phys(const sw_ctx* c, const sw_params* P, double mass, double dt, Phys* o);
 hipError_t reset_flags(sw_ctx* c, hipStream_t s);
-struct Flags { int nbr_over, nbr_need, cell_over, overlap; };
+struct Flags { int nbr_over, nbr_need, cell_over, overlap, abort; };
 hipError_t read_flags(sw_ctx* c, hipStream_t s, Flags* f);
 int grow(sw_ctx* c, const Flags& f);
 hipError_t sort_in(sw_ctx* c, const float* x, const float* v, hipStream_t s);

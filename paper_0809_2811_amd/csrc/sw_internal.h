@@ -28,8 +28,10 @@ constexpr double kBoltz = 8.314462618 / 4184.0;  // kcal/(mol K)
 constexpr double kTwo32 = 4294967296.0;
 
 // Flag slots in Dev::flags.
-enum { F_NBR_OVER = 0, F_NBR_NEED = 1, F_CELL_OVER = 2, F_OVERLAP = 3, F_REBUILDS = 4,
-       F_MAXROW = 5, F_NFLAGS = 8 };
+// Slots below F_REBUILDS are cleared at the start of every call; F_REBUILDS
+// counts row rebuilds over the context's lifetime.
+enum { F_NBR_OVER = 0, F_NBR_NEED = 1, F_CELL_OVER = 2, F_OVERLAP = 3, F_ABORT = 4, F_REBUILDS = 7,
+       F_NFLAGS = 8 };
 
 struct RepInfo {
   double L[3];        // box edges (A)
@@ -110,6 +112,19 @@ hipError_t launch_scatter_out(const Dev& d, int par, float4* x_user, float4* v_u
 hipError_t launch_copy_thermo(const Dev& d, double* energy, double* virial, hipStream_t s);
 hipError_t launch_fill_i32(int* p, int value, long long n, hipStream_t s);
 hipError_t launch_fill_f32(float* p, float value, long long n, hipStream_t s);
+
+// Persistent cooperative launch of steps t0..t1 of an sw_step call.
+struct PArgs {
+  int t0, t1;          // first and last step of this launch
+  int nsteps;          // steps of the whole call (the last one ends on a full-step velocity)
+  int thermo_every;    // 0 = no thermo rows
+  int rebuild_every;   // forced row rebuild period (0 = none)
+  double* thermo;      // caller table [nsteps / thermo_every][R][kNQ] or null
+  unsigned* bar;       // grid barrier counter (zeroed by the launcher)
+  int* abort;          // raised by a barrier wait that timed out (flags[F_ABORT])
+};
+hipError_t launch_persistent(const Dev& d, const Phys& p, int lpa, const PArgs& a, int blocks_per_cu,
+                             hipStream_t s, int* grid_out);
 
 // Tangent (forward-mode) kernels for sw_grad / sw_adjoint.
 constexpr int kTQ = 7;  // per replica: E2, E3, W2 trace, W3 trace, w.F, w.F3, d(W trace) along w

@@ -189,20 +189,22 @@ __global__ __launch_bounds__(kBlock) void k_bin(Dev d, int par, int check, float
 // index in .w, so a cell is one contiguous read), keeping every atom within
 // cutoff + skin, sorted by index.  Then the group accumulates T, V, S (and
 // P, E2 on energy steps) over the active neighbours r < a sigma.
+// Clears the cell counts and displacement flags of the other parity; every
+// block of a moments launch (or phase) takes a grid-stride share.
+__device__ __forceinline__ void clear_next(const Dev& d, int par, int b, int G) {
+  for (int r = b * kBlock + threadIdx.x; r < d.R; r += G * kBlock) d.dflag[(par ^ 1) * d.R + r] = 0;
+  for (int c = b * kBlock + threadIdx.x; c < d.ctot; c += G * kBlock) d.gcnt[par ^ 1][c] = 0;
+}
+
+// lds: [APB][cap] candidates, [APB][cap] sorted, [APB] counts, [APB][56] cell prefix and ids
 template <int LPA, bool ENERGY>
-__global__ __launch_bounds__(kBlock) void k_moments(Dev d, Phys p, int par, int force_rebuild) {
+__device__ void moments_tile(const Dev& d, const Phys& p, int par, int force_rebuild, int bid, int* lds) {
   constexpr int APB = kBlock / LPA;
-  extern __shared__ int lds[];             // [APB][cap] candidates, [APB][cap] sorted, [APB] counts,
-                                           // [APB][56] cell prefix and ids
-  const int bid = xcd_remap(blockIdx.x, gridDim.x);
   const int g = threadIdx.x / LPA, lane = threadIdx.x % LPA;
   const int i = bid * APB + g;
   const int rep = d.tile_rep[(bid * APB) >> 6];
   const RepInfo& R = d.reps[rep];
   const float sc0 = R.scale[0], sc1 = R.scale[1], sc2 = R.scale[2];
-
-  for (int r = blockIdx.x * kBlock + threadIdx.x; r < d.R; r += gridDim.x * kBlock) d.dflag[(par ^ 1) * d.R + r] = 0;
-  for (int c = blockIdx.x * kBlock + threadIdx.x; c < d.ctot; c += gridDim.x * kBlock) d.gcnt[par ^ 1][c] = 0;
 
   // each replica rebuilds on its own displacement record
   const bool rebuild = force_rebuild || d.dflag[par * d.R + rep] != 0;
@@ -347,6 +349,13 @@ __global__ __launch_bounds__(kBlock) void k_moments(Dev d, Phys p, int par, int 
   }
 }
 
+template <int LPA, bool ENERGY>
+__global__ __launch_bounds__(kBlock) void k_moments(Dev d, Phys p, int par, int force_rebuild) {
+  extern __shared__ int lds[];
+  clear_next(d, par, blockIdx.x, gridDim.x);
+  moments_tile<LPA, ENERGY>(d, p, par, force_rebuild, xcd_remap(blockIdx.x, gridDim.x), lds);
+}
+
 // ----------------------------------------------------------------- forces
 // Block partial sums of the thermo quantities (fixed order within the block).
 // The per-replica sums are taken by k_reduce_thermo after the kernel ends.
@@ -363,6 +372,7 @@ __device__ void block_partials(const Dev& d, int bid, const double* q, bool writ
     for (int a = 0; a < APB; ++a) acc += red[a * kNQ + threadIdx.x];
     d.partial[(size_t)threadIdx.x * (d.npad / APB) + bid] = acc;
   }
+  __syncthreads();   // red[] is reused by the block's next tile
 }
 
 // Force on each atom from its neighbours (pair term + its own centre's
@@ -373,9 +383,8 @@ __device__ void block_partials(const Dev& d, int bid, const double* q, bool writ
 //   NVE_LAST v += dt/2 a (full step: KE)
 //   KICK     as NVE_LAST, the thermostat kernel follows
 template <int LPA, int MODE, bool VIR>
-__global__ __launch_bounds__(kBlock) void k_forces(Dev d, Phys p, int par) {
+__device__ void forces_tile(const Dev& d, const Phys& p, int par, int bid) {
   constexpr int APB = kBlock / LPA;
-  const int bid = xcd_remap(blockIdx.x, gridDim.x);
   const int g = threadIdx.x / LPA, lane = threadIdx.x % LPA;
   const int i = bid * APB + g;
   const int rep = d.tile_rep[(bid * APB) >> 6];
@@ -491,12 +500,17 @@ __global__ __launch_bounds__(kBlock) void k_forces(Dev d, Phys p, int par) {
   if (kReduce) block_partials<APB>(d, bid, q, lane == 0, g);
 }
 
+template <int LPA, int MODE, bool VIR>
+__global__ __launch_bounds__(kBlock) void k_forces(Dev d, Phys p, int par) {
+  forces_tile<LPA, MODE, VIR>(d, p, par, xcd_remap(blockIdx.x, gridDim.x));
+}
+
 // Per-replica sums of the block partials: one block per (replica, quantity),
 // threads stride over the replica's blocks, then a fixed tree.
-__global__ __launch_bounds__(kBlock) void k_reduce_thermo(Dev d, int apb, double* ring_row) {
+__device__ void reduce_task(const Dev& d, int apb, double* ring_row, int task) {
   __shared__ double tree[kBlock];
   const int nbt = d.npad / apb;
-  for (int task = blockIdx.x; task < d.R * kNQ; task += gridDim.x) {
+  {
     const int rep = task / kNQ, k = task % kNQ;
     const RepInfo& R = d.reps[rep];
     const int b0 = R.ioff / apb, b1 = R.ipad_end / apb;
@@ -517,10 +531,13 @@ __global__ __launch_bounds__(kBlock) void k_reduce_thermo(Dev d, int apb, double
   }
 }
 
+__global__ __launch_bounds__(kBlock) void k_reduce_thermo(Dev d, int apb, double* ring_row) {
+  for (int task = blockIdx.x; task < d.R * kNQ; task += gridDim.x) reduce_task(d, apb, ring_row, task);
+}
+
 // Thermostat on the full-step velocities, then (unless last) the next
 // half-kick and drift.
-__global__ __launch_bounds__(kBlock) void k_thermostat(Dev d, Phys p, int par, int last) {
-  const int i = blockIdx.x * kBlock + threadIdx.x;
+__device__ __forceinline__ void thermostat_atom(const Dev& d, const Phys& p, int par, int last, int i) {
   if (i < d.npad) {
     const int rep = d.tile_rep[i >> 6];
     const RepInfo& R = d.reps[rep];
@@ -540,6 +557,95 @@ __global__ __launch_bounds__(kBlock) void k_thermostat(Dev d, Phys p, int par, i
         drift_bin(d, p, R, rep, i, d.u[par][i], v, par ^ 1);
       }
       d.v[i] = v;
+    }
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_thermostat(Dev d, Phys p, int par, int last) {
+  thermostat_atom(d, p, par, last, blockIdx.x * kBlock + threadIdx.x);
+}
+
+// ----------------------------------------------------------------- persistent
+// Grid-wide barrier of a cooperative launch.  Arrivals add to a counter that
+// only grows (barrier k completes at k * G arrivals).  Every wait is bounded:
+// a block that waits too long raises `abort`, and every later barrier
+// returns at once, so the grid always drains.
+__device__ bool grid_sync(const PArgs& a, unsigned G, unsigned& k) {
+  __shared__ int ok;
+  __syncthreads();
+  ++k;
+  if (threadIdx.x == 0) {
+    __threadfence();                       // release this block's writes
+    atomicAdd(a.bar, 1u);
+    const unsigned target = k * G;
+    unsigned spins = 0;
+    int good = 1;
+    while (__hip_atomic_load(a.bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+      if (__hip_atomic_load(a.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+        good = 0;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(2);
+      if (++spins > (1u << 22)) {
+        atomicOr(a.abort, 1);
+        good = 0;
+        break;
+      }
+    }
+    __threadfence();                       // acquire the other blocks' writes
+    ok = good;
+  }
+  __syncthreads();
+  return ok != 0;
+}
+
+// All steps t0..t1 of sw_step in one launch: the same tile functions as the
+// one-kernel-per-phase path, separated by grid barriers.  Worker w (blocks
+// remapped per XCD) owns a contiguous range of tiles in every phase.
+template <int LPA>
+__global__ __launch_bounds__(kBlock) void k_persistent(Dev d, Phys p, PArgs a) {
+  constexpr int APB = kBlock / LPA;
+  extern __shared__ int lds[];
+  const unsigned G = gridDim.x;
+  const int w = xcd_remap(blockIdx.x, (int)G);
+  const int ntile = d.npad / APB;
+  const int tlo = (int)((long long)ntile * w / G), thi = (int)((long long)ntile * (w + 1) / G);
+  const int n256 = (d.npad + kBlock - 1) / kBlock;
+  const int alo = (int)((long long)n256 * w / G), ahi = (int)((long long)n256 * (w + 1) / G);
+  const bool thermostat = p.thermostat != 0;
+  unsigned k = 0;
+  for (int t = a.t0; t <= a.t1; ++t) {
+    const int par = t & 1;
+    const bool rec = a.thermo_every > 0 && t % a.thermo_every == 0;
+    const bool last = t == a.nsteps;
+    const int frb = a.rebuild_every > 0 && t % a.rebuild_every == 0;
+    double* row = rec && a.thermo ? a.thermo + (size_t)(t / a.thermo_every - 1) * d.R * kNQ : nullptr;
+    clear_next(d, par, blockIdx.x, (int)G);
+    for (int b = tlo; b < thi; ++b) {
+      if (rec) moments_tile<LPA, true>(d, p, par, frb, b, lds);
+      else moments_tile<LPA, false>(d, p, par, frb, b, lds);
+    }
+    if (!grid_sync(a, G, k)) return;
+    for (int b = tlo; b < thi; ++b) {
+      if (thermostat) {
+        if (rec) forces_tile<LPA, MODE_KICK, true>(d, p, par, b);
+        else forces_tile<LPA, MODE_KICK, false>(d, p, par, b);
+      } else if (last) {
+        if (rec) forces_tile<LPA, MODE_NVE_LAST, true>(d, p, par, b);
+        else forces_tile<LPA, MODE_NVE_LAST, false>(d, p, par, b);
+      } else {
+        if (rec) forces_tile<LPA, MODE_NVE, true>(d, p, par, b);
+        else forces_tile<LPA, MODE_NVE, false>(d, p, par, b);
+      }
+    }
+    if (!grid_sync(a, G, k)) return;
+    if (rec || thermostat) {
+      for (int task = w; task < d.R * kNQ; task += (int)G) reduce_task(d, APB, row, task);
+      if (!grid_sync(a, G, k)) return;
+    }
+    if (thermostat) {
+      for (int b = alo; b < ahi; ++b) thermostat_atom(d, p, par, last, b * kBlock + threadIdx.x);
+      if (!grid_sync(a, G, k)) return;
     }
   }
 }
@@ -636,7 +742,42 @@ hipError_t forces_lpa(const Dev& d, const Phys& p, int mode, int vir, int par, d
   return hipErrorInvalidValue;
 }
 
+template <int LPA>
+hipError_t persistent_lpa(const Dev& d, const Phys& p, const PArgs& a, int blocks_per_cu, hipStream_t s,
+                          int* grid_out) {
+  constexpr int APB = kBlock / LPA;
+  const size_t lds = sizeof(int) * (2 * (size_t)APB * d.cap + APB + 56 * (size_t)APB);
+  int per_cu = 0, dev = 0, ncu = 0;
+  hipError_t e;
+  if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_persistent<LPA>, kBlock, lds)) != hipSuccess)
+    return e;
+  if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
+  if ((e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
+  if (blocks_per_cu > 0) per_cu = min(per_cu, blocks_per_cu);
+  const int ntile = d.npad / APB;
+  const int grid = max(1, min(per_cu * ncu, ntile));
+  *grid_out = grid;
+  Dev dd = d;
+  Phys pp = p;
+  PArgs aa = a;
+  void* args[] = {&dd, &pp, &aa};
+  return hipLaunchCooperativeKernel((const void*)k_persistent<LPA>, dim3(grid), dim3(kBlock), args,
+                                    (unsigned)lds, s);
+}
+
 }  // namespace
+
+hipError_t launch_persistent(const Dev& d, const Phys& p, int lpa, const PArgs& a, int blocks_per_cu,
+                             hipStream_t s, int* grid_out) {
+  hipError_t e;
+  if ((e = launch_fill_i32((int*)a.bar, 0, 1, s)) != hipSuccess) return e;
+  switch (lpa) {
+    case 4: return persistent_lpa<4>(d, p, a, blocks_per_cu, s, grid_out);
+    case 8: return persistent_lpa<8>(d, p, a, blocks_per_cu, s, grid_out);
+    case 16: return persistent_lpa<16>(d, p, a, blocks_per_cu, s, grid_out);
+  }
+  return hipErrorInvalidValue;
+}
 
 hipError_t launch_sort(const Dev& d, const float4* x_user, const float4* v_user, long long n_user,
                        const long long* uoff, int R, const int* cell_rank, uint4* uq, int* key, int* cnt,

@@ -27,6 +27,7 @@ SW_EHIP = -6
 SW_ENOMEM = -7
 SW_EUNSUPPORTED = -8
 SW_ESTATE = -9
+SW_ETIMEOUT = -10
 
 SW_NVE, SW_RESCALE, SW_BERENDSEN = 0, 1, 2
 SW_THERMO_WIDTH = 12

@@ -143,3 +143,28 @@ def test_thermo_recording_does_not_change_the_trajectory():
     a = run_gpu(x, v, L, 30, thermo_every=1)
     b = run_gpu(x, v, L, 30, thermo_every=0)
     assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+@pytest.mark.parametrize("thermostat", ["nve", "berendsen"])
+def test_persistent_launch_equals_launch_per_phase(thermostat):
+    """The cooperative persistent kernel runs the same tile functions between
+    grid barriers: results are bitwise those of one launch per phase."""
+    from paper_0809_2811_amd import sw
+    specs = [((4, 4, 4), 1.0, 300.0), ((3, 4, 5), 0.93, 250.0), ((4, 5, 6), 1.05, 220.0)]
+    xs, vs, boxes = [], [], []
+    for k, (cells, rho, T) in enumerate(specs):
+        d = synth.lattice_at_density(cells, rho, sigma=0.2, temperature=T, seed=60 + k)
+        xs.append(f32(d["x"])); vs.append(f32(d["v"])); boxes.append(d["box"])
+    offsets = np.cumsum([0] + [len(x) for x in xs])
+    kw = dict(thermo_every=5)
+    if thermostat == "berendsen":
+        kw.update(thermostat=sw.SW_BERENDSEN, T0=[s[2] for s in specs], tau_fs=100.0)
+    out = []
+    for persistent in (0, 1):
+        ctx = make_ctx(np.concatenate(xs), None, offsets=offsets, boxes=boxes, persistent=persistent,
+                       rebuild_every=10)
+        xd, vd = to_dev(np.concatenate(xs)), to_dev(np.concatenate(vs))
+        f, th = ctx.step(xd, vd, 40, **kw)
+        out.append((from_dev(xd), from_dev(vd), from_dev(f), th.cpu().numpy(), ctx.query(sw.SW_Q_REBUILDS)))
+    for k in range(5):
+        assert np.array_equal(out[0][k], out[1][k]), k
