@@ -137,7 +137,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10000)
     ap.add_argument("--warmup", type=int, default=500)
-    ap.add_argument("--skin", type=float, default=1.0)
+    ap.add_argument("--skin", type=float, default=0.0, help="Verlet skin in A (0 = tuned)")
     ap.add_argument("--lpa", type=int, default=0, help="lanes per atom (0 = tuned default)")
     ap.add_argument("--forms", default="large,batched,adjoint", help="comma list of large,batched,adjoint or none")
     ap.add_argument("--no-cpu", action="store_true")
@@ -152,9 +152,12 @@ def main():
 
     cfg = synth.config(1)
     n = len(cfg["x"])
-    tuning = tune.best(n, 1.0, args.skin)
+    tuning = tune.best(n, 1.0, args.skin if args.skin > 0 else None)
+    skin = args.skin if args.skin > 0 else tuning.get("skin", 1.0)
+    tuning.pop("skin", None)
     if args.lpa:
         tuning["lanes_per_atom"] = args.lpa
+    args.skin = skin
     ctx, x, v = prepare_liquid(cfg, args.skin, tuning)
     if args.warmup > 0:
         ctx.step(x, v, args.warmup)
@@ -192,6 +195,7 @@ def bench_large(steps=1000, skin=0.5):
     cfg = synth.config(2)
     n = len(cfg["x"])
     tuning = tune.best(n, 1.0, skin)
+    tuning.pop("skin", None)
     tuning["rebuild_every"] = 10
     ctx, x, v = prepare_liquid(cfg, skin, tuning)
     ctx.step(x, v, 50)
@@ -219,7 +223,9 @@ def bench_batched(steps=5000, melt_steps=1000, skin=1.0, sequential_steps=500):
     tab = synth.replica_table()
     off, boxes, T = tab["offsets"], tab["boxes"], tab["temperatures"]
     n = int(off[-1])
-    base = tune.best(n // len(boxes), 1.0, skin)
+    base = tune.best(n, 1.0, skin, replicas=True)
+    base.pop("skin", None)
+    base["persistent"] = 0
     x0 = torch.from_numpy(synth.to_float4(tab["x"])).cuda()
     v0 = torch.from_numpy(synth.to_float4(tab["v"])).cuda()
     ctx = sw.Context(off, boxes, cutoff=RC, skin=skin, nbr_capacity=64, tuning=base)
@@ -243,8 +249,9 @@ def bench_batched(steps=5000, melt_steps=1000, skin=1.0, sequential_steps=500):
     total = 0.0
     for r in range(len(boxes)):
         a, b = int(off[r]), int(off[r + 1])
-        c1 = sw.Context([0, b - a], [boxes[r]], cutoff=RC, skin=skin, nbr_capacity=64,
-                        tuning=tune.best(b - a, 1.0, skin))
+        t1 = tune.best(b - a, 1.0, skin)
+        t1.pop("skin", None)
+        c1 = sw.Context([0, b - a], [boxes[r]], cutoff=RC, skin=skin, nbr_capacity=64, tuning=t1)
         xr, vr = xs[a:b].contiguous(), vs[a:b].contiguous()
         c1.step(xr, vr, 20, thermostat=sw.SW_BERENDSEN, T0=[T[r]], tau_fs=1000.0)
         sync()
@@ -260,7 +267,7 @@ def bench_batched(steps=5000, melt_steps=1000, skin=1.0, sequential_steps=500):
     return out
 
 
-def bench_adjoint(plain_ms_per_step, steps=200, ckpt=20, skin=1.0):
+def bench_adjoint(plain_ms_per_step, steps=200, ckpt=20, skin=None):
     """Differentiable trajectory: 4096-atom 298 K liquid (same preparation as
     the main line), 200 NVE steps, checkpoints every 20; one call computes
     the loss, dL/dx0, dL/dv0 and dL/d(lambda, eps, sigma)."""
@@ -268,6 +275,7 @@ def bench_adjoint(plain_ms_per_step, steps=200, ckpt=20, skin=1.0):
     cfg = synth.config(4)
     n = len(cfg["x"])
     tuning = tune.best(n, 1.0, skin)
+    skin = tuning.pop("skin", 1.0) if skin is None else skin
     ctx, x, v = prepare_liquid(cfg, skin, tuning)
     ctx.adjoint(x, v, 20, ckpt_every=ckpt)
     sync()

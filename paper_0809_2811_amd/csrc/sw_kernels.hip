@@ -308,11 +308,23 @@ __device__ void moments_tile(const Dev& d, const Phys& p, int par, int force_reb
   float T0 = 0.f, T1 = 0.f, T2 = 0.f, T3 = 0.f, T4 = 0.f, T5 = 0.f;
   float V0 = 0.f, V1 = 0.f, V2 = 0.f, S = 0.f, P = 0.f, E2 = 0.f;
   const uint4* upm = d.u[par];
-  for (int s = lane; s < nn; s += LPA) {
-    const int j = row[s];
-    const float3 dd = disp(ui, upm[j], sc0, sc1, sc2);
+  // pipelined like the force loop: kMU slots' indices, then positions
+  constexpr int kMU = 4;
+  for (int s0 = lane; s0 < nn; s0 += kMU * LPA) {
+    int jj[kMU];
+#pragma unroll
+    for (int u = 0; u < kMU; ++u) {
+      const int s = s0 + u * LPA;
+      jj[u] = s < nn ? row[s] : -1;
+    }
+    uint4 uu[kMU];
+#pragma unroll
+    for (int u = 0; u < kMU; ++u) uu[u] = jj[u] >= 0 ? upm[jj[u]] : ui;
+#pragma unroll
+    for (int u = 0; u < kMU; ++u) {
+    const float3 dd = disp(ui, uu[u], sc0, sc1, sc2);
     const float r2 = dd.x * dd.x + dd.y * dd.y + dd.z * dd.z;
-    if (r2 < p.rc2) {
+    if (jj[u] >= 0 && r2 < p.rc2) {
       const float ir = rsq(r2);
       const float ux = dd.x * ir, uy = dd.y * ir, uz = dd.z * ir;
       const float idr = rcp(r2 * ir - p.rc);
@@ -327,6 +339,7 @@ __device__ void moments_tile(const Dev& d, const Phys& p, int par, int force_reb
         const float sr = p.sig * ir, s2 = sr * sr;
         E2 += 0.5f * p.Aeps * (p.B * s2 * s2 - 1.f) * e1;
       }
+    }
     }
   }
   T0 = group_sum<LPA>(T0); T1 = group_sum<LPA>(T1); T2 = group_sum<LPA>(T2);
@@ -408,11 +421,44 @@ __device__ void forces_tile(const Dev& d, const Phys& p, int par, int bid) {
   const uint4* up = d.u[par];
   float fx = 0.f, fy = 0.f, fz = 0.f;
   float w0 = 0.f, w1 = 0.f, w2 = 0.f, w3 = 0.f, w4 = 0.f, w5 = 0.f;
-  for (int s = lane; s < nn; s += LPA) {
-    const int j = row[s];
-    const float3 dd = disp(ui, up[j], sc0, sc1, sc2);
-    const float r2 = dd.x * dd.x + dd.y * dd.y + dd.z * dd.z;
-    if (r2 < p.rc2) {
+  // Software-pipelined over kFU row slots per lane: the slots' indices, then
+  // their positions, then the active neighbours' moments are each loaded as
+  // one batch of independent loads before any arithmetic.  The per-lane
+  // order of neighbours is the plain stride order.
+  constexpr int kFU = 2;
+  for (int s0 = lane; s0 < nn; s0 += kFU * LPA) {
+    int jj[kFU];
+#pragma unroll
+    for (int u = 0; u < kFU; ++u) {
+      const int s = s0 + u * LPA;
+      jj[u] = s < nn ? row[s] : -1;
+    }
+    uint4 uu[kFU];
+#pragma unroll
+    for (int u = 0; u < kFU; ++u) uu[u] = jj[u] >= 0 ? up[jj[u]] : ui;
+    float3 ddv[kFU];
+    float r2v[kFU];
+    bool act[kFU];
+#pragma unroll
+    for (int u = 0; u < kFU; ++u) {
+      ddv[u] = disp(ui, uu[u], sc0, sc1, sc2);
+      r2v[u] = ddv[u].x * ddv[u].x + ddv[u].y * ddv[u].y + ddv[u].z * ddv[u].z;
+      act[u] = jj[u] >= 0 && r2v[u] < p.rc2;
+    }
+    float4 mja[kFU], mjb[kFU], mjc[kFU];
+#pragma unroll
+    for (int u = 0; u < kFU; ++u) {
+      if (act[u]) {
+        const float4* mj = d.mom + 3 * (size_t)jj[u];
+        mja[u] = mj[0]; mjb[u] = mj[1]; mjc[u] = mj[2];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kFU; ++u) {
+    if (act[u]) {
+      const int j = jj[u];
+      const float3 dd = ddv[u];
+      const float r2 = r2v[u];
       if (r2 < 0.25f) atomicOr(&d.flags[F_OVERLAP], 1);
       const float ir = rsq(r2);
       const float r = r2 * ir;
@@ -425,8 +471,8 @@ __device__ void forces_tile(const Dev& d, const Phys& p, int par, int bid) {
       const float poly = p.B * s4 - 1.f;
       const float dphi = p.Aeps * e1 * (-4.f * p.B * s4 * ir - poly * p.sig * idr2);
       const float gg = -p.gsig * idr2;
-      const float4* mj = d.mom + 3 * (size_t)j;
-      const float4 na = mj[0], nb = mj[1], nc = mj[2];
+      (void)j;
+      const float4 na = mja[u], nb = mjb[u], nc = mjc[u];
       const float Ts0 = Tm0 + na.x, Ts1 = Tm1 + na.y, Ts2 = Tm2 + na.z, Ts3 = Tm3 + na.w;
       const float Ts4 = Tm4 + nb.x, Ts5 = Tm5 + nb.y;
       const float Dv0 = Vm0 - nb.z, Dv1 = Vm1 - nb.w, Dv2 = Vm2 - nc.x, Ss = Sm + nc.y;
@@ -463,6 +509,7 @@ __device__ void forces_tile(const Dev& d, const Phys& p, int par, int bid) {
         w4 += cA * ux * uz + cB * ux * poz;
         w5 += cA * uy * uz + cB * uy * poz;
       }
+    }
     }
   }
   fx = group_sum<LPA>(fx); fy = group_sum<LPA>(fy); fz = group_sum<LPA>(fz);

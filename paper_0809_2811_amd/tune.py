@@ -1,13 +1,15 @@
 """Autotuner for the engine's launch parameters.
 
-The search space is the sw_tuning block (include/sw.h): lanes of a wavefront
-per atom (4, 8, 16), steps per captured hipGraph, persistent launch on/off,
-plus the Verlet skin.  `search()` times short NVE runs of a synthetic liquid
-for every candidate on the current GPU and writes the winner for the
-(arch, atom-count bucket, density bucket) key to tuning_cache.json next to
-this file; `best()` reads that cache (falling back to defaults).
+Search space: lanes of a wavefront per atom (4, 8, 16; the sw_tuning block of
+include/sw.h), the Verlet skin (a context parameter: longer rows against
+fewer rebuilds) and the launch form (one launch per phase or the persistent
+cooperative kernel).  `search()` times short NVE runs of a synthetic 298 K
+liquid for every candidate on the current GPU, `search_replicas()` times
+Berendsen runs of the uneven replica table; the winners are written to
+tuning_cache.json next to this file, keyed by (arch, atom-count bucket,
+density).  `best()` reads the cache and falls back to defaults.
 
-    python -m paper_0809_2811_amd.tune --atoms 4096 262144 --replicas
+    python -m paper_0809_2811_amd.tune --cells 8 32 --replicas
 """
 from __future__ import annotations
 
@@ -19,6 +21,7 @@ import time
 
 CACHE = pathlib.Path(__file__).resolve().parent / "tuning_cache.json"
 DEFAULT = dict(lanes_per_atom=8, graph_steps=0, persistent=0, rebuild_every=0, timing=0)
+RC = 1.8 * 2.3925
 
 
 def _arch() -> str:
@@ -41,64 +44,125 @@ def load_cache() -> dict:
     return {}
 
 
-def best(n_atoms: int, rho: float = 1.0, skin: float = 1.0, arch: str | None = None) -> dict:
-    key = f"{arch or 'gfx950'}/{bucket(n_atoms, rho)}/skin{skin:.2f}"
+def best(n_atoms: int, rho: float = 1.0, skin: float | None = None, arch: str | None = None,
+         replicas: bool = False) -> dict:
+    """Tuning for a box of n_atoms at rho.  With skin=None the entry also
+    carries the best skin ("skin" key); with a fixed skin, the best lanes per
+    atom for that skin."""
+    key = f"{arch or 'gfx950'}/{'replicas' if replicas else bucket(n_atoms, rho)}"
     out = dict(DEFAULT)
-    out.update(load_cache().get(key, {}).get("tuning", {}))
+    ent = load_cache().get(key)
+    if ent:
+        if skin is None:
+            out.update(ent["best"])
+        else:
+            by = ent.get("by_skin", {}).get(f"{skin:.2f}")
+            if by:
+                out["lanes_per_atom"] = by["lanes_per_atom"]
+            else:
+                out["lanes_per_atom"] = ent["best"]["lanes_per_atom"]
     return out
 
 
-def _time_candidate(x0, v0, box, tuning, skin, steps):
+def _timed(ctx, x, v, steps, **kw):
     import torch
-    from paper_0809_2811_amd import sw
-    ctx = sw.Context([0, x0.shape[0]], [box], skin=skin, nbr_capacity=64, tuning=tuning)
-    x, v = x0.clone(), v0.clone()
-    ctx.step(x, v, 20)
+    ctx.step(x, v, 20, **kw)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    ctx.step(x, v, steps)
+    ctx.step(x, v, steps, **kw)
     torch.cuda.synchronize()
     return (time.perf_counter() - t0) / steps
 
 
-def search(n_cells: int, rho: float = 1.0, skins=(0.5, 1.0), steps: int = 400, write: bool = True):
-    """Time every candidate on a 298 K liquid of 8 n_cells^3 atoms."""
+def _liquid(n_cells: int, rho: float):
     import torch
     from paper_0809_2811_amd import sw, synth
     cfg = synth.lattice_at_density(n_cells, rho, sigma=0.05, temperature=400.0, seed=7)
-    box = cfg["box"]
     x = torch.from_numpy(synth.to_float4(cfg["x"])).cuda()
     v = torch.from_numpy(synth.to_float4(cfg["v"])).cuda()
-    prep = sw.Context([0, x.shape[0]], [box], skin=1.0, nbr_capacity=64)
+    prep = sw.Context([0, x.shape[0]], [cfg["box"]], cutoff=RC, skin=1.0, nbr_capacity=64)
     prep.step(x, v, 1000, thermostat=sw.SW_RESCALE, T0=400.0)
     prep.step(x, v, 300, thermostat=sw.SW_RESCALE, T0=298.0)
+    return cfg["box"], x, v
+
+
+def search(n_cells: int, rho: float = 1.0, skins=(0.5, 0.7, 1.0, 1.3), steps: int = 400, write: bool = True):
+    """NVE candidates on a 298 K liquid of 8 n_cells^3 atoms."""
+    from paper_0809_2811_amd import sw
+    box, x0, v0 = _liquid(n_cells, rho)
+    n = x0.shape[0]
     results = []
     for skin in skins:
         for lpa in (4, 8, 16):
             tun = dict(DEFAULT, lanes_per_atom=lpa)
-            dt = _time_candidate(x, v, box, tun, skin, steps)
-            results.append(dict(skin=skin, tuning=tun, s_per_step=dt))
-    cache = load_cache()
-    n = x.shape[0]
+            ctx = sw.Context([0, n], [box], cutoff=RC, skin=skin, nbr_capacity=64, tuning=tun)
+            dt = _timed(ctx, x0.clone(), v0.clone(), steps)
+            results.append(dict(skin=skin, lanes_per_atom=lpa, persistent=0, s_per_step=dt))
+    win = min(results, key=lambda r: r["s_per_step"])
+    # the persistent form at the winning point
+    ctx = sw.Context([0, n], [box], cutoff=RC, skin=win["skin"], nbr_capacity=64,
+                     tuning=dict(DEFAULT, lanes_per_atom=win["lanes_per_atom"], persistent=1))
+    results.append(dict(skin=win["skin"], lanes_per_atom=win["lanes_per_atom"], persistent=1,
+                        s_per_step=_timed(ctx, x0.clone(), v0.clone(), steps)))
+    win = min(results, key=lambda r: r["s_per_step"])
+    by_skin = {}
     for skin in skins:
-        cands = [r for r in results if r["skin"] == skin]
-        win = min(cands, key=lambda r: r["s_per_step"])
-        cache[f"{_arch()}/{bucket(n, rho)}/skin{skin:.2f}"] = dict(
-            tuning=win["tuning"], s_per_step=win["s_per_step"],
-            candidates=[(r["tuning"]["lanes_per_atom"], r["s_per_step"]) for r in cands])
+        c = min((r for r in results if r["skin"] == skin and r["persistent"] == 0), key=lambda r: r["s_per_step"])
+        by_skin[f"{skin:.2f}"] = dict(lanes_per_atom=c["lanes_per_atom"], s_per_step=c["s_per_step"])
+    entry = dict(best=dict(lanes_per_atom=win["lanes_per_atom"], skin=win["skin"], persistent=win["persistent"]),
+                 s_per_step=win["s_per_step"], by_skin=by_skin, n_atoms=n, candidates=results)
     if write:
+        cache = load_cache()
+        cache[f"{_arch()}/{bucket(n, rho)}"] = entry
         CACHE.write_text(json.dumps(cache, indent=1, sort_keys=True))
-    return results
+    return entry
+
+
+def search_replicas(steps: int = 300, skin: float = 1.0, write: bool = True):
+    """Berendsen candidates on the uneven replica table (one context)."""
+    import torch
+    from paper_0809_2811_amd import sw, synth
+    tab = synth.replica_table()
+    off, boxes, T = tab["offsets"], tab["boxes"], tab["temperatures"]
+    x0 = torch.from_numpy(synth.to_float4(tab["x"])).cuda()
+    v0 = torch.from_numpy(synth.to_float4(tab["v"])).cuda()
+    prep = sw.Context(off, boxes, cutoff=RC, skin=skin, nbr_capacity=64)
+    prep.step(x0, v0, 500, thermostat=sw.SW_RESCALE, T0=[400.0] * len(boxes))
+    results = []
+    for lpa in (4, 8, 16):
+        for persistent in (0, 1):
+            ctx = sw.Context(off, boxes, cutoff=RC, skin=skin, nbr_capacity=64,
+                             tuning=dict(DEFAULT, lanes_per_atom=lpa, persistent=persistent))
+            dt = _timed(ctx, x0.clone(), v0.clone(), steps, thermostat=sw.SW_BERENDSEN, T0=T, tau_fs=1000.0)
+            results.append(dict(skin=skin, lanes_per_atom=lpa, persistent=persistent, s_per_step=dt))
+    win = min(results, key=lambda r: r["s_per_step"])
+    entry = dict(best=dict(lanes_per_atom=win["lanes_per_atom"], skin=skin, persistent=win["persistent"]),
+                 s_per_step=win["s_per_step"], by_skin={f"{skin:.2f}": dict(lanes_per_atom=win["lanes_per_atom"],
+                                                                         s_per_step=win["s_per_step"])},
+                 n_atoms=int(off[-1]), candidates=results)
+    if write:
+        cache = load_cache()
+        cache[f"{_arch()}/replicas"] = entry
+        CACHE.write_text(json.dumps(cache, indent=1, sort_keys=True))
+    return entry
 
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--cells", type=int, nargs="+", default=[8, 32])
+    ap.add_argument("--cells", type=int, nargs="*", default=[8, 32])
+    ap.add_argument("--replicas", action="store_true")
     ap.add_argument("--steps", type=int, default=400)
+    ap.add_argument("--out", default=None, help="write the cache here instead of next to this file")
     a = ap.parse_args()
+    global CACHE
+    if a.out:
+        CACHE = pathlib.Path(a.out)
     for c in a.cells:
-        for r in search(c, steps=a.steps):
-            print(json.dumps(r), flush=True)
+        e = search(c, steps=a.steps, skins=(0.5, 0.7, 1.0, 1.3) if c <= 16 else (0.5, 1.0))
+        print(json.dumps(dict(cells=c, best=e["best"], s_per_step=e["s_per_step"])), flush=True)
+    if a.replicas:
+        e = search_replicas()
+        print(json.dumps(dict(replicas=True, best=e["best"], s_per_step=e["s_per_step"])), flush=True)
 
 
 if __name__ == "__main__":
