@@ -65,6 +65,7 @@ hipError_t alloc_capacity(sw_ctx* c) {
     if ((e = dalloc(c, &c->d.gmem[k], (size_t)c->ctot * c->cc, c->grow_allocs)) != hipSuccess) return e;
   c->d.cap = c->cap;
   c->d.cc = c->cc;
+  ++c->alloc_gen;
   return hipSuccess;
 }
 
@@ -201,6 +202,67 @@ hipError_t sort_in(sw_ctx* c, const float* x, const float* v, hipStream_t s) {
 
 bool valid_ptr(const void* p) { return p != nullptr; }
 
+// Enqueues step t of the per-phase path.  row: thermo destination or null.
+hipError_t enqueue_step(sw_ctx* c, const Phys& ph, int lpa, int t, int nsteps, int thermostat, bool rec,
+                        double* row, hipStream_t s, const KTimer& tm_m, const KTimer& tm_f) {
+  const int par = t & 1;
+  const int force_rb = c->tune.rebuild_every > 0 && (t % c->tune.rebuild_every == 0);
+  hipError_t e;
+  if ((e = launch_moments(c->d, ph, lpa, par, force_rb, rec, s, tm_m)) != hipSuccess) return e;
+  if (thermostat == SW_NVE) {
+    const int mode = t == nsteps ? MODE_NVE_LAST : MODE_NVE;
+    if ((e = launch_forces(c->d, ph, lpa, mode, rec, par, row, s, tm_f)) != hipSuccess) return e;
+  } else {
+    if ((e = launch_forces(c->d, ph, lpa, MODE_KICK, rec, par, row, s, tm_f)) != hipSuccess) return e;
+    if ((e = launch_thermostat(c->d, ph, par, t == nsteps, s)) != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+long long lcm_ll(long long a, long long b) {
+  long long x = a, y = b;
+  while (y) { long long r = x % y; x = y; y = r; }
+  return a / x * b;
+}
+
+// Captures steps base+1 .. base+K (base a multiple of the pattern period) of
+// the per-phase path into a graph, unless the cached one matches.
+hipError_t ensure_graph(sw_ctx* c, const Phys& ph, int lpa, int K, int thermostat, int every) {
+  std::vector<unsigned char> key(sizeof(Phys) + 6 * sizeof(int));
+  int meta[6] = {K, lpa, thermostat, every, c->tune.rebuild_every, c->alloc_gen};
+  std::memcpy(key.data(), &ph, sizeof(Phys));
+  std::memcpy(key.data() + sizeof(Phys), meta, sizeof meta);
+  if (c->gexec && key == c->gkey) return hipSuccess;
+  hipError_t e;
+  if (c->gexec) { (void)hipGraphExecDestroy(c->gexec); c->gexec = nullptr; }
+  if (c->graph) { (void)hipGraphDestroy(c->graph); c->graph = nullptr; }
+  if (!c->cap_stream && (e = hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking)) != hipSuccess) return e;
+  const size_t rows = every > 0 ? (size_t)(K / every) : 0;
+  if (rows > c->ring_rows) {
+    if (c->ring) (void)hipFree(c->ring);
+    c->ring = nullptr;
+    c->ring_rows = 0;
+    if ((e = hipMalloc((void**)&c->ring, rows * c->R * kNQ * sizeof(double))) != hipSuccess) return e;
+    c->ring_rows = rows;
+  }
+  if ((e = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal)) != hipSuccess) return e;
+  hipError_t le = hipSuccess;
+  for (int l = 1; l <= K && le == hipSuccess; ++l) {
+    const bool rec = every > 0 && l % every == 0;
+    double* row = rec ? c->ring + (size_t)(l / every - 1) * c->R * kNQ : nullptr;
+    // local step l stands for step base + l; the last step of a call is never captured
+    le = enqueue_step(c, ph, lpa, l, K + 1, thermostat, rec, row, c->cap_stream, KTimer(), KTimer());
+  }
+  hipGraph_t g = nullptr;
+  e = hipStreamEndCapture(c->cap_stream, &g);
+  if (le != hipSuccess) { if (g) (void)hipGraphDestroy(g); return le; }
+  if (e != hipSuccess) return e;
+  c->graph = g;
+  if ((e = hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0)) != hipSuccess) return e;
+  c->gkey = key;
+  return hipSuccess;
+}
+
 }  // namespace swh
 
 using namespace swh;
@@ -325,6 +387,10 @@ void sw_destroy(sw_ctx* ctx) {
   if (!ctx) return;
   (void)hipDeviceSynchronize();
   for (hipEvent_t e : ctx->tev) (void)hipEventDestroy(e);
+  if (ctx->gexec) (void)hipGraphExecDestroy(ctx->gexec);
+  if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
+  if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
+  if (ctx->ring) (void)hipFree(ctx->ring);
   free_list(ctx->grow_allocs);
   free_list(ctx->allocs);
   delete ctx;
@@ -352,7 +418,7 @@ int sw_build_neighbors(sw_ctx* ctx, const float* x, void* stream) {
   sw_params P;
   sw_params_mw(&P);
   P.a = ctx->cutoff / P.sigma;  // rows only need the row radius; moments use the full cut-off
-  Phys ph;
+  Phys ph{};
   int st = make_phys(ctx, &P, 1.0, 1.0, &ph);
   if (st != SW_OK) return st;
   for (int attempt = 0; attempt < 6; ++attempt) {
@@ -395,7 +461,7 @@ int sw_forces(sw_ctx* ctx, const float* x, const sw_params* params, float* f, do
               void* stream) {
   if (!ctx || !valid_ptr(x) || !valid_ptr(f)) return SW_EINVAL;
   hipStream_t s = (hipStream_t)stream;
-  Phys ph;
+  Phys ph{};
   int st = make_phys(ctx, params, 1.0, 1.0, &ph);
   if (st != SW_OK) return st;
   for (int attempt = 0; attempt < 6; ++attempt) {
@@ -438,7 +504,7 @@ int sw_step(sw_ctx* ctx, float* x, float* v, float* f, const sw_params* params, 
   if (thermostat == SW_BERENDSEN && !(tau_fs > 0.0)) return SW_EINVAL;
   if (thermo && thermo_every <= 0) return SW_EINVAL;
   hipStream_t s = (hipStream_t)stream;
-  Phys ph;
+  Phys ph{};
   int st = make_phys(ctx, params, mass, dt, &ph);
   if (st != SW_OK) return st;
   ph.thermostat = thermostat;
@@ -475,11 +541,33 @@ int sw_step(sw_ctx* ctx, float* x, float* v, float* f, const sw_params* params, 
                                    &ctx->last_grid)) != hipSuccess)
           return fail_hip(ctx, e);
       }
-      for (int t = 1; t <= (persistent ? 0 : nsteps); ++t) {
-        const int par = t & 1;
+      int t_first = 1;
+      if (!persistent && ctx->tune.graph_steps > 0 && nsteps > 1) {
+        // replay a captured block of K steps over steps 1 .. nsteps-1 where
+        // the block pattern (parity, thermo rows, forced rebuilds) repeats
+        long long period = 2;
+        const int every = thermo ? thermo_every : 0;
+        if (every > 0) period = lcm_ll(period, every);
+        if (ctx->tune.rebuild_every > 0) period = lcm_ll(period, ctx->tune.rebuild_every);
+        const long long K = ((ctx->tune.graph_steps + period - 1) / period) * period;
+        const long long nblk = (nsteps - 1) / K;
+        if (nblk > 0 && K <= 1 << 20) {
+          if ((e = ensure_graph(ctx, ph, lpa, (int)K, thermostat, every)) != hipSuccess) return fail_hip(ctx, e);
+          for (long long b = 0; b < nblk; ++b) {
+            if ((e = hipGraphLaunch(ctx->gexec, s)) != hipSuccess) return fail_hip(ctx, e);
+            if (every > 0) {
+              const size_t rows = (size_t)(K / every), first = (size_t)(b * K / every);
+              if ((e = hipMemcpyAsync(thermo + first * ctx->R * kNQ, ctx->ring, rows * ctx->R * kNQ * sizeof(double),
+                                      hipMemcpyDeviceToDevice, s)) != hipSuccess)
+                return fail_hip(ctx, e);
+            }
+          }
+          t_first = (int)(nblk * K) + 1;
+        }
+      }
+      for (int t = t_first; t <= (persistent ? 0 : nsteps); ++t) {
         const bool rec = thermo && (t % thermo_every == 0);
         double* row = rec ? thermo + (size_t)(t / thermo_every - 1) * ctx->R * kNQ : nullptr;
-        const int force_rb = ctx->tune.rebuild_every > 0 && (t % ctx->tune.rebuild_every == 0);
         const bool timed = samples < max_samples && !rec && t % period == 0;
         KTimer tm_m, tm_f;
         if (timed) {
@@ -487,16 +575,7 @@ int sw_step(sw_ctx* ctx, float* x, float* v, float* f, const sw_params* params, 
           tm_f = KTimer{ctx->tev[4 * samples + 2], ctx->tev[4 * samples + 3]};
           ++samples;
         }
-        if ((e = launch_moments(ctx->d, ph, lpa, par, force_rb, rec, s, tm_m)) != hipSuccess) return fail_hip(ctx, e);
-        if (thermostat == SW_NVE) {
-          const int mode = t == nsteps ? MODE_NVE_LAST : MODE_NVE;
-          if ((e = launch_forces(ctx->d, ph, lpa, mode, rec, par, row, s, tm_f)) != hipSuccess) return fail_hip(ctx, e);
-        } else {
-          if ((e = launch_forces(ctx->d, ph, lpa, MODE_KICK, rec, par, row, s, tm_f)) != hipSuccess)
-            return fail_hip(ctx, e);
-        }
-        if (thermostat != SW_NVE &&
-            (e = launch_thermostat(ctx->d, ph, par, t == nsteps, s)) != hipSuccess)
+        if ((e = enqueue_step(ctx, ph, lpa, t, nsteps, thermostat, rec, row, s, tm_m, tm_f)) != hipSuccess)
           return fail_hip(ctx, e);
       }
     }

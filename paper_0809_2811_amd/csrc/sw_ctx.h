@@ -34,6 +34,14 @@ struct sw_ctx {
   int *d_key = nullptr, *d_scnt = nullptr, *d_sstart = nullptr, *d_scur = nullptr, *d_order = nullptr;
   Tan t{};
   unsigned* d_bar = nullptr;       // grid barrier counter of the persistent launch
+  // captured block of steps (graph_steps > 0)
+  hipStream_t cap_stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  std::vector<unsigned char> gkey;
+  double* ring = nullptr;          // thermo rows of one captured block
+  size_t ring_rows = 0;
+  int alloc_gen = 0;               // bumped whenever capacity buffers move
   int last_grid = 0;               // blocks of the last persistent launch
   bool have_order = false;
   long long steps = 0;

@@ -751,12 +751,16 @@ hipError_t moments_lpa(const Dev& d, const Phys& p, int par, int force_rebuild, 
   constexpr int APB = kBlock / LPA;
   const uint32_t lds = (uint32_t)(sizeof(int) * (2 * (size_t)APB * d.cap + APB + 56 * (size_t)APB));
   const unsigned grid = (unsigned)(d.npad / APB);
-  if (energy)
+  if (!tm.start && !tm.stop) {   // plain launch (also the form used under graph capture)
+    if (energy) hipLaunchKernelGGL((k_moments<LPA, true>), dim3(grid), dim3(kBlock), lds, s, d, p, par, force_rebuild);
+    else hipLaunchKernelGGL((k_moments<LPA, false>), dim3(grid), dim3(kBlock), lds, s, d, p, par, force_rebuild);
+  } else if (energy) {
     hipExtLaunchKernelGGL((k_moments<LPA, true>), dim3(grid), dim3(kBlock), lds, s, tm.start, tm.stop, 0u, d, p,
                           par, force_rebuild);
-  else
+  } else {
     hipExtLaunchKernelGGL((k_moments<LPA, false>), dim3(grid), dim3(kBlock), lds, s, tm.start, tm.stop, 0u, d, p,
                           par, force_rebuild);
+  }
   return hipGetLastError();
 }
 
@@ -765,12 +769,16 @@ hipError_t forces_mode(const Dev& d, const Phys& p, int vir, int par, double* ri
                        const KTimer& tm) {
   constexpr int APB = kBlock / LPA;
   const unsigned grid = (unsigned)(d.npad / APB);
-  if (vir)
+  if (!tm.start && !tm.stop) {
+    if (vir) hipLaunchKernelGGL((k_forces<LPA, MODE, true>), dim3(grid), dim3(kBlock), 0, s, d, p, par);
+    else hipLaunchKernelGGL((k_forces<LPA, MODE, false>), dim3(grid), dim3(kBlock), 0, s, d, p, par);
+  } else if (vir) {
     hipExtLaunchKernelGGL((k_forces<LPA, MODE, true>), dim3(grid), dim3(kBlock), 0u, s, tm.start, tm.stop, 0u, d, p,
                           par);
-  else
+  } else {
     hipExtLaunchKernelGGL((k_forces<LPA, MODE, false>), dim3(grid), dim3(kBlock), 0u, s, tm.start, tm.stop, 0u, d,
                           p, par);
+  }
   if (vir || MODE == MODE_KICK)
     hipLaunchKernelGGL(k_reduce_thermo, dim3((unsigned)min(d.R * kNQ, 4096)), dim3(kBlock), 0, s, d, APB, ring_row);
   return hipGetLastError();

@@ -477,7 +477,7 @@ int sw_grad(sw_ctx* ctx, const float* x, const float* w, const sw_params* params
             double* dU, void* stream) {
   if (!ctx || !x || !w || !hvp) return SW_EINVAL;
   hipStream_t s = (hipStream_t)stream;
-  Phys ph;
+  Phys ph{};
   int st = make_phys(ctx, params, 1.0, 1.0, &ph);
   if (st != SW_OK) return st;
   const int lpa = lpa_for(ctx);
@@ -519,7 +519,7 @@ int sw_adjoint(sw_ctx* ctx, const float* x0, const float* v0, const sw_params* p
   if (!(mass > 0.0) || !(dt > 0.0) || nsteps < 0 || ckpt_every <= 0 || !std::isfinite(aU) || !std::isfinite(a3))
     return SW_EINVAL;
   hipStream_t s = (hipStream_t)stream;
-  Phys ph;
+  Phys ph{};
   int st = make_phys(ctx, params, mass, dt, &ph);
   if (st != SW_OK) return st;
   const int lpa = lpa_for(ctx);

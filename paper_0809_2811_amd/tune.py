@@ -99,17 +99,23 @@ def search(n_cells: int, rho: float = 1.0, skins=(0.5, 0.7, 1.0, 1.3), steps: in
             dt = _timed(ctx, x0.clone(), v0.clone(), steps)
             results.append(dict(skin=skin, lanes_per_atom=lpa, persistent=0, s_per_step=dt))
     win = min(results, key=lambda r: r["s_per_step"])
-    # the persistent form at the winning point
-    ctx = sw.Context([0, n], [box], cutoff=RC, skin=win["skin"], nbr_capacity=64,
-                     tuning=dict(DEFAULT, lanes_per_atom=win["lanes_per_atom"], persistent=1))
-    results.append(dict(skin=win["skin"], lanes_per_atom=win["lanes_per_atom"], persistent=1,
-                        s_per_step=_timed(ctx, x0.clone(), v0.clone(), steps)))
+    # the persistent form and captured step blocks at the winning point
+    for extra in (dict(persistent=1), dict(graph_steps=50)):
+        tun = dict(DEFAULT, lanes_per_atom=win["lanes_per_atom"])
+        tun.update(extra)
+        ctx = sw.Context([0, n], [box], cutoff=RC, skin=win["skin"], nbr_capacity=64, tuning=tun)
+        rec = dict(skin=win["skin"], lanes_per_atom=win["lanes_per_atom"], persistent=0, graph_steps=0)
+        rec.update(extra)
+        rec["s_per_step"] = _timed(ctx, x0.clone(), v0.clone(), steps)
+        results.append(rec)
     win = min(results, key=lambda r: r["s_per_step"])
     by_skin = {}
     for skin in skins:
-        c = min((r for r in results if r["skin"] == skin and r["persistent"] == 0), key=lambda r: r["s_per_step"])
+        c = min((r for r in results if r["skin"] == skin and r["persistent"] == 0 and not r.get("graph_steps")),
+                key=lambda r: r["s_per_step"])
         by_skin[f"{skin:.2f}"] = dict(lanes_per_atom=c["lanes_per_atom"], s_per_step=c["s_per_step"])
-    entry = dict(best=dict(lanes_per_atom=win["lanes_per_atom"], skin=win["skin"], persistent=win["persistent"]),
+    entry = dict(best=dict(lanes_per_atom=win["lanes_per_atom"], skin=win["skin"], persistent=win["persistent"],
+                           graph_steps=win.get("graph_steps", 0)),
                  s_per_step=win["s_per_step"], by_skin=by_skin, n_atoms=n, candidates=results)
     if write:
         cache = load_cache()
@@ -130,13 +136,15 @@ def search_replicas(steps: int = 300, skin: float = 1.0, write: bool = True):
     prep.step(x0, v0, 500, thermostat=sw.SW_RESCALE, T0=[400.0] * len(boxes))
     results = []
     for lpa in (4, 8, 16):
-        for persistent in (0, 1):
+        for persistent, graph_steps in ((0, 0), (1, 0), (0, 50)):
             ctx = sw.Context(off, boxes, cutoff=RC, skin=skin, nbr_capacity=64,
-                             tuning=dict(DEFAULT, lanes_per_atom=lpa, persistent=persistent))
+                             tuning=dict(DEFAULT, lanes_per_atom=lpa, persistent=persistent, graph_steps=graph_steps))
             dt = _timed(ctx, x0.clone(), v0.clone(), steps, thermostat=sw.SW_BERENDSEN, T0=T, tau_fs=1000.0)
-            results.append(dict(skin=skin, lanes_per_atom=lpa, persistent=persistent, s_per_step=dt))
+            results.append(dict(skin=skin, lanes_per_atom=lpa, persistent=persistent, graph_steps=graph_steps,
+                                s_per_step=dt))
     win = min(results, key=lambda r: r["s_per_step"])
-    entry = dict(best=dict(lanes_per_atom=win["lanes_per_atom"], skin=skin, persistent=win["persistent"]),
+    entry = dict(best=dict(lanes_per_atom=win["lanes_per_atom"], skin=skin, persistent=win["persistent"],
+                           graph_steps=win["graph_steps"]),
                  s_per_step=win["s_per_step"], by_skin={f"{skin:.2f}": dict(lanes_per_atom=win["lanes_per_atom"],
                                                                          s_per_step=win["s_per_step"])},
                  n_atoms=int(off[-1]), candidates=results)

@@ -168,3 +168,32 @@ def test_persistent_launch_equals_launch_per_phase(thermostat):
         out.append((from_dev(xd), from_dev(vd), from_dev(f), th.cpu().numpy(), ctx.query(sw.SW_Q_REBUILDS)))
     for k in range(5):
         assert np.array_equal(out[0][k], out[1][k]), k
+
+
+@pytest.mark.parametrize("thermostat", ["nve", "berendsen"])
+def test_graph_replays_equal_plain_launches(thermostat):
+    """Blocks of steps replayed from a captured hipGraph give bitwise the
+    results of plain launches, on every replay: the same context runs three
+    calls in a row with eager work and synchronisations in between."""
+    import torch
+    from paper_0809_2811_amd import sw
+    x, v, L = liquid(2)
+    x, v = f32(x), f32(v)
+    kw = dict(thermo_every=5)
+    if thermostat == "berendsen":
+        kw.update(thermostat=sw.SW_BERENDSEN, T0=[320.0], tau_fs=100.0)
+    runs = {}
+    for graph_steps in (0, 10):
+        ctx = make_ctx(x, L, skin=0.6, graph_steps=graph_steps, rebuild_every=5)
+        xd, vd = to_dev(x), to_dev(v)
+        out = []
+        for call in range(3):
+            f, th = ctx.step(xd, vd, 37, **kw)
+            out.append((from_dev(xd), from_dev(vd), from_dev(f), th.cpu().numpy()))
+            junk = torch.randn(1000, device="cuda").sum()      # eager work between replays
+            torch.cuda.synchronize()
+            assert torch.isfinite(junk)
+        runs[graph_steps] = out
+    for call in range(3):
+        for k in range(4):
+            assert np.array_equal(runs[0][call][k], runs[10][call][k]), (call, k)
