@@ -227,24 +227,41 @@ __device__ void moments_tile(const Dev& d, const Phys& p, int par, int force_reb
     const int cz = (int)__umulhi(ui.z, (unsigned)n2);
     const int* gc = d.gcnt[par];
     const uint4* gm = d.gmem[par];
-    if (real) {
-      for (int c = lane; c < 27; c += LPA) {   // independent count loads
+    // Lane l owns the contiguous cells [l*CPL, (l+1)*CPL): it loads their
+    // counts (independent loads), and a shuffle scan over the group gives
+    // every cell's prefix.
+    constexpr int CPL = (27 + LPA - 1) / LPA;
+    int mc[CPL];
+    int own = 0;
+#pragma unroll
+    for (int q = 0; q < CPL; ++q) {
+      const int c = lane * CPL + q;
+      mc[q] = 0;
+      if (real && c < 27) {
         int xx = cx + c / 9 - 1, yy = cy + (c / 3) % 3 - 1, zz = cz + c % 3 - 1;
         xx = xx < 0 ? xx + n0 : (xx >= n0 ? xx - n0 : xx);
         yy = yy < 0 ? yy + n1 : (yy >= n1 ? yy - n1 : yy);
         zz = zz < 0 ? zz + n2 : (zz >= n2 ? zz - n2 : zz);
         const int cell = R.cell_off + (xx * n1 + yy) * n2 + zz;
         cid[c] = cell;
-        pre[c + 1] = min(gc[cell], d.cc);
+        mc[q] = min(gc[cell], d.cc);
       }
+      own += mc[q];
     }
-    __syncthreads();
-    if (real && lane == 0) {
-      int run = 0;
-      pre[0] = 0;
-      for (int c = 0; c < 27; ++c) {
-        run += pre[c + 1];
-        pre[c + 1] = run;
+    int incl = own;                          // inclusive scan of the lanes' totals
+#pragma unroll
+    for (int off = 1; off < LPA; off <<= 1) {
+      const int up = __shfl_up(incl, off, LPA);
+      if (lane >= off) incl += up;
+    }
+    if (real) {
+      int run = incl - own;
+      if (lane == 0) pre[0] = 0;
+#pragma unroll
+      for (int q = 0; q < CPL; ++q) {
+        const int c = lane * CPL + q;
+        run += mc[q];
+        if (c < 27) pre[c + 1] = run;
       }
     }
     __syncthreads();
