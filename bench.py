@@ -31,18 +31,25 @@ RC = 1.8 * 2.3925
 PEAK_FP32_VALU = 78.6e12   # 256 CU x 64 lanes x 2 flop (FMA) x 2.4 GHz, non-packed FP32
 PEAK_HBM = 8.0e12
 
-# Algorithmic work of the force kernel (k_forces, NVE mode), counted from its
-# source: per active directed pair (r < a sigma) 120 flop incl. 4
-# transcendentals; per row entry beyond a sigma 14 flop (distance test);
-# per atom 30 flop (group reduction, two half-kicks, drift).  Bytes per atom:
-# own position, moments, row length and row, force, velocity, new position,
-# binning slot: 16+48+4+4*row+16+32+16+8.
+# Algorithmic work per launch, counted from the kernel sources.
+# k_forces (NVE mode): per active directed pair (r < a sigma) 120 flop
+# including 4 transcendentals; per row entry beyond a sigma 14 flop (distance
+# test); per atom 30 flop (group reduction, two half-kicks, drift).  Bytes per
+# atom: own position, own moments, row length and row, force, velocity in and
+# out, new position, binning slot: 16+48+4+4*row+16+32+16+8.
 FLOP_PER_ACTIVE = 120.0
 FLOP_PER_INACTIVE = 14.0
 FLOP_PER_ATOM = 30.0
-# Moments kernel: 44 flop incl. 3 transcendentals per active pair, 14 per
-# inactive entry, 20 per atom.
+# k_moments: 44 flop incl. 3 transcendentals per active pair, 14 per inactive
+# entry, 20 per atom; bytes per atom: position, row length and row, moments
+# out (16+4+4*row+48).  On a rebuild step add 12 flop per candidate of the 27
+# cells and, per atom, the cell slot read, the row written and the reference
+# position (16+4*row+4+16).
 MOM_FLOP_PER_ACTIVE = 44.0
+MOM_FLOP_PER_ATOM = 20.0
+REBUILD_FLOP_PER_CAND = 12.0
+COUNTERS = os.path.join(ROOT, "paper_0809_2811_amd", "hbm_counters.json")
+KERNEL_SOURCES = ("sw_kernels.hip", "sw_device.h", "sw_internal.h")
 
 
 def number_density(rho_gcc=1.0, mass=18.015):
@@ -63,6 +70,44 @@ def force_kernel_work(n_atoms, rho_gcc, skin):
     return flop, bytes_
 
 
+def moments_kernel_work(n_atoms, rho_gcc, skin, box, rebuild_frac):
+    """Average over launches; rebuild_frac of them rebuild the rows."""
+    act, row = expected_counts(rho_gcc, skin)
+    ncell = [max(3, int(np.floor(b / (RC + skin)))) for b in np.atleast_1d(box) * np.ones(3)]
+    cand = 27.0 * number_density(rho_gcc) * np.prod([b / c for b, c in zip(np.atleast_1d(box) * np.ones(3), ncell)])
+    flop = n_atoms * (act * MOM_FLOP_PER_ACTIVE + (row - act) * FLOP_PER_INACTIVE + MOM_FLOP_PER_ATOM
+                      + rebuild_frac * cand * REBUILD_FLOP_PER_CAND)
+    bytes_ = n_atoms * (16 + 4 + 4 * row + 48 + rebuild_frac * (16 + 4 * row + 4 + 16))
+    return flop, bytes_
+
+
+def kernel_sources_digest():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_0809_2811_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, each scaled by the same
+    counter's reading for a plain copy of known size) recorded for this
+    kernel and workload, or None when no record exists or the kernel sources
+    changed since the counters were taken."""
+    try:
+        with open(COUNTERS) as fh:
+            rec = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_sources_sha256") != kernel_sources_digest():
+        return None
+    ent = rec.get("kernels", {}).get(f"{workload}/{kernel}")
+    if not ent:
+        return None
+    return ent["fetch_bytes"] * rec["fetch_scale"] + ent["write_bytes"] * rec["write_scale"]
+
+
 def sync():
     import torch
     torch.cuda.synchronize()
@@ -80,7 +125,7 @@ def prepare_liquid(cfg, skin, tuning):
     return ctx, x, v
 
 
-def timed_nve(ctx, x, v, steps, thermo_every=100, timing=50):
+def timed_nve(ctx, x, v, steps, thermo_every=100, timing=49):
     from paper_0809_2811_amd import sw
     ctx.set_tuning(timing=timing)
     r0 = ctx.query(sw.SW_Q_REBUILDS)
@@ -103,13 +148,38 @@ def timed_nve(ctx, x, v, steps, thermo_every=100, timing=50):
     return out
 
 
-def roofline(n_atoms, rho, skin, kernel_us):
-    flop, bytes_ = force_kernel_work(n_atoms, rho, skin)
-    achieved = flop / (kernel_us * 1e-6)
-    return {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32_VALU / 1e12, "unit": "TFLOP/s",
-            "frac": achieved / PEAK_FP32_VALU, "traffic": None, "kernel": "k_forces (NVE mode)",
-            "kernel_us": kernel_us, "flop_per_launch": flop, "alg_bytes_per_launch": bytes_,
-            "hbm_frac_alg": bytes_ / (kernel_us * 1e-6) / PEAK_HBM}
+def kernel_roofline(kernel, flop, bytes_, kernel_us, workload):
+    """Roofline entry of one kernel: the bound is the roof the algorithmic
+    counts reach first (bytes at 8 TB/s against flop at the non-packed FP32
+    vector peak)."""
+    sec = kernel_us * 1e-6
+    t_alu, t_hbm = flop / PEAK_FP32_VALU, bytes_ / PEAK_HBM
+    traffic = measured_traffic(kernel, workload)
+    out = {"kernel": kernel, "kernel_us": kernel_us, "flop_per_launch": flop, "alg_bytes_per_launch": bytes_,
+           "alu_frac": flop / sec / PEAK_FP32_VALU, "hbm_frac": bytes_ / sec / PEAK_HBM}
+    if t_hbm >= t_alu:
+        out.update(bound="hbm", achieved=bytes_ / sec / 1e9, peak=PEAK_HBM / 1e9, unit="GB/s",
+                   frac=bytes_ / sec / PEAK_HBM)
+    else:
+        out.update(bound="alu", achieved=flop / sec / 1e12, peak=PEAK_FP32_VALU / 1e12, unit="TFLOP/s",
+                   frac=flop / sec / PEAK_FP32_VALU)
+    out["traffic"] = traffic
+    return out
+
+
+def step_rooflines(n_atoms, rho, skin, box, res, steps, lpa, workload):
+    """Both kernels of the step; the dominant one (longest average launch)
+    becomes the line's roofline, the other is kept under "other"."""
+    ff, fb = force_kernel_work(n_atoms, rho, skin)
+    mf, mb = moments_kernel_work(n_atoms, rho, skin, box, min(1.0, res["rebuilds"] / max(steps, 1)))
+    kf = kernel_roofline(f"k_forces<{lpa}, 2, false>", ff, fb, res["forces_us"], workload)
+    km = kernel_roofline(f"k_moments<{lpa}, false>", mf, mb, res["moments_us"], workload)
+    dom, other = (kf, km) if res["forces_us"] >= res["moments_us"] else (km, kf)
+    order = ("bound", "achieved", "peak", "unit", "frac", "traffic")
+    line = {k: dom[k] for k in order}
+    line.update({k: v for k, v in dom.items() if k not in order})
+    line["other"] = other
+    return line
 
 
 def cpu_baseline(target_s=15.0):
@@ -141,6 +211,9 @@ def main():
     ap.add_argument("--lpa", type=int, default=0, help="lanes per atom (0 = tuned default)")
     ap.add_argument("--forms", default="large,batched,adjoint", help="comma list of large,batched,adjoint or none")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="first run a plain FP32 copy-like kernel (out = -in) over this many MiB, three times: "
+                         "the known-size reference for scaling HBM byte counters")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on one GPU only: this engine has no multi-GPU path (see DESIGN.md for how "
@@ -149,6 +222,13 @@ def main():
     import torch
     from paper_0809_2811_amd import synth, tune
     torch.cuda.init()
+    if args.copy_mib > 0:
+        src = torch.ones(args.copy_mib << 18, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            torch.neg(src, out=dst)
+        sync()
+        del src, dst
 
     cfg = synth.config(1)
     n = len(cfg["x"])
@@ -173,8 +253,8 @@ def main():
                    "thermo_every": 100},
     }
     if "forces_us" in res:
-        line["roofline"] = roofline(n, 1.0, args.skin, res["forces_us"])
-        line["roofline"]["moments_us"] = res["moments_us"]
+        line["roofline"] = step_rooflines(n, 1.0, args.skin, cfg["box"], res, args.steps,
+                                          tuning["lanes_per_atom"], "liquid4096")
     forms = [f for f in args.forms.split(",") if f and f != "none"]
     line["forms"] = {}
     if "large" in forms:
@@ -206,8 +286,8 @@ def bench_large(steps=1000, skin=0.5):
            "workload": "large_box: 262144 atoms, 298 K liquid, NVE dt=10 fs, 0.5 A skin, rows rebuilt at "
                        "least every 10 steps"}
     if "forces_us" in res:
-        out["roofline"] = roofline(n, 1.0, skin, res["forces_us"])
-        out["roofline"]["moments_us"] = res["moments_us"]
+        out["roofline"] = step_rooflines(n, 1.0, skin, cfg["box"], res, steps, tuning["lanes_per_atom"],
+                                         "liquid262144")
     return out
 
 

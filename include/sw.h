@@ -175,7 +175,7 @@ int sw_adjoint(sw_ctx* ctx, const float* x0, const float* v0, const sw_params* p
 
 /* Execution options (chosen by the autotuner). */
 typedef struct sw_tuning {
-  int lanes_per_atom;   /* 4, 8 or 16 lanes of a wavefront share one atom      */
+  int lanes_per_atom;   /* 4, 8, 16 or 32 lanes of a wavefront share one atom  */
   int graph_steps;      /* steps per captured hipGraph (0 = plain launches)    */
   int persistent;       /* 0: one launch per phase; 1: sw_step's steps run in one
                            cooperative persistent launch at full occupancy;
@@ -184,7 +184,9 @@ typedef struct sw_tuning {
                            displacement)                                        */
   int timing;           /* > 0: every timing-th step of sw_step, bracket the
                            moments and force launches with HIP events and add
-                           their durations to the SW_Q_TIME_* counters          */
+                           their durations to the SW_Q_TIME_* counters (an odd
+                           period samples steps of both parities, so rebuild
+                           steps are sampled at their own rate)                 */
 } sw_tuning;
 int sw_set_tuning(sw_ctx* ctx, const sw_tuning* t);
 int sw_get_tuning(const sw_ctx* ctx, sw_tuning* t);

@@ -51,8 +51,9 @@ void free_list(std::vector<void*>& list) {
 
 int lpa_for(const sw_ctx* c) {
   int lpa = c->tune.lanes_per_atom;
-  // rebuild staging needs 2 * (256 / lpa) * cap ints of LDS; keep it <= 64 KiB
-  while (lpa < 16 && 2 * (kBlock / lpa) * c->cap * 4 + 57 * 4 * (kBlock / lpa) > 65536) lpa *= 2;
+  // the rebuild's LDS staging grows with atoms per block and row capacity;
+  // keep it within 64 KiB per block
+  while (lpa < kMaxLPA && moments_lds_bytes(kBlock / lpa, c->cap) > 65536) lpa *= 2;
   return lpa;
 }
 
@@ -78,7 +79,7 @@ hipError_t alloc_all(sw_ctx* c) {
   SWA(c->d.u[0], np); SWA(c->d.u[1], np); SWA(c->d.v, np); SWA(c->d.f, np); SWA(c->d.uref, np);
   SWA(c->d.ids, np); SWA(c->d.nn, np); SWA(c->d.mom, 3 * np);
   SWA(c->d.gcnt[0], (size_t)c->ctot); SWA(c->d.gcnt[1], (size_t)c->ctot);
-  SWA(c->d.partial, (np / 16 + 1) * kNQ);
+  SWA(c->d.partial, (np / kMinAPB + 1) * kNQ);   // one slot per block and quantity
   SWA(c->d.thermo_cur, (size_t)c->R * kNQ);
   SWA(c->d.arrive, (size_t)c->R);
   SWA(c->d.dflag, 2 * (size_t)c->R);
@@ -92,7 +93,7 @@ hipError_t alloc_all(sw_ctx* c) {
   SWA(c->d_uq, (size_t)c->N); SWA(c->d_key, (size_t)c->N); SWA(c->d_order, (size_t)c->N);
   SWA(c->d_scnt, (size_t)c->ctot); SWA(c->d_sstart, (size_t)c->ctot); SWA(c->d_scur, (size_t)c->ctot);
   SWA(c->t.w, np); SWA(c->t.mdot, 3 * np); SWA(c->t.fdot, np); SWA(c->t.f3, np);
-  SWA(c->t.tpartial, (np / 16 + 1) * kTQ);
+  SWA(c->t.tpartial, (np / kMinAPB + 1) * kTQ);
   SWA(c->t.tsum, (size_t)c->R * kTQ);
 #undef SWA
   if ((e = alloc_capacity(c)) != hipSuccess) return e;
@@ -398,7 +399,8 @@ void sw_destroy(sw_ctx* ctx) {
 
 int sw_set_tuning(sw_ctx* ctx, const sw_tuning* t) {
   if (!ctx || !t) return SW_EINVAL;
-  if (t->lanes_per_atom != 4 && t->lanes_per_atom != 8 && t->lanes_per_atom != 16) return SW_EUNSUPPORTED;
+  if (t->lanes_per_atom != 4 && t->lanes_per_atom != 8 && t->lanes_per_atom != 16 && t->lanes_per_atom != 32)
+    return SW_EUNSUPPORTED;
   if (t->graph_steps < 0 || t->rebuild_every < 0 || t->timing < 0 || t->persistent < 0) return SW_EINVAL;
   ctx->tune = *t;
   ctx->t_mom_ms = ctx->t_for_ms = 0.0;

@@ -22,7 +22,15 @@ namespace swk {
 
 constexpr int kBlock = 256;        // threads per block of every atom kernel
 constexpr int kTile = 64;          // replicas are padded to multiples of this
+constexpr int kMaxLPA = 32;        // most lanes per atom of any kernel variant
+constexpr int kMinAPB = kBlock / kMaxLPA;   // fewest atoms per block: sizes per-block buffers
 constexpr int kNQ = 12;            // thermo quantities per replica
+// Row rebuild staging in LDS (moments kernel), per block: candidate and
+// sorted rows [2][APB][cap] ints, row counts [APB], per-atom cell prefix and
+// cell ids [APB][56].
+__host__ __device__ constexpr size_t moments_lds_bytes(int apb, int cap) {
+  return sizeof(int) * (2 * (size_t)apb * cap + apb + 56 * (size_t)apb);
+}
 constexpr double kAcc = 4.184e-4;  // (A/fs^2) per ((kcal/mol/A)/(g/mol))
 constexpr double kBoltz = 8.314462618 / 4184.0;  // kcal/(mol K)
 constexpr double kTwo32 = 4294967296.0;

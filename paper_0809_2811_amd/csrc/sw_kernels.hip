@@ -29,26 +29,39 @@
 namespace swk {
 namespace {
 
+// Replica geometry the integrator needs, read into registers before the
+// kernel's first store (later reads could not be hoisted above the stores).
+struct Geo {
+  float sc0, sc1, sc2, is0, is1, is2;
+  int nc0, nc1, nc2, cell_off;
+};
+
+__device__ __forceinline__ Geo geo_of(const RepInfo& R) {
+  return Geo{R.scale[0], R.scale[1], R.scale[2], R.inv_scale[0], R.inv_scale[1], R.inv_scale[2],
+             R.nc[0], R.nc[1], R.nc[2], R.cell_off};
+}
+
 // Drift by dt*v in fraction units, bin into grid `gp`, and raise the
 // replica's rebuild flag if the atom is now more than half the skin away from
 // its row-build position.  Flags steps longer than a quarter edge.
-__device__ __forceinline__ void drift_bin(const Dev& d, const Phys& p, const RepInfo& R, int rep, int i,
-                                          uint4 u, const float4& v, int gp) {
-  const float mx = p.dt * v.x * R.inv_scale[0];
-  const float my = p.dt * v.y * R.inv_scale[1];
-  const float mz = p.dt * v.z * R.inv_scale[2];
+__device__ __forceinline__ void drift_bin(const Dev& d, const Phys& p, const Geo& G, int rep, int i, uint4 u,
+                                          const float4& v, const uint4& uref, int gp) {
+  const float mx = p.dt * v.x * G.is0;
+  const float my = p.dt * v.y * G.is1;
+  const float mz = p.dt * v.z * G.is2;
   const float lim = 1073741824.0f;  // 2^30: a quarter of the edge
   if (!(fabsf(mx) < lim && fabsf(my) < lim && fabsf(mz) < lim)) atomicOr(&d.flags[F_OVERLAP], 2);
   u.x += (unsigned)__float2int_rn(fminf(fmaxf(mx, -lim), lim));
   u.y += (unsigned)__float2int_rn(fminf(fmaxf(my, -lim), lim));
   u.z += (unsigned)__float2int_rn(fminf(fmaxf(mz, -lim), lim));
+  const float3 dd = disp(uref, u, G.sc0, G.sc1, G.sc2);
+  const bool moved = dd.x * dd.x + dd.y * dd.y + dd.z * dd.z > p.half_skin * p.half_skin;
   d.u[gp][i] = u;
-  const int c = R.cell_off + cell_of(u, R.nc[0], R.nc[1], R.nc[2]);
+  const int c = G.cell_off + cell_of(u, G.nc0, G.nc1, G.nc2);
   const int slot = atomicAdd(&d.gcnt[gp][c], 1);
+  if (moved) d.dflag[gp * d.R + rep] = 1;
   if (slot < d.cc) d.gmem[gp][(size_t)c * d.cc + slot] = make_uint4(u.x, u.y, u.z, (unsigned)i);
   else atomicOr(&d.flags[F_CELL_OVER], 1);
-  const float3 dd = disp(d.uref[i], u, R.scale[0], R.scale[1], R.scale[2]);
-  if (dd.x * dd.x + dd.y * dd.y + dd.z * dd.z > p.half_skin * p.half_skin) d.dflag[gp * d.R + rep] = 1;
 }
 
 // ----------------------------------------------------------------- sorting
@@ -200,19 +213,31 @@ __device__ __forceinline__ void clear_next(const Dev& d, int par, int b, int G) 
 template <int LPA, bool ENERGY>
 __device__ void moments_tile(const Dev& d, const Phys& p, int par, int force_rebuild, int bid, int* lds) {
   constexpr int APB = kBlock / LPA;
+  // row slots per lane per batch: a batch spans at most 32 slots, one
+  // 128-byte line of the row
+  constexpr int kMU = LPA >= 32 ? 1 : (32 / LPA < 4 ? 32 / LPA : 4);
   const int g = threadIdx.x / LPA, lane = threadIdx.x % LPA;
   const int i = bid * APB + g;
   const int rep = d.tile_rep[(bid * APB) >> 6];
   const RepInfo& R = d.reps[rep];
-  const float sc0 = R.scale[0], sc1 = R.scale[1], sc2 = R.scale[2];
-
-  // each replica rebuilds on its own displacement record
-  const bool rebuild = force_rebuild || d.dflag[par * d.R + rep] != 0;
-  const bool real = i < R.iend;
+  // Every load that does not depend on another is issued up front, before
+  // the kernel's first store: geometry, own position, rebuild flag, row
+  // length and the first batch of row slots (slots below the capacity are
+  // always addressable; they are masked by the row length later).
+  const Geo G = geo_of(R);
+  const int iend = R.iend, ioff = R.ioff;
+  const float sc0 = G.sc0, sc1 = G.sc1, sc2 = G.sc2;
+  const bool real = i < iend;
   const uint4 ui = d.u[par][i];
   const int cap = d.cap;
-  int nn = 0;
   const int* row = d.nl + (size_t)i * cap;
+  int jn[kMU];
+#pragma unroll
+  for (int u = 0; u < kMU; ++u) jn[u] = row[min(lane + u * LPA, cap - 1)];
+  const int nn_row = real ? d.nn[i] : 0;
+  // each replica rebuilds on its own displacement record
+  const bool rebuild = force_rebuild || d.dflag[par * d.R + rep] != 0;
+  int nn = nn_row;
 
   if (rebuild) {                           // block-uniform
     int* cand = lds + g * cap;
@@ -221,33 +246,38 @@ __device__ void moments_tile(const Dev& d, const Phys& p, int par, int force_reb
     int* pre = lds + 2 * APB * cap + APB + g * 56;   // [28] prefix of cell counts
     int* cid = pre + 28;                             // [27] cell ids
     if (lane == 0) cnt[g] = 0;
-    const int n0 = R.nc[0], n1 = R.nc[1], n2 = R.nc[2];
+    const int n0 = G.nc0, n1 = G.nc1, n2 = G.nc2;
     const int cx = (int)__umulhi(ui.x, (unsigned)n0);
     const int cy = (int)__umulhi(ui.y, (unsigned)n1);
     const int cz = (int)__umulhi(ui.z, (unsigned)n2);
     const int* gc = d.gcnt[par];
     const uint4* gm = d.gmem[par];
-    // Lane l owns the contiguous cells [l*CPL, (l+1)*CPL): it loads their
-    // counts (independent loads), and a shuffle scan over the group gives
-    // every cell's prefix.
+    const int ccap = d.cc;
+    // Lane l owns the contiguous cells [l*CPL, (l+1)*CPL): their counts are
+    // one batch of loads, and a shuffle scan over the group gives every
+    // cell's prefix.  Neighbouring atoms read the same cells, so these reads
+    // and the candidate reads below mostly hit the CU's L1.
     constexpr int CPL = (27 + LPA - 1) / LPA;
-    int mc[CPL];
-    int own = 0;
+    int cl[CPL], mc[CPL];
 #pragma unroll
     for (int q = 0; q < CPL; ++q) {
       const int c = lane * CPL + q;
-      mc[q] = 0;
-      if (real && c < 27) {
-        int xx = cx + c / 9 - 1, yy = cy + (c / 3) % 3 - 1, zz = cz + c % 3 - 1;
-        xx = xx < 0 ? xx + n0 : (xx >= n0 ? xx - n0 : xx);
-        yy = yy < 0 ? yy + n1 : (yy >= n1 ? yy - n1 : yy);
-        zz = zz < 0 ? zz + n2 : (zz >= n2 ? zz - n2 : zz);
-        const int cell = R.cell_off + (xx * n1 + yy) * n2 + zz;
-        cid[c] = cell;
-        mc[q] = min(gc[cell], d.cc);
-      }
-      own += mc[q];
+      int xx = cx + c / 9 - 1, yy = cy + (c / 3) % 3 - 1, zz = cz + c % 3 - 1;
+      xx = xx < 0 ? xx + n0 : (xx >= n0 ? xx - n0 : xx);
+      yy = yy < 0 ? yy + n1 : (yy >= n1 ? yy - n1 : yy);
+      zz = zz < 0 ? zz + n2 : (zz >= n2 ? zz - n2 : zz);
+      cl[q] = G.cell_off + (xx * n1 + yy) * n2 + zz;   // a valid cell for every c < 36
+      mc[q] = gc[cl[q]];
     }
+    // An unconditional use of every count keeps the compiler from sinking
+    // the loads into the masking branches below, which would serialise them.
+#pragma unroll
+    for (int q = 0; q < CPL; ++q) asm volatile("" ::"v"(mc[q]));
+#pragma unroll
+    for (int q = 0; q < CPL; ++q) mc[q] = (real && lane * CPL + q < 27) ? min(mc[q], ccap) : 0;
+    int own = 0;
+#pragma unroll
+    for (int q = 0; q < CPL; ++q) own += mc[q];
     int incl = own;                          // inclusive scan of the lanes' totals
 #pragma unroll
     for (int off = 1; off < LPA; off <<= 1) {
@@ -261,18 +291,22 @@ __device__ void moments_tile(const Dev& d, const Phys& p, int par, int force_reb
       for (int q = 0; q < CPL; ++q) {
         const int c = lane * CPL + q;
         run += mc[q];
-        if (c < 27) pre[c + 1] = run;
+        if (c < 27) {
+          pre[c + 1] = run;
+          cid[c] = cl[q];
+        }
       }
     }
     __syncthreads();
     if (real) {
       const int ncand = pre[27];
       const float rl2 = p.rl2;
-      // candidate slots k = lane + LPA*t, four per pass with independent loads
-      for (int k0 = lane; k0 < ncand; k0 += 4 * LPA) {
-        uint4 e[4];
+      // candidate slots k = lane + LPA*t, kCL per pass with independent loads
+      constexpr int kCL = 8;
+      for (int k0 = lane; k0 < ncand; k0 += kCL * LPA) {
+        uint4 e[kCL];
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
+        for (int t = 0; t < kCL; ++t) {
           const int k = k0 + t * LPA;
           e[t] = make_uint4(ui.x, ui.y, ui.z, (unsigned)i);
           if (k < ncand) {
@@ -280,11 +314,11 @@ __device__ void moments_tile(const Dev& d, const Phys& p, int par, int force_reb
 #pragma unroll
             for (int step = 16; step >= 1; step >>= 1)
               if (c + step < 27 && pre[c + step] <= k) c += step;
-            e[t] = gm[(size_t)cid[c] * d.cc + (k - pre[c])];
+            e[t] = gm[(size_t)cid[c] * ccap + (k - pre[c])];
           }
         }
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
+        for (int t = 0; t < kCL; ++t) {
           const int j = (int)e[t].w;
           const float3 dd = disp(ui, e[t], sc0, sc1, sc2);
           if (j != i && dd.x * dd.x + dd.y * dd.y + dd.z * dd.z < rl2) {
@@ -317,46 +351,45 @@ __device__ void moments_tile(const Dev& d, const Phys& p, int par, int force_reb
     __syncthreads();
     nn = real ? total : 0;
     row = srt;
-    if (bid * APB == R.ioff && threadIdx.x == 0) atomicAdd(&d.flags[F_REBUILDS], 1);
-  } else {
-    nn = real ? d.nn[i] : 0;
+#pragma unroll
+    for (int u = 0; u < kMU; ++u) jn[u] = srt[min(lane + u * LPA, cap - 1)];
+    if (bid * APB == ioff && threadIdx.x == 0) atomicAdd(&d.flags[F_REBUILDS], 1);
   }
 
   float T0 = 0.f, T1 = 0.f, T2 = 0.f, T3 = 0.f, T4 = 0.f, T5 = 0.f;
   float V0 = 0.f, V1 = 0.f, V2 = 0.f, S = 0.f, P = 0.f, E2 = 0.f;
   const uint4* upm = d.u[par];
-  // pipelined like the force loop: kMU slots' indices, then positions
-  constexpr int kMU = 4;
+  // pipelined like the force loop: a batch of slots' positions, then the
+  // arithmetic, with the next batch's slots read in between
   for (int s0 = lane; s0 < nn; s0 += kMU * LPA) {
     int jj[kMU];
 #pragma unroll
-    for (int u = 0; u < kMU; ++u) {
-      const int s = s0 + u * LPA;
-      jj[u] = s < nn ? row[s] : -1;
-    }
+    for (int u = 0; u < kMU; ++u) jj[u] = s0 + u * LPA < nn ? jn[u] : -1;
+#pragma unroll
+    for (int u = 0; u < kMU; ++u) jn[u] = row[min(s0 + (kMU + u) * LPA, nn - 1)];
     uint4 uu[kMU];
 #pragma unroll
     for (int u = 0; u < kMU; ++u) uu[u] = jj[u] >= 0 ? upm[jj[u]] : ui;
 #pragma unroll
     for (int u = 0; u < kMU; ++u) {
-    const float3 dd = disp(ui, uu[u], sc0, sc1, sc2);
-    const float r2 = dd.x * dd.x + dd.y * dd.y + dd.z * dd.z;
-    if (jj[u] >= 0 && r2 < p.rc2) {
-      const float ir = rsq(r2);
-      const float ux = dd.x * ir, uy = dd.y * ir, uz = dd.z * ir;
-      const float idr = rcp(r2 * ir - p.rc);
-      const float eg = ex2(p.gsig_l2e * idr);
-      const float ex = eg * ux, ey = eg * uy, ez = eg * uz;
-      T0 += ex * ux; T1 += ey * uy; T2 += ez * uz;
-      T3 += ex * uy; T4 += ex * uz; T5 += ey * uz;
-      V0 += ex; V1 += ey; V2 += ez; S += eg;
-      if (ENERGY) {
-        P += eg * eg;
-        const float e1 = ex2(p.sig_l2e * idr);
-        const float sr = p.sig * ir, s2 = sr * sr;
-        E2 += 0.5f * p.Aeps * (p.B * s2 * s2 - 1.f) * e1;
+      const float3 dd = disp(ui, uu[u], sc0, sc1, sc2);
+      const float r2 = dd.x * dd.x + dd.y * dd.y + dd.z * dd.z;
+      if (jj[u] >= 0 && r2 < p.rc2) {
+        const float ir = rsq(r2);
+        const float ux = dd.x * ir, uy = dd.y * ir, uz = dd.z * ir;
+        const float idr = rcp(r2 * ir - p.rc);
+        const float eg = ex2(p.gsig_l2e * idr);
+        const float ex = eg * ux, ey = eg * uy, ez = eg * uz;
+        T0 += ex * ux; T1 += ey * uy; T2 += ez * uz;
+        T3 += ex * uy; T4 += ex * uz; T5 += ey * uz;
+        V0 += ex; V1 += ey; V2 += ez; S += eg;
+        if (ENERGY) {
+          P += eg * eg;
+          const float e1 = ex2(p.sig_l2e * idr);
+          const float sr = p.sig * ir, s2 = sr * sr;
+          E2 += 0.5f * p.Aeps * (p.B * s2 * s2 - 1.f) * e1;
+        }
       }
-    }
     }
   }
   T0 = group_sum<LPA>(T0); T1 = group_sum<LPA>(T1); T2 = group_sum<LPA>(T2);
@@ -382,8 +415,8 @@ __device__ void moments_tile(const Dev& d, const Phys& p, int par, int force_reb
 template <int LPA, bool ENERGY>
 __global__ __launch_bounds__(kBlock) void k_moments(Dev d, Phys p, int par, int force_rebuild) {
   extern __shared__ int lds[];
-  clear_next(d, par, blockIdx.x, gridDim.x);
   moments_tile<LPA, ENERGY>(d, p, par, force_rebuild, xcd_remap(blockIdx.x, gridDim.x), lds);
+  clear_next(d, par, blockIdx.x, gridDim.x);
 }
 
 // ----------------------------------------------------------------- forces
@@ -391,6 +424,7 @@ __global__ __launch_bounds__(kBlock) void k_moments(Dev d, Phys p, int par, int 
 // The per-replica sums are taken by k_reduce_thermo after the kernel ends.
 template <int APB>
 __device__ void block_partials(const Dev& d, int bid, const double* q, bool writer, int g) {
+  static_assert(APB >= kMinAPB, "partial sums are sized for at least kMinAPB atoms per block");
   __shared__ double red[APB * kNQ];
   if (writer) {
 #pragma unroll
@@ -419,7 +453,8 @@ __device__ void forces_tile(const Dev& d, const Phys& p, int par, int bid) {
   const int i = bid * APB + g;
   const int rep = d.tile_rep[(bid * APB) >> 6];
   const RepInfo& R = d.reps[rep];
-  const float sc0 = R.scale[0], sc1 = R.scale[1], sc2 = R.scale[2];
+  const Geo G = geo_of(R);
+  const float sc0 = G.sc0, sc1 = G.sc1, sc2 = G.sc2;
   const bool real = i < R.iend;
   const uint4 ui = d.u[par][i];
   const float c0 = p.c0, c02 = p.c0 * p.c0;
@@ -427,32 +462,57 @@ __device__ void forces_tile(const Dev& d, const Phys& p, int par, int bid) {
   float Tm0 = 0.f, Tm1 = 0.f, Tm2 = 0.f, Tm3 = 0.f, Tm4 = 0.f, Tm5 = 0.f, Vm0 = 0.f, Vm1 = 0.f, Vm2 = 0.f,
         Sm = 0.f, E2i = 0.f, E3i = 0.f;
   int nn = 0;
+  const int* row = d.nl + (size_t)i * d.cap;
+  const uint4* up = d.u[par];
+  // Software pipelined.  Everything that does not depend on a previous load
+  // is issued first as one batch: own moments, row length, the first kFU
+  // row slots of every lane (read whatever the row length, since slots below
+  // the capacity are always addressable, and masked once it is known), and
+  // the velocity and row-build position the integrator needs.  Then, per
+  // kFU slots, the neighbours' positions and moments are one batch of
+  // independent loads before any arithmetic.  The per-lane order of
+  // neighbours is the plain stride order.
+  constexpr int kFU = LPA >= 32 ? 1 : 2;   // a batch spans at most 32 slots (one row line)
+  const int cap = d.cap;
+  int jn[kFU];
+#pragma unroll
+  for (int u = 0; u < kFU; ++u) jn[u] = row[min(lane + u * LPA, cap - 1)];
+  float4 vi = make_float4(0.f, 0.f, 0.f, 0.f);
+  uint4 urefi = make_uint4(0u, 0u, 0u, 0u);
   if (real) {
     const float4* m = d.mom + 3 * (size_t)i;
     const float4 a = m[0], b = m[1], c = m[2];
     Tm0 = a.x; Tm1 = a.y; Tm2 = a.z; Tm3 = a.w; Tm4 = b.x; Tm5 = b.y;
     Vm0 = b.z; Vm1 = b.w; Vm2 = c.x; Sm = c.y; E2i = c.z; E3i = c.w;
     nn = d.nn[i];
+    if (MODE != MODE_FORCES && lane == 0) {
+      vi = d.v[i];
+      if (MODE == MODE_START || MODE == MODE_NVE) urefi = d.uref[i];
+    }
   }
-  const int* row = d.nl + (size_t)i * d.cap;
-  const uint4* up = d.u[par];
   float fx = 0.f, fy = 0.f, fz = 0.f;
   float w0 = 0.f, w1 = 0.f, w2 = 0.f, w3 = 0.f, w4 = 0.f, w5 = 0.f;
-  // Software-pipelined over kFU row slots per lane: the slots' indices, then
-  // their positions, then the active neighbours' moments are each loaded as
-  // one batch of independent loads before any arithmetic.  The per-lane
-  // order of neighbours is the plain stride order.
-  constexpr int kFU = 2;
   for (int s0 = lane; s0 < nn; s0 += kFU * LPA) {
     int jj[kFU];
 #pragma unroll
     for (int u = 0; u < kFU; ++u) {
       const int s = s0 + u * LPA;
-      jj[u] = s < nn ? row[s] : -1;
+      jj[u] = s < nn ? jn[u] : -1;
     }
-    uint4 uu[kFU];
 #pragma unroll
-    for (int u = 0; u < kFU; ++u) uu[u] = jj[u] >= 0 ? up[jj[u]] : ui;
+    for (int u = 0; u < kFU; ++u) jn[u] = row[min(s0 + (kFU + u) * LPA, nn - 1)];   // next batch's slots
+    uint4 uu[kFU];
+    float4 mja[kFU], mjb[kFU], mjc[kFU];
+#pragma unroll
+    for (int u = 0; u < kFU; ++u) {
+      if (jj[u] >= 0) {
+        const float4* mj = d.mom + 3 * (size_t)jj[u];
+        uu[u] = up[jj[u]];
+        mja[u] = mj[0]; mjb[u] = mj[1]; mjc[u] = mj[2];
+      } else {
+        uu[u] = ui;
+      }
+    }
     float3 ddv[kFU];
     float r2v[kFU];
     bool act[kFU];
@@ -461,14 +521,6 @@ __device__ void forces_tile(const Dev& d, const Phys& p, int par, int bid) {
       ddv[u] = disp(ui, uu[u], sc0, sc1, sc2);
       r2v[u] = ddv[u].x * ddv[u].x + ddv[u].y * ddv[u].y + ddv[u].z * ddv[u].z;
       act[u] = jj[u] >= 0 && r2v[u] < p.rc2;
-    }
-    float4 mja[kFU], mjb[kFU], mjc[kFU];
-#pragma unroll
-    for (int u = 0; u < kFU; ++u) {
-      if (act[u]) {
-        const float4* mj = d.mom + 3 * (size_t)jj[u];
-        mja[u] = mj[0]; mjb[u] = mj[1]; mjc[u] = mj[2];
-      }
     }
 #pragma unroll
     for (int u = 0; u < kFU; ++u) {
@@ -547,7 +599,7 @@ __device__ void forces_tile(const Dev& d, const Phys& p, int par, int bid) {
       q[3] = w0; q[4] = w1; q[5] = w2; q[6] = w3; q[7] = w4; q[8] = w5;
     }
     if (MODE != MODE_FORCES) {
-      float4 v = d.v[i];
+      float4 v = vi;
       v.x += p.hdt_cm * F.x; v.y += p.hdt_cm * F.y; v.z += p.hdt_cm * F.z;
       if (MODE != MODE_START) {
         const float vx2 = v.x * v.x, vy2 = v.y * v.y, vz2 = v.z * v.z;
@@ -557,7 +609,7 @@ __device__ void forces_tile(const Dev& d, const Phys& p, int par, int bid) {
       if (MODE == MODE_NVE) {
         v.x += p.hdt_cm * F.x; v.y += p.hdt_cm * F.y; v.z += p.hdt_cm * F.z;
       }
-      if (MODE == MODE_START || MODE == MODE_NVE) drift_bin(d, p, R, rep, i, ui, v, par ^ 1);
+      if (MODE == MODE_START || MODE == MODE_NVE) drift_bin(d, p, G, rep, i, ui, v, urefi, par ^ 1);
       d.v[i] = v;
     }
   }
@@ -618,7 +670,7 @@ __device__ __forceinline__ void thermostat_atom(const Dev& d, const Phys& p, int
       if (!last) {
         const float4 F = d.f[i];
         v.x += p.hdt_cm * F.x; v.y += p.hdt_cm * F.y; v.z += p.hdt_cm * F.z;
-        drift_bin(d, p, R, rep, i, d.u[par][i], v, par ^ 1);
+        drift_bin(d, p, geo_of(R), rep, i, d.u[par][i], v, d.uref[i], par ^ 1);
       }
       d.v[i] = v;
     }
@@ -684,11 +736,11 @@ __global__ __launch_bounds__(kBlock) void k_persistent(Dev d, Phys p, PArgs a) {
     const bool last = t == a.nsteps;
     const int frb = a.rebuild_every > 0 && t % a.rebuild_every == 0;
     double* row = rec && a.thermo ? a.thermo + (size_t)(t / a.thermo_every - 1) * d.R * kNQ : nullptr;
-    clear_next(d, par, blockIdx.x, (int)G);
     for (int b = tlo; b < thi; ++b) {
       if (rec) moments_tile<LPA, true>(d, p, par, frb, b, lds);
       else moments_tile<LPA, false>(d, p, par, frb, b, lds);
     }
+    clear_next(d, par, blockIdx.x, (int)G);
     if (!grid_sync(a, G, k)) return;
     for (int b = tlo; b < thi; ++b) {
       if (thermostat) {
@@ -766,7 +818,7 @@ template <int LPA>
 hipError_t moments_lpa(const Dev& d, const Phys& p, int par, int force_rebuild, int energy, hipStream_t s,
                        const KTimer& tm) {
   constexpr int APB = kBlock / LPA;
-  const uint32_t lds = (uint32_t)(sizeof(int) * (2 * (size_t)APB * d.cap + APB + 56 * (size_t)APB));
+  const uint32_t lds = (uint32_t)moments_lds_bytes(APB, d.cap);
   const unsigned grid = (unsigned)(d.npad / APB);
   if (!tm.start && !tm.stop) {   // plain launch (also the form used under graph capture)
     if (energy) hipLaunchKernelGGL((k_moments<LPA, true>), dim3(grid), dim3(kBlock), lds, s, d, p, par, force_rebuild);
@@ -818,7 +870,7 @@ template <int LPA>
 hipError_t persistent_lpa(const Dev& d, const Phys& p, const PArgs& a, int blocks_per_cu, hipStream_t s,
                           int* grid_out) {
   constexpr int APB = kBlock / LPA;
-  const size_t lds = sizeof(int) * (2 * (size_t)APB * d.cap + APB + 56 * (size_t)APB);
+  const size_t lds = moments_lds_bytes(APB, d.cap);
   int per_cu = 0, dev = 0, ncu = 0;
   hipError_t e;
   if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_persistent<LPA>, kBlock, lds)) != hipSuccess)
@@ -847,6 +899,7 @@ hipError_t launch_persistent(const Dev& d, const Phys& p, int lpa, const PArgs& 
     case 4: return persistent_lpa<4>(d, p, a, blocks_per_cu, s, grid_out);
     case 8: return persistent_lpa<8>(d, p, a, blocks_per_cu, s, grid_out);
     case 16: return persistent_lpa<16>(d, p, a, blocks_per_cu, s, grid_out);
+    case 32: return persistent_lpa<32>(d, p, a, blocks_per_cu, s, grid_out);
   }
   return hipErrorInvalidValue;
 }
@@ -883,6 +936,7 @@ hipError_t launch_moments(const Dev& d, const Phys& p, int lpa, int par, int for
     case 4: return moments_lpa<4>(d, p, par, force_rebuild, energy, s, tm);
     case 8: return moments_lpa<8>(d, p, par, force_rebuild, energy, s, tm);
     case 16: return moments_lpa<16>(d, p, par, force_rebuild, energy, s, tm);
+    case 32: return moments_lpa<32>(d, p, par, force_rebuild, energy, s, tm);
   }
   return hipErrorInvalidValue;
 }
@@ -893,6 +947,7 @@ hipError_t launch_forces(const Dev& d, const Phys& p, int lpa, int mode, int vir
     case 4: return forces_lpa<4>(d, p, mode, vir, par, ring_row, s, tm);
     case 8: return forces_lpa<8>(d, p, mode, vir, par, ring_row, s, tm);
     case 16: return forces_lpa<16>(d, p, mode, vir, par, ring_row, s, tm);
+    case 32: return forces_lpa<32>(d, p, mode, vir, par, ring_row, s, tm);
   }
   return hipErrorInvalidValue;
 }

@@ -119,6 +119,7 @@ template <int LPA, bool ADJ>
 __global__ __launch_bounds__(kBlock) void k_tan_forces(Dev d, Tan t, Phys p, const float4* __restrict__ w, int par,
                                                        Adj a) {
   constexpr int APB = kBlock / LPA;
+  static_assert(APB >= kMinAPB, "tangent partials are sized for at least kMinAPB atoms per block");
   __shared__ double red[APB * kTQ];
   const int bid = xcd_remap(blockIdx.x, gridDim.x);
   const int g = threadIdx.x / LPA, lane = threadIdx.x % LPA;
@@ -338,6 +339,7 @@ hipError_t launch_tan_moments(const Dev& d, const Tan& t, const Phys& p, int lpa
     case 4: return tan_launch<4>(d, t, p, w, par, nullptr, s, true);
     case 8: return tan_launch<8>(d, t, p, w, par, nullptr, s, true);
     case 16: return tan_launch<16>(d, t, p, w, par, nullptr, s, true);
+    case 32: return tan_launch<32>(d, t, p, w, par, nullptr, s, true);
   }
   return hipErrorInvalidValue;
 }
@@ -348,6 +350,7 @@ hipError_t launch_tan_forces(const Dev& d, const Tan& t, const Phys& p, int lpa,
     case 4: return tan_launch<4>(d, t, p, w, par, adj, s, false);
     case 8: return tan_launch<8>(d, t, p, w, par, adj, s, false);
     case 16: return tan_launch<16>(d, t, p, w, par, adj, s, false);
+    case 32: return tan_launch<32>(d, t, p, w, par, adj, s, false);
   }
   return hipErrorInvalidValue;
 }

@@ -38,15 +38,19 @@ def min_image(d, L):
     return d - L * np.round(d / L)
 
 
-@pytest.mark.parametrize("which", ["ice", "liquid"])
-def test_ten_steps_match_oracle(which):
+@pytest.mark.parametrize("which,lpa", [("ice", 8), ("liquid", 8), ("liquid", 32), ("liquid4096", 32)])
+def test_ten_steps_match_oracle(which, lpa):
+    """liquid4096 at 32 lanes per atom is also the regression case for the
+    per-block partial sums, which must hold 8-atom blocks."""
     if which == "ice":
         d = synth.config(0)
         x, v, L = d["x"], d["v"], d["box"]
+    elif which == "liquid4096":
+        x, v, L = liquid(2)
     else:
         x, v, L = liquid(1, sigma=0.0)
     x, v = f32(x), f32(v)
-    xg, vg, fg, thg, _ = run_gpu(x, v, L, 10)
+    xg, vg, fg, thg, _ = run_gpu(x, v, L, 10, lpa=lpa)
     xo, vo, fo, tho = oracle.vv(x, v, L, 10, dt=10.0)
     assert np.abs(min_image(xg - xo, L)).max() < 1e-4
     assert np.abs(vg - vo).max() < 1e-5 * np.abs(vo).max() * 10
