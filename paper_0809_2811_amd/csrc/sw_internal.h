@@ -120,6 +120,7 @@ hipError_t launch_scatter_out(const Dev& d, int par, float4* x_user, float4* v_u
 hipError_t launch_copy_thermo(const Dev& d, double* energy, double* virial, hipStream_t s);
 hipError_t launch_fill_i32(int* p, int value, long long n, hipStream_t s);
 hipError_t launch_fill_f32(float* p, float value, long long n, hipStream_t s);
+hipError_t launch_fill_f64(double* p, double value, long long n, hipStream_t s);
 
 // Persistent cooperative launch of steps t0..t1 of an sw_step call.
 struct PArgs {
@@ -154,10 +155,6 @@ struct Adj {
   int S;             // trajectory steps (loss normalisation 1 / (n_r (S + 1)))
   int last;          // last frame: do not form the next direction
 };
-hipError_t launch_tan_moments(const Dev& d, const Tan& t, const Phys& p, int lpa, const float4* w, int par,
-                              hipStream_t s);
-hipError_t launch_tan_forces(const Dev& d, const Tan& t, const Phys& p, int lpa, const float4* w, int par,
-                             const Adj* adj, hipStream_t s);
 hipError_t launch_gather_vec(const Dev& d, const float4* user, float4* internal, hipStream_t s);
 hipError_t launch_scatter_vec(const Dev& d, const float4* internal, float4* user, hipStream_t s);
 hipError_t launch_copy_u(const Dev& d, const uint4* src, uint4* dst, hipStream_t s);

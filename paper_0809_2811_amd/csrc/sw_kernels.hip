@@ -810,6 +810,11 @@ __global__ void k_fill_f32(float* p, float value, long long n) {
   if (k < n) p[k] = value;
 }
 
+__global__ void k_fill_f64(double* p, double value, long long n) {
+  const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) p[k] = value;
+}
+
 inline unsigned nblk(long long n, int b) { return (unsigned)((n + b - 1) / b); }
 
 // Launches go through hipExtLaunchKernelGGL so that sampled launches can
@@ -978,6 +983,12 @@ hipError_t launch_fill_i32(int* p, int value, long long n, hipStream_t s) {
 hipError_t launch_fill_f32(float* p, float value, long long n, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_fill_f32, dim3(nblk(n, kBlock)), dim3(kBlock), 0, s, p, value, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_f64(double* p, double value, long long n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_f64, dim3(nblk(n, kBlock)), dim3(kBlock), 0, s, p, value, n);
   return hipGetLastError();
 }
 

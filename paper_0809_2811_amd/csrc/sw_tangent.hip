@@ -18,9 +18,13 @@
 //   for s = S-1 .. 0:  vb += dt xb;  frame(s, s > 0 ? dt : dt/2)
 //   frame(s, c):  xb += c J(x_s) vb + dl_s/dx_s,  thbar += c vb . da/dtheta + dl_s/dtheta
 // One tangent pass along vb at x_s gives every term of a frame.  Positions
-// are recomputed per checkpoint segment; a segment always starts with a fresh
-// row build and force pass and ends on a full-step velocity, so the recompute
-// repeats the forward kernels exactly.
+// are recomputed per checkpoint segment from a checkpoint of positions,
+// full-step velocities and the row state, so the recompute repeats the
+// forward kernels exactly.  While a segment is recomputed (or, for the last
+// segment, while it first runs) every launch writes the frame's positions and
+// cell binning straight into per-frame stores; a frame of the reverse sweep
+// then builds its rows from the stored cells and runs the tangent pass with
+// no copies.  The loss terms are summed during the reverse sweep.
 #include "sw_ctx.h"
 #include "sw_device.h"
 
@@ -236,56 +240,62 @@ __global__ __launch_bounds__(kBlock) void k_tan_forces(Dev d, Tan t, Phys p, con
   }
 }
 
-// Per-replica sums of the tangent partials, one block per (replica, quantity).
-__global__ __launch_bounds__(kBlock) void k_reduce_tan(Dev d, Tan t, int apb) {
-  __shared__ double tree[kBlock];
+// What to do with a tangent pass's per-replica sums: sw_grad outputs, or one
+// frame's contribution to the parameter adjoint and the loss (frame weight
+// coef_cm, loss weights aU, a3 with the 1/(n (S+1)) normalisation).
+struct PTerm {
+  double lam, eps, sig;
+  double* wdF;
+  double* dU;
+  double* thbar;
+  double* loss;
+  double coef_cm, aU, a3;
+  int S;
+};
+
+// Per-replica sums of the tangent partials (one block per replica, all
+// quantities at once, fixed order), then the parameter terms.
+__global__ __launch_bounds__(kBlock) void k_reduce_tan(Dev d, Tan t, int apb, PTerm pt) {
+  __shared__ double part[kBlock / 64][kTQ];
   const int nbt = d.npad / apb;
-  for (int task = blockIdx.x; task < d.R * kTQ; task += gridDim.x) {
-    const int rep = task / kTQ, k = task % kTQ;
+  const int wl = (int)threadIdx.x & 63, wv = (int)threadIdx.x >> 6;
+  for (int rep = blockIdx.x; rep < d.R; rep += gridDim.x) {
     const RepInfo& R = d.reps[rep];
-    const double* src = t.tpartial + (size_t)k * nbt;
-    double acc = 0.0;
-    for (int b = R.ioff / apb + (int)threadIdx.x; b < R.ipad_end / apb; b += kBlock) acc += src[b];
-    tree[threadIdx.x] = acc;
-    __syncthreads();
-    for (int st = kBlock / 2; st > 0; st >>= 1) {
-      if ((int)threadIdx.x < st) tree[threadIdx.x] += tree[threadIdx.x + st];
-      __syncthreads();
+    double acc[kTQ];
+#pragma unroll
+    for (int k = 0; k < kTQ; ++k) acc[k] = 0.0;
+    for (int b = R.ioff / apb + (int)threadIdx.x; b < R.ipad_end / apb; b += kBlock) {
+#pragma unroll
+      for (int k = 0; k < kTQ; ++k) acc[k] += t.tpartial[(size_t)k * nbt + b];
     }
-    if (threadIdx.x == 0) t.tsum[rep * kTQ + k] = tree[0];
+#pragma unroll
+    for (int k = 0; k < kTQ; ++k)
+      for (int m = 32; m >= 1; m >>= 1) acc[k] += __shfl_xor(acc[k], m, 64);
+    if (wl == 0) {
+#pragma unroll
+      for (int k = 0; k < kTQ; ++k) part[wv][k] = acc[k];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double q[kTQ];
+#pragma unroll
+      for (int k = 0; k < kTQ; ++k) {
+        q[k] = ((part[0][k] + part[1][k]) + part[2][k]) + part[3][k];
+        t.tsum[rep * kTQ + k] = q[k];
+      }
+      const double E2 = q[0], E3 = q[1], W2 = q[2], W3 = q[3], wF = q[4], wF3 = q[5], Wd = q[6];
+      const double g[3] = {wF3 / pt.lam, wF / pt.eps, -Wd / pt.sig};   // w . dF/d(lambda, eps, sigma)
+      const double u[3] = {E3 / pt.lam, (E2 + E3) / pt.eps, (W2 + W3) / pt.sig};
+      const double u3[3] = {E3 / pt.lam, E3 / pt.eps, W3 / pt.sig};
+      if (pt.wdF) for (int k = 0; k < 3; ++k) pt.wdF[3 * rep + k] = g[k];
+      if (pt.dU) for (int k = 0; k < 3; ++k) pt.dU[3 * rep + k] = u[k];
+      const double norm = 1.0 / ((double)R.n * (pt.S + 1));
+      if (pt.thbar)
+        for (int k = 0; k < 3; ++k) pt.thbar[3 * rep + k] += pt.coef_cm * g[k] + norm * (pt.aU * u[k] + pt.a3 * u3[k]);
+      if (pt.loss) pt.loss[rep] += norm * (pt.aU * (E2 + E3) + pt.a3 * E3);
+    }
     __syncthreads();
   }
-}
-
-// sw_grad outputs, or the per-frame parameter adjoint (frame weight coef_cm,
-// loss weights aU, a3 with the 1/(n (S+1)) normalisation).
-__global__ void k_param_terms(Tan t, int R, const RepInfo* reps, double lam, double eps, double sig, double* wdF,
-                              double* dU, double* thbar, double coef_cm, double aU, double a3, int S) {
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= R) return;
-  const double* q = t.tsum + r * kTQ;
-  const double E2 = q[0], E3 = q[1], W2 = q[2], W3 = q[3], wF = q[4], wF3 = q[5], Wd = q[6];
-  const double g[3] = {wF3 / lam, wF / eps, -Wd / sig};   // w . dF/d(lambda, eps, sigma)
-  const double u[3] = {E3 / lam, (E2 + E3) / eps, (W2 + W3) / sig};
-  const double u3[3] = {E3 / lam, E3 / eps, W3 / sig};
-  if (wdF) for (int k = 0; k < 3; ++k) wdF[3 * r + k] = g[k];
-  if (dU) for (int k = 0; k < 3; ++k) dU[3 * r + k] = u[k];
-  if (thbar) {
-    const double norm = 1.0 / ((double)reps[r].n * (S + 1));
-    for (int k = 0; k < 3; ++k) thbar[3 * r + k] += coef_cm * g[k] + norm * (aU * u[k] + a3 * u3[k]);
-  }
-}
-
-// Frame loss from recorded thermo rows [S+1][R][kNQ].
-__global__ void k_loss(const double* th, int S, int R, const RepInfo* reps, double aU, double a3, double* loss) {
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= R) return;
-  double acc = 0.0;
-  for (int s = 0; s <= S; ++s) {
-    const double* row = th + ((size_t)s * R + r) * kNQ;
-    acc += aU * (row[0] + row[1]) + a3 * row[1];
-  }
-  loss[r] = acc / ((double)reps[r].n * (S + 1));
 }
 
 __global__ void k_gather_vec(Dev d, const float4* __restrict__ user, float4* __restrict__ internal) {
@@ -317,7 +327,7 @@ inline unsigned nb(long long n) { return (unsigned)((n + kBlock - 1) / kBlock); 
 
 template <int LPA>
 hipError_t tan_launch(const Dev& d, const Tan& t, const Phys& p, const float4* w, int par, const Adj* adj,
-                      hipStream_t s, bool moments) {
+                      const PTerm& pt, hipStream_t s, bool moments) {
   constexpr int APB = kBlock / LPA;
   const unsigned grid = (unsigned)(d.npad / APB);
   if (moments) {
@@ -326,34 +336,36 @@ hipError_t tan_launch(const Dev& d, const Tan& t, const Phys& p, const float4* w
     Adj a = adj ? *adj : Adj{};
     if (adj) hipLaunchKernelGGL((k_tan_forces<LPA, true>), dim3(grid), dim3(kBlock), 0, s, d, t, p, w, par, a);
     else hipLaunchKernelGGL((k_tan_forces<LPA, false>), dim3(grid), dim3(kBlock), 0, s, d, t, p, w, par, a);
-    hipLaunchKernelGGL(k_reduce_tan, dim3((unsigned)std::min(d.R * kTQ, 4096)), dim3(kBlock), 0, s, d, t, APB);
+    hipLaunchKernelGGL(k_reduce_tan, dim3((unsigned)std::min(d.R, 4096)), dim3(kBlock), 0, s, d, t, APB, pt);
   }
   return hipGetLastError();
 }
 
-}  // namespace
-
 hipError_t launch_tan_moments(const Dev& d, const Tan& t, const Phys& p, int lpa, const float4* w, int par,
                               hipStream_t s) {
+  const PTerm none{};
   switch (lpa) {
-    case 4: return tan_launch<4>(d, t, p, w, par, nullptr, s, true);
-    case 8: return tan_launch<8>(d, t, p, w, par, nullptr, s, true);
-    case 16: return tan_launch<16>(d, t, p, w, par, nullptr, s, true);
-    case 32: return tan_launch<32>(d, t, p, w, par, nullptr, s, true);
+    case 4: return tan_launch<4>(d, t, p, w, par, nullptr, none, s, true);
+    case 8: return tan_launch<8>(d, t, p, w, par, nullptr, none, s, true);
+    case 16: return tan_launch<16>(d, t, p, w, par, nullptr, none, s, true);
+    case 32: return tan_launch<32>(d, t, p, w, par, nullptr, none, s, true);
   }
   return hipErrorInvalidValue;
 }
 
+// Tangent forces, then the per-replica sums and the parameter terms of pt.
 hipError_t launch_tan_forces(const Dev& d, const Tan& t, const Phys& p, int lpa, const float4* w, int par,
-                             const Adj* adj, hipStream_t s) {
+                             const Adj* adj, const PTerm& pt, hipStream_t s) {
   switch (lpa) {
-    case 4: return tan_launch<4>(d, t, p, w, par, adj, s, false);
-    case 8: return tan_launch<8>(d, t, p, w, par, adj, s, false);
-    case 16: return tan_launch<16>(d, t, p, w, par, adj, s, false);
-    case 32: return tan_launch<32>(d, t, p, w, par, adj, s, false);
+    case 4: return tan_launch<4>(d, t, p, w, par, adj, pt, s, false);
+    case 8: return tan_launch<8>(d, t, p, w, par, adj, pt, s, false);
+    case 16: return tan_launch<16>(d, t, p, w, par, adj, pt, s, false);
+    case 32: return tan_launch<32>(d, t, p, w, par, adj, pt, s, false);
   }
   return hipErrorInvalidValue;
 }
+
+}  // namespace
 
 hipError_t launch_gather_vec(const Dev& d, const float4* user, float4* internal, hipStream_t s) {
   hipLaunchKernelGGL(k_gather_vec, dim3(nb(d.npad)), dim3(kBlock), 0, s, d, user, internal);
@@ -396,36 +408,60 @@ struct AdjBuffers {
   }
 };
 
-// Positions x_c (in u[0]), full-step velocities and the rows in force at
-// x_c -> len steps of NVE velocity Verlet.  The first segment of a
-// trajectory builds its rows; later segments continue with the rows they
-// inherit, so the step sequence, and every rebuild decision, is the same for
-// any checkpoint interval.  Ends on the full-step velocity.  If th is given,
-// rows c..c+len of the thermo table get E2, E3, ... of every frame.  If seg
-// is given, seg[k] receives the positions of frame c+k.  Leaves the end
-// positions in u[0].
-hipError_t run_segment(sw_ctx* c, const Phys& ph, int lpa, int len, bool first, double* th, uint4* seg,
+// Per-frame stores of one segment (frames 0..K): positions and the cell
+// binning of each frame's positions.
+struct FrameStore {
+  uint4* u;      // [K+1][Npad]
+  int* cnt;      // [K+1][cells]
+  uint4* cells;  // [K+1][cells][cell capacity]
+};
+
+// The context's device view for frame k of a stored segment of len steps:
+// the frame's positions and cells in the parity slot the step reads, the
+// next frame's in the slot it writes (the moments launch clears those
+// counts, the force launch bins into them).  Without a store: the context's
+// own ping-pong arrays.
+Dev frame_dev(const sw_ctx* c, const FrameStore* fs, int k, int len) {
+  Dev d = c->d;
+  if (!fs) return d;
+  const int par = k & 1;
+  const size_t np = c->npad, nc = c->ctot, ncm = (size_t)c->ctot * c->cc;
+  d.u[par] = fs->u + (size_t)k * np;
+  d.gcnt[par] = fs->cnt + (size_t)k * nc;
+  d.gmem[par] = fs->cells + (size_t)k * ncm;
+  if (k < len) {
+    d.u[par ^ 1] = fs->u + (size_t)(k + 1) * np;
+    d.gcnt[par ^ 1] = fs->cnt + (size_t)(k + 1) * nc;
+    d.gmem[par ^ 1] = fs->cells + (size_t)(k + 1) * ncm;
+  }
+  return d;
+}
+
+// len steps of NVE velocity Verlet from positions x_c, full-step velocities
+// and the rows in force at x_c.  The first segment of a trajectory builds its
+// rows; later segments continue with the rows they inherit, so the step
+// sequence, and every rebuild decision, is the same for any checkpoint
+// interval.  Ends on the full-step velocity.  Without a store the positions
+// start and end in u[0]; with one they start in frame 0 of the store and
+// every frame's positions and cells stay there.
+hipError_t run_segment(sw_ctx* c, const Phys& ph, int lpa, int len, bool first, const FrameStore* fs,
                        hipStream_t s) {
-  const Dev& d = c->d;
-  const size_t rowsz = (size_t)c->R * kNQ;
-  const int rec = th != nullptr;
   hipError_t e;
-  if ((e = launch_fill_i32(d.gcnt[0], 0, c->ctot, s)) != hipSuccess) return e;
-  if ((e = launch_fill_i32(d.dflag, 0, 2 * c->R, s)) != hipSuccess) return e;
-  if ((e = launch_bin(d, 0, 0, 0.f, s)) != hipSuccess) return e;
-  if ((e = launch_moments(d, ph, lpa, 0, first ? 1 : 0, rec, s)) != hipSuccess) return e;
-  if (seg && (e = launch_copy_u(d, d.u[0], seg, s)) != hipSuccess) return e;
-  if (len == 0) return launch_forces(d, ph, lpa, MODE_FORCES, 1, 0, th, s);
-  if ((e = launch_forces(d, ph, lpa, MODE_START, rec, 0, th, s)) != hipSuccess) return e;
+  const Dev d0 = frame_dev(c, fs, 0, len);
+  if ((e = launch_fill_i32(d0.gcnt[0], 0, c->ctot, s)) != hipSuccess) return e;
+  if ((e = launch_fill_i32(d0.dflag, 0, 2 * c->R, s)) != hipSuccess) return e;
+  if ((e = launch_bin(d0, 0, 0, 0.f, s)) != hipSuccess) return e;
+  if ((e = launch_moments(d0, ph, lpa, 0, first ? 1 : 0, 0, s)) != hipSuccess) return e;
+  if (len == 0) return launch_forces(d0, ph, lpa, MODE_FORCES, 0, 0, nullptr, s);
+  if ((e = launch_forces(d0, ph, lpa, MODE_START, 0, 0, nullptr, s)) != hipSuccess) return e;
   for (int t = 1; t <= len; ++t) {
     const int par = t & 1;
-    if ((e = launch_moments(d, ph, lpa, par, 0, rec, s)) != hipSuccess) return e;
-    if (seg && (e = launch_copy_u(d, d.u[par], seg + (size_t)t * d.npad, s)) != hipSuccess) return e;
+    const Dev dt = frame_dev(c, fs, t, len);
+    if ((e = launch_moments(dt, ph, lpa, par, 0, 0, s)) != hipSuccess) return e;
     const int mode = t == len ? MODE_NVE_LAST : MODE_NVE;
-    if ((e = launch_forces(d, ph, lpa, mode, rec, par, rec ? th + (size_t)t * rowsz : nullptr, s)) != hipSuccess)
-      return e;
+    if ((e = launch_forces(dt, ph, lpa, mode, 0, par, nullptr, s)) != hipSuccess) return e;
   }
-  if (len & 1) return launch_copy_u(d, d.u[1], d.u[0], s);
+  if (!fs && (len & 1)) return launch_copy_u(c->d, c->d.u[1], c->d.u[0], s);
   return hipSuccess;
 }
 
@@ -449,18 +485,33 @@ hipError_t save_ckpt(sw_ctx* c, const Ckpt& k, hipStream_t s) {
   return hipMemcpyAsync(k.nl, c->d.nl, sizeof(int) * np * c->cap, hipMemcpyDeviceToDevice, s);
 }
 
-hipError_t load_ckpt(sw_ctx* c, const Ckpt& k, hipStream_t s) {
+// Restores a checkpoint; its positions go to u_dst.  The first segment's
+// checkpoint holds no row state (that segment builds its rows).
+hipError_t load_ckpt(sw_ctx* c, const Ckpt& k, uint4* u_dst, bool rows, hipStream_t s) {
   const size_t np = c->npad;
   hipError_t e;
-  if ((e = launch_copy_u(c->d, k.u, c->d.u[0], s)) != hipSuccess) return e;
+  if ((e = launch_copy_u(c->d, k.u, u_dst, s)) != hipSuccess) return e;
   if ((e = launch_copy_v(c->d, k.v, c->d.v, s)) != hipSuccess) return e;
+  if (!rows) return hipSuccess;
   if ((e = launch_copy_u(c->d, k.uref, c->d.uref, s)) != hipSuccess) return e;
   if ((e = hipMemcpyAsync(c->d.nn, k.nn, sizeof(int) * np, hipMemcpyDeviceToDevice, s)) != hipSuccess) return e;
   return hipMemcpyAsync(c->d.nl, k.nl, sizeof(int) * np * c->cap, hipMemcpyDeviceToDevice, s);
 }
 
-// Tangent pass at positions u[0] along w (rows rebuilt first).
-hipError_t tangent_pass(sw_ctx* c, const Phys& ph, int lpa, const float4* w, const Adj* adj, hipStream_t s,
+// Tangent pass along w at the positions of dv.u[0], whose cells are binned
+// in dv.gcnt[0] / dv.gmem[0]: rows built fresh there, moments with energies,
+// tangent moments, tangent forces and the per-replica terms of pt.
+hipError_t tangent_frame(sw_ctx* c, const Dev& dv, const Phys& ph, int lpa, const float4* w, const Adj* adj,
+                         const PTerm& pt, hipStream_t s) {
+  hipError_t e;
+  if ((e = launch_moments(dv, ph, lpa, 0, 1, 1, s)) != hipSuccess) return e;
+  if ((e = launch_tan_moments(dv, c->t, ph, lpa, w, 0, s)) != hipSuccess) return e;
+  return launch_tan_forces(dv, c->t, ph, lpa, w, 0, adj, pt, s);
+}
+
+// Tangent pass at positions u[0] along w; rows rebuilt first, or kept when
+// no atom has moved half the skin since they were built.
+hipError_t tangent_pass(sw_ctx* c, const Phys& ph, int lpa, const float4* w, const PTerm& pt, hipStream_t s,
                         bool rebuild) {
   const Dev& d = c->d;
   hipError_t e;
@@ -469,7 +520,7 @@ hipError_t tangent_pass(sw_ctx* c, const Phys& ph, int lpa, const float4* w, con
   if ((e = launch_bin(d, 0, rebuild ? 0 : 1, ph.half_skin, s)) != hipSuccess) return e;
   if ((e = launch_moments(d, ph, lpa, 0, rebuild ? 1 : 0, 1, s)) != hipSuccess) return e;
   if ((e = launch_tan_moments(d, c->t, ph, lpa, w, 0, s)) != hipSuccess) return e;
-  return launch_tan_forces(d, c->t, ph, lpa, w, 0, adj, s);
+  return launch_tan_forces(d, c->t, ph, lpa, w, 0, nullptr, pt, s);
 }
 
 }  // namespace
@@ -484,6 +535,7 @@ int sw_grad(sw_ctx* ctx, const float* x, const float* w, const sw_params* params
   int st = make_phys(ctx, params, 1.0, 1.0, &ph);
   if (st != SW_OK) return st;
   const int lpa = lpa_for(ctx);
+  const PTerm pt{params->lambda, params->epsilon, params->sigma, wdF, dU, nullptr, nullptr, 0.0, 0.0, 0.0, 0};
   for (int attempt = 0; attempt < 6; ++attempt) {
     hipError_t e;
     if ((e = reset_flags(ctx, s)) != hipSuccess) return fail_hip(ctx, e);
@@ -495,7 +547,7 @@ int sw_grad(sw_ctx* ctx, const float* x, const float* w, const sw_params* params
       return fail_hip(ctx, e);
     }
     if ((e = launch_gather_vec(ctx->d, (const float4*)w, ctx->t.w, s)) != hipSuccess) return fail_hip(ctx, e);
-    if ((e = tangent_pass(ctx, ph, lpa, ctx->t.w, nullptr, s, rebuild)) != hipSuccess) return fail_hip(ctx, e);
+    if ((e = tangent_pass(ctx, ph, lpa, ctx->t.w, pt, s, rebuild)) != hipSuccess) return fail_hip(ctx, e);
     Flags fl;
     if ((e = read_flags(ctx, s, &fl)) != hipSuccess) return fail_hip(ctx, e);
     if (fl.nbr_over || fl.cell_over) {
@@ -503,12 +555,6 @@ int sw_grad(sw_ctx* ctx, const float* x, const float* w, const sw_params* params
       continue;
     }
     if ((e = launch_scatter_vec(ctx->d, ctx->t.fdot, (float4*)hvp, s)) != hipSuccess) return fail_hip(ctx, e);
-    if (wdF || dU) {
-      hipLaunchKernelGGL(k_param_terms, dim3((ctx->R + 63) / 64), dim3(64), 0, s, ctx->t, ctx->R, ctx->d_reps,
-                         params->lambda, params->epsilon, params->sigma, wdF, dU, (double*)nullptr, 0.0, 0.0, 0.0,
-                         0);
-      if ((e = hipGetLastError()) != hipSuccess) return fail_hip(ctx, e);
-    }
     if ((e = hipStreamSynchronize(s)) != hipSuccess) return fail_hip(ctx, e);
     return fl.overlap ? SW_EOVERLAP : SW_OK;
   }
@@ -526,32 +572,35 @@ int sw_adjoint(sw_ctx* ctx, const float* x0, const float* v0, const sw_params* p
   int st = make_phys(ctx, params, mass, dt, &ph);
   if (st != SW_OK) return st;
   const int lpa = lpa_for(ctx);
-  const int S = nsteps, K = ckpt_every;
+  const int S = nsteps, K = std::min(ckpt_every, std::max(S, 1));
   const int nseg = S == 0 ? 1 : (S + K - 1) / K;
   const size_t np = ctx->npad;
   const double c_m = kAcc / mass;
   for (int attempt = 0; attempt < 6; ++attempt) {
     AdjBuffers B;
-    uint4 *ck_u = nullptr, *ck_uref = nullptr, *seg = nullptr;
+    uint4 *ck_u = nullptr, *ck_uref = nullptr, *fs_u = nullptr, *fs_cells = nullptr;
     float4 *ck_v = nullptr, *xb = nullptr, *vb[2] = {nullptr, nullptr};
-    int *ck_nl = nullptr, *ck_nn = nullptr;
-    double *th = nullptr, *thb = nullptr;
+    int *ck_nl = nullptr, *ck_nn = nullptr, *fs_cnt = nullptr;
+    double* thb = nullptr;
     hipError_t e;
+    const size_t nf = (size_t)K + 1;
     if ((e = B.get(&ck_u, np * nseg)) != hipSuccess || (e = B.get(&ck_v, np * nseg)) != hipSuccess ||
         (e = B.get(&ck_uref, np * nseg)) != hipSuccess || (e = B.get(&ck_nn, np * nseg)) != hipSuccess ||
-        (e = B.get(&ck_nl, np * ctx->cap * nseg)) != hipSuccess ||
-        (e = B.get(&seg, np * (K + 1))) != hipSuccess || (e = B.get(&xb, np)) != hipSuccess ||
-        (e = B.get(&vb[0], np)) != hipSuccess || (e = B.get(&vb[1], np)) != hipSuccess ||
-        (e = B.get(&th, (size_t)(S + 1) * ctx->R * kNQ)) != hipSuccess ||
-        (e = B.get(&thb, (size_t)ctx->R * 3)) != hipSuccess)
+        (e = B.get(&ck_nl, np * ctx->cap * nseg)) != hipSuccess || (e = B.get(&fs_u, np * nf)) != hipSuccess ||
+        (e = B.get(&fs_cnt, (size_t)ctx->ctot * nf)) != hipSuccess ||
+        (e = B.get(&fs_cells, (size_t)ctx->ctot * ctx->cc * nf)) != hipSuccess ||
+        (e = B.get(&xb, np)) != hipSuccess || (e = B.get(&vb[0], np)) != hipSuccess ||
+        (e = B.get(&vb[1], np)) != hipSuccess || (e = B.get(&thb, (size_t)ctx->R * 3)) != hipSuccess)
       return e == hipErrorOutOfMemory ? SW_ENOMEM : fail_hip(ctx, e);
+    const FrameStore fs{fs_u, fs_cnt, fs_cells};
     if ((e = reset_flags(ctx, s)) != hipSuccess) return fail_hip(ctx, e);
     if ((e = sort_in(ctx, x0, v0, s)) != hipSuccess) return fail_hip(ctx, e);
-    // forward, with checkpoints of (x, v) at every segment start
     auto ckpt = [&](int j) {
       return Ckpt{ck_u + (size_t)j * np, ck_v + (size_t)j * np, ck_nl + (size_t)j * np * ctx->cap,
                   ck_nn + (size_t)j * np, ck_uref + (size_t)j * np};
     };
+    // forward with a checkpoint at every segment start; the last segment
+    // runs into the frame store, so the reverse sweep needs no recompute of it
     for (int j = 0; j < nseg; ++j) {
       const int c = j * K, len = std::min(K, S - c);
       if (j > 0 && (e = save_ckpt(ctx, ckpt(j), s)) != hipSuccess) return fail_hip(ctx, e);
@@ -559,7 +608,9 @@ int sw_adjoint(sw_ctx* ctx, const float* x0, const float* v0, const sw_params* p
         if ((e = launch_copy_u(ctx->d, ctx->d.u[0], ck_u, s)) != hipSuccess) return fail_hip(ctx, e);
         if ((e = launch_copy_v(ctx->d, ctx->d.v, ck_v, s)) != hipSuccess) return fail_hip(ctx, e);
       }
-      if ((e = run_segment(ctx, ph, lpa, len, j == 0, th + (size_t)c * ctx->R * kNQ, nullptr, s)) != hipSuccess)
+      const bool last = j == nseg - 1;
+      if (last && (e = launch_copy_u(ctx->d, ctx->d.u[0], fs.u, s)) != hipSuccess) return fail_hip(ctx, e);
+      if ((e = run_segment(ctx, ph, lpa, len, j == 0, last ? &fs : nullptr, s)) != hipSuccess)
         return fail_hip(ctx, e);
     }
     Flags fl;
@@ -568,38 +619,39 @@ int sw_adjoint(sw_ctx* ctx, const float* x0, const float* v0, const sw_params* p
       if ((st = grow(ctx, fl)) != SW_OK) return st;
       continue;
     }
-    hipLaunchKernelGGL(k_loss, dim3((ctx->R + 63) / 64), dim3(64), 0, s, th, S, ctx->R, ctx->d_reps, aU, a3, loss);
-    if (xS && (e = launch_scatter_out(ctx->d, 0, (float4*)xS, nullptr, nullptr, s)) != hipSuccess)
-      return fail_hip(ctx, e);
-    if (vS && (e = launch_scatter_out(ctx->d, 0, nullptr, (float4*)vS, nullptr, s)) != hipSuccess)
-      return fail_hip(ctx, e);
+    {
+      const int len_last = S - (nseg - 1) * K;
+      Dev dS = ctx->d;
+      dS.u[0] = fs.u + (size_t)len_last * np;
+      if (xS && (e = launch_scatter_out(dS, 0, (float4*)xS, nullptr, nullptr, s)) != hipSuccess)
+        return fail_hip(ctx, e);
+      if (vS && (e = launch_scatter_out(dS, 0, nullptr, (float4*)vS, nullptr, s)) != hipSuccess)
+        return fail_hip(ctx, e);
+    }
     // reverse sweep
     int cur = 0;
     if ((e = launch_gather_vec(ctx->d, (const float4*)xbar_S, xb, s)) != hipSuccess) return fail_hip(ctx, e);
     if ((e = launch_gather_vec(ctx->d, (const float4*)vbar_S, vb[0], s)) != hipSuccess) return fail_hip(ctx, e);
-    if ((e = hipMemsetAsync(thb, 0, sizeof(double) * 3 * ctx->R, s)) != hipSuccess) return fail_hip(ctx, e);
+    if ((e = launch_fill_f64(thb, 0.0, 3 * (long long)ctx->R, s)) != hipSuccess) return fail_hip(ctx, e);
+    if ((e = launch_fill_f64(loss, 0.0, ctx->R, s)) != hipSuccess) return fail_hip(ctx, e);
     for (int j = nseg - 1; j >= 0; --j) {
       const int c = j * K, len = std::min(K, S - c);
-      if (j > 0) {
-        if ((e = load_ckpt(ctx, ckpt(j), s)) != hipSuccess) return fail_hip(ctx, e);
-      } else {
-        if ((e = launch_copy_u(ctx->d, ck_u, ctx->d.u[0], s)) != hipSuccess) return fail_hip(ctx, e);
-        if ((e = launch_copy_v(ctx->d, ck_v, ctx->d.v, s)) != hipSuccess) return fail_hip(ctx, e);
+      if (j < nseg - 1) {   // recompute the segment into the frame store
+        if ((e = load_ckpt(ctx, ckpt(j), fs.u, j > 0, s)) != hipSuccess) return fail_hip(ctx, e);
+        if ((e = run_segment(ctx, ph, lpa, len, j == 0, &fs, s)) != hipSuccess) return fail_hip(ctx, e);
       }
-      // same kernel variants as the forward pass (which recorded energies), so
-      // the recomputed positions are the forward's bit for bit
-      if ((e = run_segment(ctx, ph, lpa, len, j == 0, th + (size_t)c * ctx->R * kNQ, seg, s)) != hipSuccess)
-        return fail_hip(ctx, e);
       const int s_lo = j == 0 ? 0 : c + 1;
       for (int sf = c + len; sf >= s_lo; --sf) {
-        if ((e = launch_copy_u(ctx->d, seg + (size_t)(sf - c) * np, ctx->d.u[0], s)) != hipSuccess)
-          return fail_hip(ctx, e);
+        const int k = sf - c;
+        Dev dv = ctx->d;   // frame sf: its positions and cells in parity slot 0
+        dv.u[0] = fs.u + (size_t)k * np;
+        dv.gcnt[0] = fs.cnt + (size_t)k * ctx->ctot;
+        dv.gmem[0] = fs.cells + (size_t)k * ctx->ctot * ctx->cc;
         const double coef = (sf == S || sf == 0) ? 0.5 * dt : dt;
-        Adj a{xb, vb[cur ^ 1], (float)(coef * c_m), (float)dt, (float)aU, (float)a3, S, sf == 0};
-        if ((e = tangent_pass(ctx, ph, lpa, vb[cur], &a, s, true)) != hipSuccess) return fail_hip(ctx, e);
-        hipLaunchKernelGGL(k_param_terms, dim3((ctx->R + 63) / 64), dim3(64), 0, s, ctx->t, ctx->R, ctx->d_reps,
-                           params->lambda, params->epsilon, params->sigma, (double*)nullptr, (double*)nullptr, thb,
-                           coef * c_m, aU, a3, S);
+        const Adj a{xb, vb[cur ^ 1], (float)(coef * c_m), (float)dt, (float)aU, (float)a3, S, sf == 0};
+        const PTerm pt{params->lambda, params->epsilon, params->sigma, nullptr, nullptr, thb, loss,
+                       coef * c_m, aU, a3, S};
+        if ((e = tangent_frame(ctx, dv, ph, lpa, vb[cur], &a, pt, s)) != hipSuccess) return fail_hip(ctx, e);
         if (sf > 0) cur ^= 1;
       }
     }
