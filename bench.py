@@ -209,7 +209,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=500)
     ap.add_argument("--skin", type=float, default=0.0, help="Verlet skin in A (0 = tuned)")
     ap.add_argument("--lpa", type=int, default=0, help="lanes per atom (0 = tuned default)")
-    ap.add_argument("--forms", default="large,batched,adjoint", help="comma list of large,batched,adjoint or none")
+    ap.add_argument("--forms", default="large,batched,adjoint,observables",
+                    help="comma list of large,batched,adjoint,observables or none")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="first run a plain FP32 copy-like kernel (out = -in) over this many MiB, three times: "
@@ -263,6 +264,8 @@ def main():
         line["forms"]["batched"] = bench_batched()
     if "adjoint" in forms:
         line["forms"]["adjoint"] = bench_adjoint(line["ms_per_step"])
+    if "observables" in forms:
+        line["forms"]["observables"] = bench_observables(ctx, x)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline()
     print(json.dumps(line), flush=True)
@@ -372,6 +375,30 @@ def bench_adjoint(plain_ms_per_step, steps=200, ckpt=20, skin=None):
             "seconds_per_trajectory": dt, "ms_per_step": ms, "value": n * steps / dt, "unit": "atom-steps/s",
             "ratio_to_plain_step": ms / plain_ms_per_step, "loss": float(res["loss"].cpu()[0]),
             "dL_dtheta": [float(t) for t in th]}
+
+
+def bench_observables(ctx, x, reps=20):
+    """One sampling frame of the Sec. II.C estimators on the main-line liquid
+    (4096 atoms): pair-distance histogram to the largest radius the cells allow
+    (0.02 A bins), angle histogram over the 8 closest neighbours (1 degree
+    bins), and the mean square displacement update; each call sorts and bins
+    the positions itself."""
+    rmax = ctx.max_search_radius()
+    r_edges = np.arange(0.0, rmax, 0.02)
+    th = np.arange(0.0, 180.01, 1.0)
+    out = {"workload": f"observables: {x.shape[0]}-atom 298 K liquid, g(r) to {rmax:.2f} A, P(theta) over 8 "
+                       "closest neighbours, MSD update", "n_atoms": int(x.shape[0])}
+    ctx.msd(x, reset=True)
+    for name, fn in (("rdf", lambda: ctx.rdf(x, r_edges)), ("adf", lambda: ctx.adf(x, th, n_near=8)),
+                     ("msd", lambda: ctx.msd(x))):
+        fn()
+        sync()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        sync()
+        out[f"{name}_ms"] = (time.perf_counter() - t0) * 1e3 / reps
+    return out
 
 
 if __name__ == "__main__":

@@ -173,6 +173,53 @@ int sw_adjoint(sw_ctx* ctx, const float* x0, const float* v0, const sw_params* p
                const float* xbar_S, const float* vbar_S, double* loss, float* xbar0,
                float* vbar0, double* thbar, float* xS, float* vS, void* stream);
 
+/* Structural observables (Sec. II.C).  Positions x are the caller's device
+ * float[N][4] in A; they are re-sorted into the context's internal order and
+ * binned (the context's next sw_step sorts again).  Coordinates follow the
+ * engine's convention u = floor(frac(x / L) 2^32) per component, and every
+ * distance and angle is formed in FP64 from them with single correctly
+ * rounded operations in a fixed order, so the counts are exact functions of
+ * x and of the caller's edges.  The search radius is limited to the smallest
+ * binning-cell edge, floor-divided from the box by cutoff + skin (the 27
+ * surrounding cells are searched).  Synchronise. */
+
+/* Pair distance histogram for g(r) and n_c:
+ *  h_r2_edges  host double[nbins + 1], strictly ascending squared distances
+ *              (A^2), e[0] >= 0 and e[nbins] <= (smallest cell edge)^2.
+ *  counts      device unsigned long long[R][nbins] out: ordered pairs (i, j),
+ *              j != i, of replica r with e[0] <= r^2 < e[nbins], in the bin given
+ *              by how many of the interior edges e[1..nbins-1] are <= r^2.
+ *  1 <= nbins <= 8192.  SW_EINVAL on bad edges or sizes. */
+int sw_rdf(sw_ctx* ctx, const float* x, int nbins, const double* h_r2_edges,
+           unsigned long long* counts, void* stream);
+
+/* Angular distribution P(theta) over each molecule's n_near closest neighbours
+ * (Sec. II.C uses n_c = 8): for every centre k, the neighbours with
+ * r^2 < r_search^2 ordered by (r^2, caller index); every unordered pair (a, b)
+ * of the first n_near gives cos = (d_a . d_b) / sqrt(r_a^2 r_b^2).
+ *  h_cos_edges host double[nbins + 1], strictly descending cosines (ascending
+ *              angles); the bin is the number of interior edges
+ *              c[1..nbins-1] that are >= cos.
+ *  counts      device unsigned long long[R][nbins] out.
+ *  h_short     host long long out (may be NULL): centres with fewer than n_near
+ *              neighbours inside r_search (skipped).
+ *  2 <= n_near <= 16, 0 < r_search <= smallest cell edge.  SW_ENBR_OVERFLOW if
+ *  a centre has more than 64 neighbours inside r_search. */
+int sw_adf(sw_ctx* ctx, const float* x, int n_near, double r_search, int nbins,
+           const double* h_cos_edges, unsigned long long* counts, long long* h_short,
+           void* stream);
+
+/* Mean square displacement for the Einstein relation D = lim <|r(t) - r(0)|^2>/6t
+ * (Sec. II.C).  The context keeps, in caller order, each atom's position at
+ * the last call and its displacement since the reference call, accumulated
+ * in FP64 from minimum images (so successive calls must be less than half a
+ * box edge of motion apart).
+ *  x      device float[N][4] caller order (A).
+ *  reset  nonzero: this call is the reference (displacements zeroed).
+ *  msd    device double[R] out: per-replica mean of |displacement|^2 (A^2).
+ *  SW_ESTATE if the first call does not reset. */
+int sw_msd(sw_ctx* ctx, const float* x, int reset, double* msd, void* stream);
+
 /* Execution options (chosen by the autotuner). */
 typedef struct sw_tuning {
   int lanes_per_atom;   /* 4, 8, 16 or 32 lanes of a wavefront share one atom  */

@@ -6,8 +6,10 @@ shares no code with the HIP engine in ``paper_0809_2811_amd``; the product path
 never calls it.
 
 The arithmetic lives in ``sw_oracle.cpp`` (plain C++ doubles, dual numbers for
-tangents); this module only marshals numpy arrays.  See that file's header for
-the equations it follows (Sec. II.A of the mW paper, Eq. E, phi2, phi3).
+tangents) and ``obs_oracle.cpp`` (the observables of Sec. II.C); this module
+only marshals numpy arrays, except for the mean square displacement, which is
+a few numpy lines here.  See the sources' headers for the equations they
+follow (Sec. II.A of the mW paper, Eq. E, phi2, phi3; Sec. II.C).
 """
 from __future__ import annotations
 
@@ -19,6 +21,7 @@ import numpy as np
 
 _HERE = pathlib.Path(__file__).resolve().parent
 _SRC = _HERE / "sw_oracle.cpp"
+_SRCS = (_SRC, _HERE / "obs_oracle.cpp")
 _LIB_PATH = _HERE / "liboracle_sw.so"
 _lib = None
 
@@ -35,7 +38,8 @@ THERMO_WIDTH = 12
 def build(force: bool = True) -> pathlib.Path:
     """Compile the oracle with g++ (FP64, no fast-math)."""
     if force or not _LIB_PATH.exists():
-        cmd = ["g++", "-O2", "-std=c++17", "-fPIC", "-shared", "-o", str(_LIB_PATH), str(_SRC)]
+        cmd = ["g++", "-O2", "-std=c++17", "-ffp-contract=off", "-fPIC", "-shared", "-o", str(_LIB_PATH),
+               *[str(s) for s in _SRCS]]
         subprocess.run(cmd, check=True)
     return _LIB_PATH
 
@@ -43,7 +47,7 @@ def build(force: bool = True) -> pathlib.Path:
 def lib():
     global _lib
     if _lib is None:
-        if not _LIB_PATH.exists() or _LIB_PATH.stat().st_mtime < _SRC.stat().st_mtime:
+        if not _LIB_PATH.exists() or any(_LIB_PATH.stat().st_mtime < s.stat().st_mtime for s in _SRCS):
             build()
         L = ctypes.CDLL(str(_LIB_PATH))
         dp = ctypes.POINTER(ctypes.c_double)
@@ -64,6 +68,10 @@ def lib():
                                   c_double, dp, dp, dp, dp, dp, dp]
         L.ora_neighbour_counts.argtypes = [c_int, dp, dp, c_double, ip]
         L.ora_neighbour_lists.argtypes = [c_int, dp, dp, c_double, llp, ip]
+        u64p = ctypes.POINTER(ctypes.c_uint64)
+        L.ora_quantize.argtypes = [c_int, dp, dp, ctypes.POINTER(ctypes.c_uint32)]
+        L.ora_rdf.argtypes = [c_int, dp, dp, c_int, dp, u64p]
+        L.ora_adf.argtypes = [c_int, dp, dp, c_int, c_double, c_int, dp, u64p, llp]
         _lib = L
     return _lib
 
@@ -193,3 +201,53 @@ def temperature(v, mass=M_WATER):
     v = _d(v)
     ke = 0.5 * mass * float(np.sum(v * v)) / ACC
     return 2.0 * ke / ((3 * len(v) - 3) * KB)
+
+
+# ---------------------------------------------------------------- observables
+# Sec. II.C: pair distribution, angular distribution of the n_c closest
+# neighbours, mean square displacement.
+
+def quantize(x, box):
+    """The engine's coordinate convention: u = floor(frac(x / L) 2^32)."""
+    x = _d(x); box = _d(box)
+    u = np.zeros((len(x), 3), dtype=np.uint32)
+    lib().ora_quantize(len(x), _ptr(x), _ptr(box), u.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)))
+    return u
+
+
+def rdf_counts(x, box, r2_edges):
+    """Ordered-pair counts per bin of squared distance (edges ascending)."""
+    x = _d(x); box = _d(box); e = _d(r2_edges)
+    c = np.zeros(len(e) - 1, dtype=np.uint64)
+    lib().ora_rdf(len(x), _ptr(x), _ptr(box), len(e) - 1, _ptr(e), c.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)))
+    return c
+
+
+def adf_counts(x, box, n_near, r_search, cos_edges):
+    """Angle counts over the n_near closest neighbours within r_search of each
+    centre (cosine edges descending); returns (counts, centres skipped)."""
+    x = _d(x); box = _d(box); e = _d(cos_edges)
+    c = np.zeros(len(e) - 1, dtype=np.uint64)
+    short = ctypes.c_longlong(0)
+    lib().ora_adf(len(x), _ptr(x), _ptr(box), int(n_near), float(r_search) ** 2, len(e) - 1, _ptr(e),
+                  c.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)), ctypes.byref(short))
+    return c, short.value
+
+
+class Displacement:
+    """Unwrapped displacement of every atom since the reference frame
+    (Einstein relation of Sec. II.C): between two frames each atom moves by
+    the minimum image of its position difference, accumulated in FP64."""
+
+    def __init__(self, x, box):
+        self.last = _d(x).copy()
+        self.box = _d(box)
+        self.acc = np.zeros_like(self.last)
+
+    def update(self, x):
+        x = _d(x)
+        d = x - self.last
+        d = d - self.box * np.rint(d / self.box)
+        self.acc += d
+        self.last = x.copy()
+        return float(np.mean(np.sum(self.acc * self.acc, axis=1)))

@@ -49,6 +49,12 @@ struct sw_ctx {
   size_t bytes = 0;
   std::vector<void*> allocs;       // everything freed by free_all
   std::vector<void*> grow_allocs;  // capacity-dependent buffers
+  // observables (allocated on first use)
+  double* obs_edges = nullptr;     // bin edges of the last histogram call
+  unsigned long long* obs_flags = nullptr;   // [0] centres short of neighbours, [1] candidate overflow
+  double* msd_last = nullptr;      // [N][3] caller order: positions at the last sample
+  double* msd_acc = nullptr;       // [N][3] unwrapped displacement since the reference
+  bool msd_ready = false;
 };
 
 

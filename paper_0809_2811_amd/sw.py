@@ -38,7 +38,7 @@ SW_Q_TIME_MOMENTS_NS, SW_Q_TIME_FORCES_NS, SW_Q_TIMED_STEPS = 8, 9, 10
 # symbols declared in include/sw.h
 EXPORTS = ("sw_params_mw", "sw_create", "sw_destroy", "sw_build_neighbors", "sw_get_neighbors",
            "sw_forces", "sw_step", "sw_grad", "sw_adjoint", "sw_set_tuning", "sw_get_tuning",
-           "sw_query", "sw_status_string", "sw_last_hip_error")
+           "sw_query", "sw_status_string", "sw_last_hip_error", "sw_rdf", "sw_adf", "sw_msd")
 
 
 class sw_params(ctypes.Structure):
@@ -88,6 +88,9 @@ def lib():
         L.sw_query.argtypes = [vp, ip, P(ctypes.c_longlong)]
         L.sw_status_string.argtypes = [ip]; L.sw_status_string.restype = ctypes.c_char_p
         L.sw_last_hip_error.argtypes = [vp]
+        L.sw_rdf.argtypes = [vp, fp, ip, P(ctypes.c_double), vp, vp]
+        L.sw_adf.argtypes = [vp, fp, ip, dp, ip, P(ctypes.c_double), vp, P(ctypes.c_longlong), vp]
+        L.sw_msd.argtypes = [vp, fp, ip, vp, vp]
         _lib = L
     return _lib
 
@@ -220,6 +223,47 @@ def sw_adjoint(ctx: int, x0, v0, params: sw_params, mass: float, dt: float, nste
                             opt(xS, "xS"), opt(vS, "vS"), _stream()), "sw_adjoint")
 
 
+def _counts(t, shape, name):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or t.dtype != torch.int64 or not t.is_cuda:
+        raise TypeError(f"{name}: expected an int64 CUDA tensor (holds unsigned counts)")
+    if tuple(t.shape) != tuple(shape) or not t.is_contiguous():
+        raise ValueError(f"{name}: expected a contiguous {tuple(shape)} tensor, got {tuple(t.shape)}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _host_doubles(a, name):
+    import numpy as np
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    if a.ndim != 1 or len(a) < 2:
+        raise ValueError(f"{name}: expected at least two edges")
+    return a, a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def sw_rdf(ctx: int, x, r2_edges, counts, R: int = 1):
+    n = x.shape[0]
+    e, ep = _host_doubles(r2_edges, "r2_edges")
+    nb = len(e) - 1
+    _check(lib().sw_rdf(ctypes.c_void_p(ctx), _atoms(x, n, "x"), nb, ep, _counts(counts, (R, nb), "counts"),
+                        _stream()), "sw_rdf")
+
+
+def sw_adf(ctx: int, x, n_near: int, r_search: float, cos_edges, counts, R: int = 1) -> int:
+    n = x.shape[0]
+    e, ep = _host_doubles(cos_edges, "cos_edges")
+    nb = len(e) - 1
+    short = ctypes.c_longlong(0)
+    _check(lib().sw_adf(ctypes.c_void_p(ctx), _atoms(x, n, "x"), int(n_near), float(r_search), nb, ep,
+                        _counts(counts, (R, nb), "counts"), ctypes.byref(short), _stream()), "sw_adf")
+    return short.value
+
+
+def sw_msd(ctx: int, x, reset: bool, msd, R: int = 1):
+    n = x.shape[0]
+    _check(lib().sw_msd(ctypes.c_void_p(ctx), _atoms(x, n, "x"), 1 if reset else 0, _doubles(msd, (R,), "msd"),
+                        _stream()), "sw_msd")
+
+
 def sw_set_tuning(ctx: int, lanes_per_atom=8, graph_steps=0, persistent=0, rebuild_every=0, timing=0):
     t = sw_tuning(int(lanes_per_atom), int(graph_steps), int(persistent), int(rebuild_every), int(timing))
     _check(lib().sw_set_tuning(ctypes.c_void_p(ctx), ctypes.byref(t)), "sw_set_tuning")
@@ -326,6 +370,43 @@ class Context:
         sw_adjoint(self.handle, x0, v0, params, mass, dt, nsteps, ckpt_every, aU, a3, xbar_S, vbar_S, loss,
                    xbar0, vbar0, thbar, xS, vS, R=self.R)
         return dict(loss=loss, xbar0=xbar0, vbar0=vbar0, thbar=thbar, xS=xS, vS=vS)
+
+    def rdf(self, x, r_edges):
+        """Ordered-pair counts per distance bin (edges in A, ascending), per
+        replica: int64 tensor [R][len(r_edges) - 1] (see sw_rdf)."""
+        import numpy as np
+        torch = _torch()
+        e = np.asarray(r_edges, dtype=np.float64) ** 2
+        counts = torch.empty((self.R, len(e) - 1), dtype=torch.int64, device=x.device)
+        sw_rdf(self.handle, x, e, counts, R=self.R)
+        return counts
+
+    def adf(self, x, theta_edges_deg, n_near: int = 8, r_search: Optional[float] = None):
+        """Angle counts over the n_near closest neighbours (edges in degrees,
+        ascending), per replica, and the number of centres skipped for lack of
+        neighbours within r_search (default: the largest allowed)."""
+        import numpy as np
+        torch = _torch()
+        c = np.cos(np.radians(np.asarray(theta_edges_deg, dtype=np.float64)))
+        if r_search is None:
+            r_search = self.max_search_radius()
+        counts = torch.empty((self.R, len(c) - 1), dtype=torch.int64, device=x.device)
+        short = sw_adf(self.handle, x, n_near, r_search, c, counts, R=self.R)
+        return counts, short
+
+    def msd(self, x, reset: bool = False):
+        """Per-replica mean square displacement since the last reset (A^2)."""
+        torch = _torch()
+        out = torch.empty(self.R, dtype=torch.float64, device=x.device)
+        sw_msd(self.handle, x, reset, out, R=self.R)
+        return out
+
+    def max_search_radius(self) -> float:
+        """Smallest binning-cell edge: the largest r_max / r_search the
+        observables accept."""
+        import math
+        rl = self.cutoff + self.skin
+        return min(L / min(math.floor(L / rl), 1024) for box in self.boxes for L in box)
 
     def query(self, what: int) -> int:
         return sw_query(self.handle, what)
