@@ -68,6 +68,8 @@ def lib():
                                   c_double, dp, dp, dp, dp, dp, dp]
         L.ora_neighbour_counts.argtypes = [c_int, dp, dp, c_double, ip]
         L.ora_neighbour_lists.argtypes = [c_int, dp, dp, c_double, llp, ip]
+        L.ora_npt.argtypes = [c_int, dp, dp, dp, dp, c_double, c_double, c_int, c_double, c_double, c_double,
+                              c_double, c_int, dp, dp]
         u64p = ctypes.POINTER(ctypes.c_uint64)
         L.ora_quantize.argtypes = [c_int, dp, dp, ctypes.POINTER(ctypes.c_uint32)]
         L.ora_rdf.argtypes = [c_int, dp, dp, c_int, dp, u64p]
@@ -251,3 +253,26 @@ class Displacement:
         self.acc += d
         self.last = x.copy()
         return float(np.mean(np.sum(self.acc * self.acc, axis=1)))
+
+
+# ---------------------------------------------------------------- NPT
+BAR = 1e5 * 1e-30 * 6.02214076e23 / 4184.0      # kcal/mol/A^3 per bar
+NPT_STATE = 17
+NPT_ROW = 8
+
+
+def npt(x, v, box, nsteps, T0, p_bar=0.0, tau_T=1000.0, tau_P=2500.0, chain=3, state=None, dt=10.0,
+        mass=M_WATER, P=None):
+    """Nose-Hoover NPT (see ora_npt); returns the final x, v, box, extended
+    state and one row per step (V, P_int in bar, T, U, KE, pV, E_ext, H')."""
+    x = _d(x).copy(); v = _d(v).copy(); L = _d(box).copy()
+    st = np.zeros(NPT_STATE) if state is None else _d(state).copy()
+    rows = np.zeros((max(nsteps, 1), NPT_ROW))
+    P = params() if P is None else _d(P)
+    rc = lib().ora_npt(len(x), _ptr(x), _ptr(v), _ptr(L), _ptr(P), float(mass), float(dt), int(nsteps),
+                       float(T0), float(p_bar) * BAR, float(tau_T), float(tau_P), int(chain), _ptr(st), _ptr(rows))
+    if rc != 0:
+        raise ValueError(f"oracle npt: error {rc}")
+    rows = rows[:nsteps].copy()
+    rows[:, 1] /= BAR
+    return dict(x=x, v=v, box=L, state=st, rows=rows)

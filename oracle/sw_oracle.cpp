@@ -530,6 +530,122 @@ int ora_adjoint(int n, const double* x0, const double* v0, const double* L, cons
   return 0;
 }
 
+// Isothermal-isobaric dynamics (the Nose-Hoover thermostat and barostat of
+// Sec. II.B, relaxation times tau_T and tau_P, pressure p), read as the
+// isotropic Martyna-Tobias-Klein equations with Nose-Hoover chains of length M
+// on the particles (xi) and on the barostat (eta):
+//   dr/dt = v + v_e r,          dv/dt = a(r) - (1 + 3/Nf) v_e v - vxi_1 v
+//   dL/dt = v_e L (each edge),  dv_e/dt = [(1 + 3/Nf) sum m v^2 + W - 3 p V] / Wb - veta_1 v_e
+//   chains: dvxi_1/dt = (sum m v^2 - Nf kT)/Q_1 - vxi_2 vxi_1, ..., same for eta
+//           with Wb v_e^2 in place of sum m v^2 and 1 in place of Nf,
+// Nf = 3N - 3, W = virial trace, masses Q_1 = Nf kT tau_T^2, Q_k = kT tau_T^2,
+// Wb = (Nf + 3) kT tau_P^2, Q'_k = kT tau_P^2.  Conserved:
+//   H' = KE + U + p V + Wb v_e^2/2 + sum_k Q_k vxi_k^2/2 + Nf kT xi_1 + kT sum_{k>1} xi_k
+//        + sum_k Q'_k veta_k^2/2 + kT sum_k eta_k.
+// One step of length dt = 2h is the symmetric splitting
+//   chain(eta, h) chain(xi, h) baro(h) kick(h) drift(2h) kick(h) baro(h) chain(xi, h) chain(eta, h)
+// with the exact flows kick: v <- v e^{-c h} + h a e^{-c h/2} sinhc(c h/2), c = (1 + 3/Nf) v_e;
+// drift: r <- r e^{v_e dt} + v dt e^{v_e dt/2} sinhc(v_e dt/2), L <- L e^{v_e dt};
+// baro: v_e += h [(1 + 3/Nf) sum m v^2 + W - 3 p V] / Wb; and a chain half step
+// of one Suzuki-Yoshida stage.  Pressure p in kcal/mol/A^3.
+// state: [0] v_e, [1..4] xi, [5..8] vxi, [9..12] eta, [13..16] veta (chain M <= 4).
+// rows (may be NULL): per step, after the step: V, P_int (kcal/mol/A^3), T, U, KE,
+// p V, the extended energies, H'.
+namespace {
+double sinhc(double x) { return std::fabs(x) < 1e-4 ? 1.0 + x * x / 6.0 : std::sinh(x) / x; }
+
+// One chain half step of length h on a subsystem with kinetic term k2 (twice
+// its kinetic energy) and nf degrees of freedom; returns the velocity scale.
+double chain_half(double h, double& k2, double nf, double kT, const double* Q, double* xi, double* vxi, int M) {
+  auto G = [&](int k) { return k == 0 ? (k2 - nf * kT) / Q[0] : (Q[k - 1] * vxi[k - 1] * vxi[k - 1] - kT) / Q[k]; };
+  vxi[M - 1] += 0.5 * h * G(M - 1);
+  for (int k = M - 2; k >= 0; --k) {
+    const double e = std::exp(-0.25 * h * vxi[k + 1]);
+    vxi[k] = (vxi[k] * e + 0.5 * h * G(k)) * e;
+  }
+  const double s = std::exp(-h * vxi[0]);
+  k2 *= s * s;
+  for (int k = 0; k < M; ++k) xi[k] += h * vxi[k];
+  for (int k = 0; k < M - 1; ++k) {
+    const double e = std::exp(-0.25 * h * vxi[k + 1]);
+    vxi[k] = (vxi[k] * e + 0.5 * h * G(k)) * e;
+  }
+  vxi[M - 1] += 0.5 * h * G(M - 1);
+  return s;
+}
+}  // namespace
+
+int ora_npt(int n, double* x, double* v, double* L, const double* P, double mass, double dt, int nsteps,
+            double T0, double p_ext, double tauT, double tauP, int M, double* state, double* rows) {
+  if (M < 1 || M > 4 || n < 2) return -2;
+  const double rc = P[8] * P[2];
+  for (int c = 0; c < 3; ++c) if (L[c] < 2.0 * rc) return -1;
+  const double c_m = kAcc / mass, h = 0.5 * dt;
+  const double nf = 3.0 * n - 3.0, kT = kBoltz * T0, alpha = 1.0 + 3.0 / nf;
+  double Q[4], Qb[4];
+  for (int k = 0; k < 4; ++k) {
+    Q[k] = (k == 0 ? nf : 1.0) * kT * tauT * tauT;
+    Qb[k] = kT * tauP * tauP;
+  }
+  const double Wb = (nf + 3.0) * kT * tauP * tauP;
+  double& ve = state[0];
+  double *xi = state + 1, *vxi = state + 5, *eta = state + 9, *veta = state + 13;
+  Box b = make_box(L);
+  Eval ev = eval_value(n, x, b, P);
+  auto vir = [&]() { return ev.w2[0] + ev.w2[4] + ev.w2[8] + ev.w3[0] + ev.w3[4] + ev.w3[8]; };
+  auto k2_of = [&]() { return 2.0 * kinetic(n, v, mass, nullptr); };
+  auto baro = [&](double k2) {
+    const double V = b.L[0] * b.L[1] * b.L[2];
+    ve += h * (alpha * k2 + vir() - 3.0 * p_ext * V) / Wb;
+  };
+  auto kick = [&]() {
+    const double c = alpha * ve;
+    const double ea = std::exp(-c * h), eb = h * c_m * std::exp(-0.5 * c * h) * sinhc(0.5 * c * h);
+    for (int i = 0; i < 3 * n; ++i) v[i] = v[i] * ea + eb * ev.f[i];
+  };
+  auto chains = [&](double& k2, bool first) {
+    double kb = Wb * ve * ve;
+    if (first) {
+      ve *= chain_half(h, kb, 1.0, kT, Qb, eta, veta, M);
+      const double s = chain_half(h, k2, nf, kT, Q, xi, vxi, M);
+      for (int i = 0; i < 3 * n; ++i) v[i] *= s;
+    } else {
+      const double s = chain_half(h, k2, nf, kT, Q, xi, vxi, M);
+      for (int i = 0; i < 3 * n; ++i) v[i] *= s;
+      kb = Wb * ve * ve;
+      ve *= chain_half(h, kb, 1.0, kT, Qb, eta, veta, M);
+    }
+  };
+  for (int s = 0; s < nsteps; ++s) {
+    double k2 = k2_of();
+    chains(k2, true);
+    baro(k2_of());
+    kick();
+    const double g = std::exp(ve * dt), d = dt * std::exp(0.5 * ve * dt) * sinhc(0.5 * ve * dt);
+    for (int i = 0; i < 3 * n; ++i) x[i] = x[i] * g + v[i] * d;
+    for (int c = 0; c < 3; ++c) b.L[c] *= g;
+    wrap_positions(n, x, b);
+    ev = eval_value(n, x, b, P);
+    kick();
+    baro(k2_of());
+    k2 = k2_of();
+    chains(k2, false);
+    if (rows) {
+      const double V = b.L[0] * b.L[1] * b.L[2];
+      const double ke = 0.5 * k2_of(), U = ev.e[0] + ev.e[1];
+      double ext = 0.5 * Wb * ve * ve;
+      for (int k = 0; k < M; ++k)
+        ext += 0.5 * Q[k] * vxi[k] * vxi[k] + (k == 0 ? nf : 1.0) * kT * xi[k] + 0.5 * Qb[k] * veta[k] * veta[k] +
+               kT * eta[k];
+      double* row = rows + 8 * (size_t)s;
+      row[0] = V; row[1] = (2.0 * ke + vir()) / (3.0 * V); row[2] = 2.0 * ke / (nf * kBoltz); row[3] = U;
+      row[4] = ke; row[5] = p_ext * V; row[6] = ext; row[7] = ke + U + p_ext * V + ext;
+    }
+  }
+  for (int c = 0; c < 3; ++c) L[c] = b.L[c];
+  return 0;
+}
+
 // Number of neighbours within rc of each atom (for list-capacity checks).
 int ora_neighbour_counts(int n, const double* x, const double* L, double rc, int* counts) {
   Box b = make_box(L);
