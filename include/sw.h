@@ -220,6 +220,40 @@ int sw_adf(sw_ctx* ctx, const float* x, int n_near, double r_search, int nbins,
  *  SW_ESTATE if the first call does not reset. */
 int sw_msd(sw_ctx* ctx, const float* x, int reset, double* msd, void* stream);
 
+/* Isothermal-isobaric dynamics: the Nose-Hoover thermostat and barostat of
+ * Sec. II.B (relaxation times tau_T = 1 ps and tau_P = 2.5 ps in the paper,
+ * p = 0), read as the isotropic Martyna-Tobias-Klein equations with
+ * Nose-Hoover chains of length `chain` on the particles (xi) and on the
+ * barostat (eta).  With N_f = 3N_r - 3, kT = k_B T0_r, the masses are
+ * Q_1 = N_f kT tau_T^2, Q_k = kT tau_T^2, W = (N_f + 3) kT tau_P^2 and
+ * Q'_k = kT tau_P^2.  One step of length dt is the symmetric splitting
+ *   chain(eta) chain(xi) barostat kick drift kick barostat chain(xi) chain(eta)
+ * (half steps except the drift), exact flows for the kicks
+ * v <- v e^{-c h} + h a e^{-c h/2} sinh(c h/2)/(c h/2), c = (1 + 3/N_f) v_e, and
+ * the drift, which scales every box edge by e^{v_e dt}.  Every replica has
+ * its own box, T0 and pressure; the boxes persist in the context (sw_get_box)
+ * and so do the extended variables (sw_npt_state) between calls.
+ *  x, v, f   as for sw_step (positions in A in the box at the end).
+ *  h_T0      host double[R] K;  h_p_bar host double[R] bar.
+ *  chain     1..4 (the paper names no chain length; 3 is customary).
+ *  reset     nonzero: extended variables start from zero (box kept).
+ *  rows      device double[nsteps / every][R][SW_NPT_WIDTH] out, may be NULL:
+ *            after each recorded step: V (A^3), P_int (bar), T (K), U, KE,
+ *            p V, extended energy, conserved H' (kcal/mol).
+ * Cell grids are rebuilt with a margin when a box shrinks toward its
+ * cutoff + skin edge; the call is then redone from its inputs.
+ * Synchronises. */
+#define SW_NPT_WIDTH 8
+#define SW_NPT_STATE 17   /* v_e, xi[4], vxi[4], eta[4], veta[4] per replica */
+int sw_npt(sw_ctx* ctx, float* x, float* v, float* f, const sw_params* params, double mass,
+           double dt, int nsteps, const double* h_T0, const double* h_p_bar, double tau_T_fs,
+           double tau_P_fs, int chain, int reset, double* rows, int every, void* stream);
+/* Current box edges: host double[R][3] out (A). */
+int sw_get_box(const sw_ctx* ctx, double* h_box);
+/* Extended variables of sw_npt: host double[R][SW_NPT_STATE]; set = 0 reads
+ * them, set != 0 replaces them (the box is not part of this state). */
+int sw_npt_state(sw_ctx* ctx, double* h_state, int set);
+
 /* Execution options (chosen by the autotuner). */
 typedef struct sw_tuning {
   int lanes_per_atom;   /* 4, 8, 16 or 32 lanes of a wavefront share one atom  */
@@ -247,6 +281,8 @@ enum {
   SW_Q_CELL_CAPACITY = 5,
   SW_Q_DEVICE_BYTES = 6,  /* device memory owned by the context        */
   SW_Q_STEPS = 7,         /* integration steps since creation          */
+  SW_Q_MIN_CELL_EDGE = 11, /* smallest binning-cell edge in 1e-6 A (the
+                              observables' search-radius limit)            */
   SW_Q_TIME_MOMENTS_NS = 8, /* summed event time of sampled moments launches */
   SW_Q_TIME_FORCES_NS = 9,  /* summed event time of sampled force launches   */
   SW_Q_TIMED_STEPS = 10     /* number of sampled steps (reset by sw_set_tuning) */

@@ -33,20 +33,56 @@ int fail_hip(sw_ctx* c, hipError_t e) {
   return SW_EHIP;
 }
 
-template <class T>
-hipError_t dalloc(sw_ctx* c, T** p, size_t n, std::vector<void*>& list) {
+hipError_t dalloc_raw(sw_ctx* c, void** p, size_t bytes, std::vector<void*>& list) {
   *p = nullptr;
-  if (n == 0) n = 1;
-  hipError_t e = hipMalloc((void**)p, n * sizeof(T));
+  if (bytes == 0) bytes = 1;
+  hipError_t e = hipMalloc(p, bytes);
   if (e != hipSuccess) return e;
-  list.push_back((void*)*p);
-  c->bytes += n * sizeof(T);
+  list.push_back(*p);
+  c->sizes[*p] = bytes;
   return hipSuccess;
 }
 
-void free_list(std::vector<void*>& list) {
-  for (void* p : list) (void)hipFree(p);
+template <class T>
+hipError_t dalloc(sw_ctx* c, T** p, size_t n, std::vector<void*>& list) {
+  return dalloc_raw(c, (void**)p, std::max<size_t>(n, 1) * sizeof(T), list);
+}
+
+void free_list(sw_ctx* c, std::vector<void*>& list) {
+  for (void* p : list) {
+    (void)hipFree(p);
+    c->sizes.erase(p);
+  }
   list.clear();
+}
+
+// Frees one allocation of the context's main list.
+void dfree(sw_ctx* c, void* p) {
+  if (!p) return;
+  (void)hipFree(p);
+  c->sizes.erase(p);
+  auto& L = c->allocs;
+  L.erase(std::remove(L.begin(), L.end(), p), L.end());
+}
+
+size_t device_bytes(const sw_ctx* c) {
+  size_t b = 0;
+  for (const auto& kv : c->sizes) b += kv.second;
+  return b;
+}
+
+// Morton rank of every cell of replica R (cells numbered from coff) into rank.
+void cell_ranks(const RepInfo& R, int coff, std::vector<int>& rank) {
+  std::vector<std::pair<unsigned, int>> codes(R.ncell);
+  for (int x = 0; x < R.nc[0]; ++x)
+    for (int y = 0; y < R.nc[1]; ++y)
+      for (int z = 0; z < R.nc[2]; ++z) {
+        const int local = (x * R.nc[1] + y) * R.nc[2] + z;
+        codes[local] = {(part1by2(x) << 2) | (part1by2(y) << 1) | part1by2(z), local};
+      }
+  std::sort(codes.begin(), codes.end());
+  rank.resize(coff + R.ncell);
+  for (int k = 0; k < R.ncell; ++k) rank[coff + codes[k].second] = coff + k;
 }
 
 int lpa_for(const sw_ctx* c) {
@@ -59,7 +95,7 @@ int lpa_for(const sw_ctx* c) {
 
 // Buffers whose size depends on the row and cell capacities.
 hipError_t alloc_capacity(sw_ctx* c) {
-  free_list(c->grow_allocs);
+  free_list(c, c->grow_allocs);
   hipError_t e;
   if ((e = dalloc(c, &c->d.nl, (size_t)c->npad * c->cap, c->grow_allocs)) != hipSuccess) return e;
   for (int k = 0; k < 2; ++k)
@@ -90,6 +126,8 @@ hipError_t alloc_all(sw_ctx* c) {
   SWA(c->d_uoff, (size_t)c->R + 1);
   SWA(c->d_cell_rank, (size_t)c->ctot);
   SWA(c->d_T0, (size_t)c->R);
+  SWA(c->d.lref, (size_t)c->R);
+  SWA(c->d_kick, (size_t)c->R);
   SWA(c->d_uq, (size_t)c->N); SWA(c->d_key, (size_t)c->N); SWA(c->d_order, (size_t)c->N);
   SWA(c->d_scnt, (size_t)c->ctot); SWA(c->d_sstart, (size_t)c->ctot); SWA(c->d_scur, (size_t)c->ctot);
   SWA(c->t.w, np); SWA(c->t.mdot, 3 * np); SWA(c->t.fdot, np); SWA(c->t.f3, np);
@@ -100,6 +138,7 @@ hipError_t alloc_all(sw_ctx* c) {
   c->d.reps = c->d_reps;
   c->d.tile_rep = c->d_tile_rep;
   c->d.T0 = c->d_T0;
+  c->d.npt_kick = c->d_kick;
   c->d.npad = c->npad;
   c->d.ctot = c->ctot;
   c->d.R = c->R;
@@ -164,6 +203,7 @@ hipError_t read_flags(sw_ctx* c, hipStream_t s, Flags* f) {
   f->cell_over = h[F_CELL_OVER];
   f->overlap = h[F_OVERLAP];
   f->abort = h[F_ABORT];
+  f->box = h[F_BOX];
   return hipSuccess;
 }
 
@@ -185,6 +225,48 @@ int grow(sw_ctx* c, const Flags& f) {
   if (!grew) return SW_EINVAL;
   hipError_t e = alloc_capacity(c);
   if (e != hipSuccess) return e == hipErrorOutOfMemory ? SW_ENOMEM : fail_hip(c, e);
+  c->have_order = false;
+  return SW_OK;
+}
+
+// Recomputes every replica's binning grid from its current box so that a
+// cell edge is at least (cutoff + skin)(1 + margin), and reallocates the
+// grid-sized buffers if the grid changed.
+int regrid(sw_ctx* c, double margin) {
+  const double rl = c->cutoff + c->skin;
+  bool same = true;
+  std::vector<RepInfo> reps = c->reps;
+  for (int r = 0; r < c->R; ++r)
+    for (int k = 0; k < 3; ++k) {
+      const int nc = std::min((int)std::floor(c->box[3 * r + k] / (rl * (1.0 + margin))), 1024);
+      if (nc < 3) return SW_EBOX_TOO_SMALL;
+      same = same && nc == reps[r].nc[k];
+      reps[r].nc[k] = nc;
+    }
+  if (same) return SW_OK;
+  std::vector<int> rank;
+  int coff = 0;
+  for (auto& R : reps) {
+    R.ncell = R.nc[0] * R.nc[1] * R.nc[2];
+    R.cell_off = coff;
+    cell_ranks(R, coff, rank);
+    coff += R.ncell;
+  }
+  c->reps = reps;
+  c->cell_rank = rank;
+  c->ctot = coff;
+  hipError_t e;
+  for (int** p : {&c->d.gcnt[0], &c->d.gcnt[1], &c->d_cell_rank, &c->d_scnt, &c->d_sstart, &c->d_scur}) {
+    dfree(c, *p);
+    if ((e = dalloc(c, p, (size_t)c->ctot, c->allocs)) != hipSuccess)
+      return e == hipErrorOutOfMemory ? SW_ENOMEM : fail_hip(c, e);
+  }
+  if ((e = alloc_capacity(c)) != hipSuccess) return e == hipErrorOutOfMemory ? SW_ENOMEM : fail_hip(c, e);
+  c->d.ctot = c->ctot;
+  if ((e = hipMemcpy(c->d_reps, c->reps.data(), sizeof(RepInfo) * c->R, hipMemcpyHostToDevice)) != hipSuccess ||
+      (e = hipMemcpy(c->d_cell_rank, c->cell_rank.data(), sizeof(int) * c->ctot, hipMemcpyHostToDevice)) !=
+          hipSuccess)
+    return fail_hip(c, e);
   c->have_order = false;
   return SW_OK;
 }
@@ -351,17 +433,7 @@ int sw_create(sw_ctx** out, int n_replicas, const long long* h_offsets, const do
     R.ipad_end = ioff + ((n + kTile - 1) / kTile) * kTile;
     R.uoff = h_offsets[r];
     R.ndof_kb = (3.0 * n - 3.0) * kBoltz;
-    // Morton rank of every cell of this replica
-    std::vector<std::pair<unsigned, int>> codes(R.ncell);
-    for (int x = 0; x < R.nc[0]; ++x)
-      for (int y = 0; y < R.nc[1]; ++y)
-        for (int z = 0; z < R.nc[2]; ++z) {
-          const int local = (x * R.nc[1] + y) * R.nc[2] + z;
-          codes[local] = {(part1by2(x) << 2) | (part1by2(y) << 1) | part1by2(z), local};
-        }
-    std::sort(codes.begin(), codes.end());
-    c->cell_rank.resize(coff + R.ncell);
-    for (int k = 0; k < R.ncell; ++k) c->cell_rank[coff + codes[k].second] = coff + k;
+    cell_ranks(R, coff, c->cell_rank);
     for (int t = ioff / kTile; t < R.ipad_end / kTile; ++t) c->tile_rep.push_back(r);
     ioff = R.ipad_end;
     coff += R.ncell;
@@ -375,8 +447,8 @@ int sw_create(sw_ctx** out, int n_replicas, const long long* h_offsets, const do
   c->cc = std::max(32, (int)std::ceil(4.0 * mean / 8.0) * 8);
   hipError_t e = alloc_all(c);
   if (e != hipSuccess) {
-    free_list(c->grow_allocs);
-    free_list(c->allocs);
+    free_list(c, c->grow_allocs);
+    free_list(c, c->allocs);
     delete c;
     return e == hipErrorOutOfMemory ? SW_ENOMEM : SW_EHIP;
   }
@@ -392,8 +464,8 @@ void sw_destroy(sw_ctx* ctx) {
   if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
   if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
   if (ctx->ring) (void)hipFree(ctx->ring);
-  free_list(ctx->grow_allocs);
-  free_list(ctx->allocs);
+  free_list(ctx, ctx->grow_allocs);
+  free_list(ctx, ctx->allocs);
   delete ctx;
 }
 
@@ -613,11 +685,18 @@ int sw_query(sw_ctx* ctx, int what, long long* out) {
     case SW_Q_NREPLICAS: *out = ctx->R; return SW_OK;
     case SW_Q_NBR_CAPACITY: *out = ctx->cap; return SW_OK;
     case SW_Q_CELL_CAPACITY: *out = ctx->cc; return SW_OK;
-    case SW_Q_DEVICE_BYTES: *out = (long long)ctx->bytes; return SW_OK;
+    case SW_Q_DEVICE_BYTES: *out = (long long)device_bytes(ctx); return SW_OK;
     case SW_Q_STEPS: *out = ctx->steps; return SW_OK;
     case SW_Q_TIME_MOMENTS_NS: *out = (long long)(ctx->t_mom_ms * 1e6); return SW_OK;
     case SW_Q_TIME_FORCES_NS: *out = (long long)(ctx->t_for_ms * 1e6); return SW_OK;
     case SW_Q_TIMED_STEPS: *out = ctx->t_samples; return SW_OK;
+    case SW_Q_MIN_CELL_EDGE: {
+      double m = 1e300;
+      for (const RepInfo& R : ctx->reps)
+        for (int k = 0; k < 3; ++k) m = std::min(m, R.L[k] / R.nc[k]);
+      *out = (long long)std::floor(m * 1e6);
+      return SW_OK;
+    }
     case SW_Q_REBUILDS: {
       int h[F_NFLAGS];
       hipError_t e = hipDeviceSynchronize();

@@ -3,6 +3,7 @@
 #include "sw.h"
 #include "sw_internal.h"
 
+#include <unordered_map>
 #include <vector>
 
 using swk::RepInfo;
@@ -46,7 +47,7 @@ struct sw_ctx {
   bool have_order = false;
   long long steps = 0;
   int last_hip = 0;
-  size_t bytes = 0;
+  std::unordered_map<void*, size_t> sizes;   // live device allocations
   std::vector<void*> allocs;       // everything freed by free_all
   std::vector<void*> grow_allocs;  // capacity-dependent buffers
   // observables (allocated on first use)
@@ -55,6 +56,12 @@ struct sw_ctx {
   double* msd_last = nullptr;      // [N][3] caller order: positions at the last sample
   double* msd_acc = nullptr;       // [N][3] unwrapped displacement since the reference
   bool msd_ready = false;
+  // isobaric dynamics (allocated on first use)
+  swk::NptState* d_npt = nullptr;  // [2][R] double-buffered extended state
+  double* d_pext = nullptr;        // [R]
+  float2* d_kick = nullptr;        // [R] isobaric kick coefficients (Dev::npt_kick)
+  std::vector<swk::NptState> npt;  // host copy between calls
+  bool npt_ready = false;
 };
 
 
@@ -64,9 +71,12 @@ int fail_hip(sw_ctx* c, hipError_t e);
 int lpa_for(const sw_ctx* c);
 int make_phys(const sw_ctx* c, const sw_params* P, double mass, double dt, Phys* o);
 hipError_t reset_flags(sw_ctx* c, hipStream_t s);
-struct Flags { int nbr_over, nbr_need, cell_over, overlap, abort; };
+struct Flags { int nbr_over, nbr_need, cell_over, overlap, abort, box; };
 hipError_t read_flags(sw_ctx* c, hipStream_t s, Flags* f);
 int grow(sw_ctx* c, const Flags& f);
 hipError_t sort_in(sw_ctx* c, const float* x, const float* v, hipStream_t s);
 bool valid_ptr(const void* p);
+int regrid(sw_ctx* c, double margin);
+hipError_t dalloc_raw(sw_ctx* c, void** p, size_t bytes, std::vector<void*>& list);
+size_t device_bytes(const sw_ctx* c);
 }  // namespace swh

@@ -34,11 +34,12 @@ __host__ __device__ constexpr size_t moments_lds_bytes(int apb, int cap) {
 constexpr double kAcc = 4.184e-4;  // (A/fs^2) per ((kcal/mol/A)/(g/mol))
 constexpr double kBoltz = 8.314462618 / 4184.0;  // kcal/(mol K)
 constexpr double kTwo32 = 4294967296.0;
+constexpr double kBar = 1e5 * 1e-30 * 6.02214076e23 / 4184.0;   // kcal/mol/A^3 per bar
 
 // Flag slots in Dev::flags.
 // Slots below F_REBUILDS are cleared at the start of every call; F_REBUILDS
 // counts row rebuilds over the context's lifetime.
-enum { F_NBR_OVER = 0, F_NBR_NEED = 1, F_CELL_OVER = 2, F_OVERLAP = 3, F_ABORT = 4, F_REBUILDS = 7,
+enum { F_NBR_OVER = 0, F_NBR_NEED = 1, F_CELL_OVER = 2, F_OVERLAP = 3, F_ABORT = 4, F_BOX = 5, F_REBUILDS = 7,
        F_NFLAGS = 8 };
 
 struct RepInfo {
@@ -76,6 +77,8 @@ struct Dev {
   const RepInfo* reps;
   const int* tile_rep; // [Npad / 64] replica of each 64-atom tile
   const double* T0;    // [R] thermostat targets
+  const float2* npt_kick;  // [R] (a, b) of the isobaric half kick v <- a v + b F
+  double* lref;        // [R] box edge 0 at the replica's last row build
   int npad, cap, cc, ctot, R;
 };
 
@@ -97,7 +100,31 @@ struct Phys {
 };
 
 // Kernel modes of the force kernel.
-enum { MODE_FORCES = 0, MODE_START = 1, MODE_NVE = 2, MODE_NVE_LAST = 3, MODE_KICK = 4 };
+enum { MODE_FORCES = 0, MODE_START = 1, MODE_NVE = 2, MODE_NVE_LAST = 3, MODE_KICK = 4, MODE_NPT = 5 };
+
+// Isothermal-isobaric dynamics (Nose-Hoover chains on the particles and on
+// an isotropic barostat).  One replica's extended variables, FP64.
+constexpr int kNptChain = 4;
+struct NptState {
+  double L[3];                             // box edges (A)
+  double ve;                               // barostat rate v_e (1/fs)
+  double xi[kNptChain], vxi[kNptChain];    // particle chain
+  double eta[kNptChain], veta[kNptChain];  // barostat chain
+};
+enum { NPT_BEGIN = 1, NPT_STEP = 3, NPT_END = 2 };   // bit 1: open a step, bit 2: close the previous one
+struct NptArgs {
+  const NptState* in;    // [R] state before this launch
+  NptState* out;         // [R] state after it
+  RepInfo* reps;         // writable view: box edges and scales follow the state
+  float2* kick;          // [R] kick coefficients of the step opened here
+  const double* pext;    // [R] external pressure (kcal/mol/A^3)
+  double tauT, tauP, rl, rc, dt, c_m;
+  int chain;             // chain length 1..kNptChain
+  int mode;              // NPT_BEGIN / NPT_STEP / NPT_END
+  int par;               // parity of the positions this launch reads
+  double* row;           // [R][kNptRow] record of the step closed here, or null
+};
+constexpr int kNptRow = 8;
 
 // Optional start/stop events recorded at a launch's dispatch.
 struct KTimer {
@@ -121,6 +148,7 @@ hipError_t launch_copy_thermo(const Dev& d, double* energy, double* virial, hipS
 hipError_t launch_fill_i32(int* p, int value, long long n, hipStream_t s);
 hipError_t launch_fill_f32(float* p, float value, long long n, hipStream_t s);
 hipError_t launch_fill_f64(double* p, double value, long long n, hipStream_t s);
+hipError_t launch_npt_kick(const Dev& d, const Phys& p, const NptArgs& a, hipStream_t s);
 
 // Persistent cooperative launch of steps t0..t1 of an sw_step call.
 struct PArgs {

@@ -41,21 +41,22 @@ __device__ __forceinline__ Geo geo_of(const RepInfo& R) {
              R.nc[0], R.nc[1], R.nc[2], R.cell_off};
 }
 
-// Drift by dt*v in fraction units, bin into grid `gp`, and raise the
-// replica's rebuild flag if the atom is now more than half the skin away from
-// its row-build position.  Flags steps longer than a quarter edge.
-__device__ __forceinline__ void drift_bin(const Dev& d, const Phys& p, const Geo& G, int rep, int i, uint4 u,
-                                          const float4& v, const uint4& uref, int gp) {
-  const float mx = p.dt * v.x * G.is0;
-  const float my = p.dt * v.y * G.is1;
-  const float mz = p.dt * v.z * G.is2;
+// Drift by tx*v in fraction units (tx = dt, or its isobaric equivalent),
+// bin into grid `gp`, and raise the replica's rebuild flag if the atom is now
+// more than hs (half the effective skin) away from its row-build position.
+// Flags steps longer than a quarter edge.
+__device__ __forceinline__ void drift_bin(const Dev& d, const Geo& G, int rep, int i, uint4 u, const float4& v,
+                                          const uint4& uref, float tx, float hs, int gp) {
+  const float mx = tx * v.x * G.is0;
+  const float my = tx * v.y * G.is1;
+  const float mz = tx * v.z * G.is2;
   const float lim = 1073741824.0f;  // 2^30: a quarter of the edge
   if (!(fabsf(mx) < lim && fabsf(my) < lim && fabsf(mz) < lim)) atomicOr(&d.flags[F_OVERLAP], 2);
   u.x += (unsigned)__float2int_rn(fminf(fmaxf(mx, -lim), lim));
   u.y += (unsigned)__float2int_rn(fminf(fmaxf(my, -lim), lim));
   u.z += (unsigned)__float2int_rn(fminf(fmaxf(mz, -lim), lim));
   const float3 dd = disp(uref, u, G.sc0, G.sc1, G.sc2);
-  const bool moved = dd.x * dd.x + dd.y * dd.y + dd.z * dd.z > p.half_skin * p.half_skin;
+  const bool moved = dd.x * dd.x + dd.y * dd.y + dd.z * dd.z > hs * hs;
   d.u[gp][i] = u;
   const int c = G.cell_off + cell_of(u, G.nc0, G.nc1, G.nc2);
   const int slot = atomicAdd(&d.gcnt[gp][c], 1);
@@ -353,7 +354,10 @@ __device__ void moments_tile(const Dev& d, const Phys& p, int par, int force_reb
     row = srt;
 #pragma unroll
     for (int u = 0; u < kMU; ++u) jn[u] = srt[min(lane + u * LPA, cap - 1)];
-    if (bid * APB == ioff && threadIdx.x == 0) atomicAdd(&d.flags[F_REBUILDS], 1);
+    if (bid * APB == ioff && threadIdx.x == 0) {
+      atomicAdd(&d.flags[F_REBUILDS], 1);
+      d.lref[rep] = R.L[0];
+    }
   }
 
   float T0 = 0.f, T1 = 0.f, T2 = 0.f, T3 = 0.f, T4 = 0.f, T5 = 0.f;
@@ -587,7 +591,7 @@ __device__ void forces_tile(const Dev& d, const Phys& p, int par, int bid) {
     w3 = group_sum<LPA>(w3); w4 = group_sum<LPA>(w4); w5 = group_sum<LPA>(w5);
   }
 
-  constexpr bool kReduce = VIR || MODE == MODE_KICK;
+  constexpr bool kReduce = VIR || MODE == MODE_KICK || MODE == MODE_NPT;
   double q[kNQ];
 #pragma unroll
   for (int k = 0; k < kNQ; ++k) q[k] = 0.0;
@@ -598,7 +602,15 @@ __device__ void forces_tile(const Dev& d, const Phys& p, int par, int bid) {
       q[0] = E2i; q[1] = E3i;
       q[3] = w0; q[4] = w1; q[5] = w2; q[6] = w3; q[7] = w4; q[8] = w5;
     }
-    if (MODE != MODE_FORCES) {
+    if (MODE == MODE_NPT) {
+      const float2 k = d.npt_kick[rep];
+      float4 v = vi;
+      v.x = k.x * v.x + k.y * F.x; v.y = k.x * v.y + k.y * F.y; v.z = k.x * v.z + k.y * F.z;
+      const float vx2 = v.x * v.x, vy2 = v.y * v.y, vz2 = v.z * v.z;
+      q[2] = (double)(p.half_m_acc * (vx2 + vy2 + vz2));
+      q[9] = (double)(p.m_acc * vx2); q[10] = (double)(p.m_acc * vy2); q[11] = (double)(p.m_acc * vz2);
+      d.v[i] = v;
+    } else if (MODE != MODE_FORCES) {
       float4 v = vi;
       v.x += p.hdt_cm * F.x; v.y += p.hdt_cm * F.y; v.z += p.hdt_cm * F.z;
       if (MODE != MODE_START) {
@@ -609,7 +621,7 @@ __device__ void forces_tile(const Dev& d, const Phys& p, int par, int bid) {
       if (MODE == MODE_NVE) {
         v.x += p.hdt_cm * F.x; v.y += p.hdt_cm * F.y; v.z += p.hdt_cm * F.z;
       }
-      if (MODE == MODE_START || MODE == MODE_NVE) drift_bin(d, p, G, rep, i, ui, v, urefi, par ^ 1);
+      if (MODE == MODE_START || MODE == MODE_NVE) drift_bin(d, G, rep, i, ui, v, urefi, p.dt, p.half_skin, par ^ 1);
       d.v[i] = v;
     }
   }
@@ -670,7 +682,7 @@ __device__ __forceinline__ void thermostat_atom(const Dev& d, const Phys& p, int
       if (!last) {
         const float4 F = d.f[i];
         v.x += p.hdt_cm * F.x; v.y += p.hdt_cm * F.y; v.z += p.hdt_cm * F.z;
-        drift_bin(d, p, geo_of(R), rep, i, d.u[par][i], v, d.uref[i], par ^ 1);
+        drift_bin(d, geo_of(R), rep, i, d.u[par][i], v, d.uref[i], p.dt, p.half_skin, par ^ 1);
       }
       d.v[i] = v;
     }
@@ -679,6 +691,125 @@ __device__ __forceinline__ void thermostat_atom(const Dev& d, const Phys& p, int
 
 __global__ __launch_bounds__(kBlock) void k_thermostat(Dev d, Phys p, int par, int last) {
   thermostat_atom(d, p, par, last, blockIdx.x * kBlock + threadIdx.x);
+}
+
+// ----------------------------------------------------------------- isobaric
+// Nose-Hoover chains and the isotropic barostat (the thermostat and barostat
+// of Sec. II.B, read as the Martyna-Tobias-Klein equations; one step of
+// length dt = 2h is the symmetric splitting
+//   chain(eta) chain(xi) baro kick(h) drift(dt) kick(h) baro chain(xi) chain(eta)).
+// One launch closes the previous step (baro, particle chain, barostat chain,
+// record) and opens the next one (barostat chain, particle chain, baro,
+// first kick, drift with the box scaling, binning); the force launch makes
+// the second kick.  The per-replica arithmetic is FP64 and repeated by every
+// thread of the replica (identical inputs, identical results); the thread
+// of the replica's first atom stores the new state, box and kick
+// coefficients.
+
+__device__ __forceinline__ double sinhc_d(double x) { return fabs(x) < 1e-4 ? 1.0 + x * x / 6.0 : sinh(x) / x; }
+
+// One chain half step of length h on a subsystem with kinetic term k2 (twice
+// its kinetic energy) and nf degrees of freedom; returns the velocity scale.
+__device__ double chain_half(double h, double& k2, double nf, double kT, const double* Q, double* x, double* vx,
+                             int M) {
+  auto g = [&](int k) { return k == 0 ? (k2 - nf * kT) / Q[0] : (Q[k - 1] * vx[k - 1] * vx[k - 1] - kT) / Q[k]; };
+  vx[M - 1] += 0.5 * h * g(M - 1);
+  for (int k = M - 2; k >= 0; --k) {
+    const double e = exp(-0.25 * h * vx[k + 1]);
+    vx[k] = (vx[k] * e + 0.5 * h * g(k)) * e;
+  }
+  const double sc = exp(-h * vx[0]);
+  k2 *= sc * sc;
+  for (int k = 0; k < M; ++k) x[k] += h * vx[k];
+  for (int k = 0; k < M - 1; ++k) {
+    const double e = exp(-0.25 * h * vx[k + 1]);
+    vx[k] = (vx[k] * e + 0.5 * h * g(k)) * e;
+  }
+  vx[M - 1] += 0.5 * h * g(M - 1);
+  return sc;
+}
+
+__global__ __launch_bounds__(kBlock) void k_npt_kick(Dev d, Phys p, NptArgs a) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= d.npad) return;
+  const int rep = d.tile_rep[i >> 6];
+  const RepInfo& R = d.reps[rep];
+  NptState st = a.in[rep];
+  const int M = a.chain;
+  const double h = 0.5 * a.dt;
+  const double nf = 3.0 * R.n - 3.0, kT = kBoltz * d.T0[rep], alpha = 1.0 + 3.0 / nf;
+  double Q[kNptChain], Qb[kNptChain];
+  for (int k = 0; k < kNptChain; ++k) {
+    Q[k] = (k == 0 ? nf : 1.0) * kT * a.tauT * a.tauT;
+    Qb[k] = kT * a.tauP * a.tauP;
+  }
+  const double Wb = (nf + 3.0) * kT * a.tauP * a.tauP;
+  const double pext = a.pext[rep];
+  const double* th = d.thermo_cur + (size_t)rep * kNQ;
+  const double W = th[3] + th[4] + th[5];
+  double k2 = 2.0 * th[2];
+  double vs = 1.0;
+  const bool lead = i == R.ioff;
+  if (a.mode & NPT_END) {
+    const double V = st.L[0] * st.L[1] * st.L[2];
+    st.ve += h * (alpha * k2 + W - 3.0 * pext * V) / Wb;
+    vs = chain_half(h, k2, nf, kT, Q, st.xi, st.vxi, M);
+    double kb2 = Wb * st.ve * st.ve;
+    st.ve *= chain_half(h, kb2, 1.0, kT, Qb, st.eta, st.veta, M);
+    if (lead && a.row) {
+      double ext = 0.5 * Wb * st.ve * st.ve;
+      for (int k = 0; k < M; ++k)
+        ext += 0.5 * Q[k] * st.vxi[k] * st.vxi[k] + (k == 0 ? nf : 1.0) * kT * st.xi[k] +
+               0.5 * Qb[k] * st.veta[k] * st.veta[k] + kT * st.eta[k];
+      const double U = th[0] + th[1], ke = 0.5 * k2;
+      double* row = a.row + (size_t)rep * kNptRow;
+      row[0] = V; row[1] = (k2 + W) / (3.0 * V) / kBar; row[2] = k2 / (nf * kBoltz); row[3] = U;
+      row[4] = ke; row[5] = pext * V; row[6] = ext; row[7] = ke + U + pext * V + ext;
+    }
+  }
+  float ka = 1.f, kb = 0.f, tx = 0.f, hs = 0.f;
+  Geo G{};
+  if (a.mode & NPT_BEGIN) {
+    double kb2 = Wb * st.ve * st.ve;
+    st.ve *= chain_half(h, kb2, 1.0, kT, Qb, st.eta, st.veta, M);
+    vs *= chain_half(h, k2, nf, kT, Q, st.xi, st.vxi, M);
+    const double V = st.L[0] * st.L[1] * st.L[2];
+    st.ve += h * (alpha * k2 + W - 3.0 * pext * V) / Wb;
+    const double c = alpha * st.ve;
+    ka = (float)exp(-c * h);
+    kb = (float)(h * a.c_m * exp(-0.5 * c * h) * sinhc_d(0.5 * c * h));
+    const double gr = exp(st.ve * a.dt);
+    tx = (float)(a.dt * exp(0.5 * st.ve * a.dt) * sinhc_d(0.5 * st.ve * a.dt));
+    for (int k = 0; k < 3; ++k) st.L[k] *= gr;
+    hs = (float)(0.5 * (st.L[0] / d.lref[rep] * a.rl - a.rc) - 1e-4);
+    G = Geo{(float)(st.L[0] / kTwo32), (float)(st.L[1] / kTwo32), (float)(st.L[2] / kTwo32),
+            (float)(kTwo32 / st.L[0]), (float)(kTwo32 / st.L[1]), (float)(kTwo32 / st.L[2]),
+            R.nc[0], R.nc[1], R.nc[2], R.cell_off};
+  }
+  if (i < R.iend) {
+    float4 v = d.v[i];
+    const float fs = (float)vs;
+    v.x *= fs; v.y *= fs; v.z *= fs;
+    if (a.mode & NPT_BEGIN) {
+      const float4 F = d.f[i];
+      v.x = ka * v.x + kb * F.x; v.y = ka * v.y + kb * F.y; v.z = ka * v.z + kb * F.z;
+      drift_bin(d, G, rep, i, d.u[a.par][i], v, d.uref[i], tx, hs, a.par ^ 1);
+    }
+    d.v[i] = v;
+  }
+  if (lead) {
+    a.out[rep] = st;
+    if (a.mode & NPT_BEGIN) {
+      a.kick[rep] = make_float2(ka, kb);
+      RepInfo& Rw = a.reps[rep];
+      for (int k = 0; k < 3; ++k) {
+        Rw.L[k] = st.L[k];
+        Rw.scale[k] = (float)(st.L[k] / kTwo32);
+        Rw.inv_scale[k] = (float)(kTwo32 / st.L[k]);
+        if (st.L[k] / R.nc[k] < a.rl) atomicOr(&d.flags[F_BOX], 1);
+      }
+    }
+  }
 }
 
 // ----------------------------------------------------------------- persistent
@@ -867,6 +998,7 @@ hipError_t forces_lpa(const Dev& d, const Phys& p, int mode, int vir, int par, d
     case MODE_NVE: return forces_mode<LPA, MODE_NVE>(d, p, vir, par, ring_row, s, tm);
     case MODE_NVE_LAST: return forces_mode<LPA, MODE_NVE_LAST>(d, p, vir, par, ring_row, s, tm);
     case MODE_KICK: return forces_mode<LPA, MODE_KICK>(d, p, vir, par, ring_row, s, tm);
+    case MODE_NPT: return forces_mode<LPA, MODE_NPT>(d, p, 1, par, ring_row, s, tm);
   }
   return hipErrorInvalidValue;
 }
@@ -983,6 +1115,11 @@ hipError_t launch_fill_i32(int* p, int value, long long n, hipStream_t s) {
 hipError_t launch_fill_f32(float* p, float value, long long n, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_fill_f32, dim3(nblk(n, kBlock)), dim3(kBlock), 0, s, p, value, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_npt_kick(const Dev& d, const Phys& p, const NptArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_npt_kick, dim3(nblk(d.npad, kBlock)), dim3(kBlock), 0, s, d, p, a);
   return hipGetLastError();
 }
 

@@ -1,0 +1,207 @@
+// Isothermal-isobaric dynamics: host side of the Nose-Hoover thermostat and
+// barostat of Sec. II.B (relaxation times tau_T, tau_P; the paper runs at
+// p = 0), read as the isotropic Martyna-Tobias-Klein equations with
+// Nose-Hoover chains.  The kernels are k_npt_kick (chains, barostat, first
+// kick, scaled drift, binning), the moments kernel and the force kernel in
+// its isobaric mode (second kick, kinetic and virial sums), then the
+// per-replica reduction.  Every replica has its own box, temperature and
+// pressure; boxes change every step, positions stay box fractions.
+#include "sw_ctx.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+using namespace swk;
+using namespace swh;
+
+namespace {
+
+constexpr double kGridMargin = 0.02;   // cell edges kept this much above cutoff + skin
+
+NptState fresh_state(const sw_ctx* c, int r) {
+  NptState s{};
+  for (int k = 0; k < 3; ++k) s.L[k] = c->box[3 * r + k];
+  return s;
+}
+
+int ensure_npt(sw_ctx* c) {
+  hipError_t e;
+  if (!c->d_npt &&
+      (e = dalloc_raw(c, (void**)&c->d_npt, sizeof(NptState) * 2 * c->R, c->allocs)) != hipSuccess)
+    return e == hipErrorOutOfMemory ? SW_ENOMEM : fail_hip(c, e);
+  if (!c->d_pext && (e = dalloc_raw(c, (void**)&c->d_pext, sizeof(double) * c->R, c->allocs)) != hipSuccess)
+    return e == hipErrorOutOfMemory ? SW_ENOMEM : fail_hip(c, e);
+  if (!c->npt_ready) {
+    c->npt.resize(c->R);
+    for (int r = 0; r < c->R; ++r) c->npt[r] = fresh_state(c, r);
+    c->npt_ready = true;
+  }
+  return SW_OK;
+}
+
+// Box edges of the host view from the extended state (scales follow).
+void set_boxes(sw_ctx* c, const std::vector<NptState>& st) {
+  for (int r = 0; r < c->R; ++r)
+    for (int k = 0; k < 3; ++k) {
+      const double L = st[r].L[k];
+      c->box[3 * r + k] = L;
+      c->reps[r].L[k] = L;
+      c->reps[r].scale[k] = (float)(L / kTwo32);
+      c->reps[r].inv_scale[k] = (float)(kTwo32 / L);
+    }
+}
+
+bool grid_fits(const sw_ctx* c, double margin) {
+  const double rl = c->cutoff + c->skin;
+  for (int r = 0; r < c->R; ++r)
+    for (int k = 0; k < 3; ++k)
+      if (c->box[3 * r + k] / c->reps[r].nc[k] < rl * (1.0 + margin)) return false;
+  return true;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sw_npt(sw_ctx* ctx, float* x, float* v, float* f, const sw_params* params, double mass, double dt, int nsteps,
+           const double* h_T0, const double* h_p_bar, double tau_T_fs, double tau_P_fs, int chain, int reset,
+           double* rows, int every, void* stream) {
+  if (!ctx || !x || !v || !h_T0 || !h_p_bar || nsteps < 0) return SW_EINVAL;
+  if (!(tau_T_fs > 0.0) || !(tau_P_fs > 0.0) || chain < 1 || chain > kNptChain) return SW_EINVAL;
+  if (rows && every <= 0) return SW_EINVAL;
+  for (int r = 0; r < ctx->R; ++r)
+    if (!(h_T0[r] > 0.0) || !std::isfinite(h_T0[r]) || !std::isfinite(h_p_bar[r])) return SW_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  Phys ph{};
+  int st = make_phys(ctx, params, mass, dt, &ph);
+  if (st != SW_OK) return st;
+  if ((st = ensure_npt(ctx)) != SW_OK) return st;
+  if (reset)
+    for (int r = 0; r < ctx->R; ++r) ctx->npt[r] = fresh_state(ctx, r);
+  const std::vector<NptState> start = ctx->npt;
+  std::vector<double> pext(ctx->R);
+  for (int r = 0; r < ctx->R; ++r) pext[r] = h_p_bar[r] * kBar;
+  const std::vector<float2> unit(ctx->R, make_float2(1.f, 0.f));
+  const int lpa = lpa_for(ctx);
+  const double rl = ctx->cutoff + ctx->skin;
+  double margin = kGridMargin;
+  set_boxes(ctx, start);
+  if (!grid_fits(ctx, 0.5 * margin) && (st = regrid(ctx, margin)) != SW_OK) return st;
+  int failure = SW_ENBR_OVERFLOW;
+  for (int attempt = 0; attempt < 8; ++attempt) {
+    hipError_t e;
+    set_boxes(ctx, start);
+    if ((e = hipMemcpyAsync(ctx->d_reps, ctx->reps.data(), sizeof(RepInfo) * ctx->R, hipMemcpyHostToDevice, s)) !=
+            hipSuccess ||
+        (e = hipMemcpyAsync(ctx->d_npt, start.data(), sizeof(NptState) * ctx->R, hipMemcpyHostToDevice, s)) !=
+            hipSuccess ||
+        (e = hipMemcpyAsync(ctx->d_pext, pext.data(), sizeof(double) * ctx->R, hipMemcpyHostToDevice, s)) !=
+            hipSuccess ||
+        (e = hipMemcpyAsync(ctx->d_T0, h_T0, sizeof(double) * ctx->R, hipMemcpyHostToDevice, s)) != hipSuccess ||
+        (e = hipMemcpyAsync(ctx->d_kick, unit.data(), sizeof(float2) * ctx->R, hipMemcpyHostToDevice, s)) !=
+            hipSuccess)
+      return fail_hip(ctx, e);
+    if ((e = reset_flags(ctx, s)) != hipSuccess) return fail_hip(ctx, e);
+    if ((e = sort_in(ctx, x, v, s)) != hipSuccess) return fail_hip(ctx, e);
+    // forces, virial and kinetic sums at the initial state (kick = identity)
+    if ((e = launch_moments(ctx->d, ph, lpa, 0, 1, 0, s)) != hipSuccess) return fail_hip(ctx, e);
+    if ((e = launch_forces(ctx->d, ph, lpa, MODE_NPT, 1, 0, nullptr, s)) != hipSuccess) return fail_hip(ctx, e);
+    NptArgs a{};
+    a.reps = ctx->d_reps;
+    a.kick = ctx->d_kick;
+    a.pext = ctx->d_pext;
+    a.tauT = tau_T_fs;
+    a.tauP = tau_P_fs;
+    a.rl = rl;
+    a.rc = ctx->cutoff;
+    a.dt = dt;
+    a.c_m = kAcc / mass;
+    a.chain = chain;
+    const size_t rowsz = (size_t)ctx->R * kNptRow;
+    auto row_of = [&](int step) -> double* {   // record of 1-based step, or null
+      return rows && step > 0 && step % every == 0 ? rows + (size_t)(step / every - 1) * rowsz : nullptr;
+    };
+    for (int t = 1; t <= nsteps; ++t) {
+      a.in = ctx->d_npt + (size_t)((t - 1) & 1) * ctx->R;
+      a.out = ctx->d_npt + (size_t)(t & 1) * ctx->R;
+      a.mode = t == 1 ? NPT_BEGIN : NPT_STEP;
+      a.par = (t - 1) & 1;
+      a.row = row_of(t - 1);
+      if ((e = launch_npt_kick(ctx->d, ph, a, s)) != hipSuccess) return fail_hip(ctx, e);
+      const int rec = row_of(t) != nullptr;
+      if ((e = launch_moments(ctx->d, ph, lpa, t & 1, 0, rec, s)) != hipSuccess) return fail_hip(ctx, e);
+      if ((e = launch_forces(ctx->d, ph, lpa, MODE_NPT, 1, t & 1, nullptr, s)) != hipSuccess)
+        return fail_hip(ctx, e);
+    }
+    if (nsteps > 0) {   // close the last step
+      a.in = ctx->d_npt + (size_t)(nsteps & 1) * ctx->R;
+      a.out = ctx->d_npt + (size_t)((nsteps + 1) & 1) * ctx->R;
+      a.mode = NPT_END;
+      a.par = nsteps & 1;
+      a.row = row_of(nsteps);
+      if ((e = launch_npt_kick(ctx->d, ph, a, s)) != hipSuccess) return fail_hip(ctx, e);
+    }
+    Flags fl;
+    if ((e = read_flags(ctx, s, &fl)) != hipSuccess) return fail_hip(ctx, e);
+    if (fl.nbr_over || fl.cell_over) {
+      if ((st = grow(ctx, fl)) != SW_OK) return st;
+      failure = SW_ENBR_OVERFLOW;
+      continue;
+    }
+    std::vector<NptState> end(ctx->R);
+    if ((e = hipMemcpy(end.data(), ctx->d_npt + (size_t)((nsteps + (nsteps > 0 ? 1 : 0)) & 1) * ctx->R,
+                       sizeof(NptState) * ctx->R, hipMemcpyDeviceToHost)) != hipSuccess)
+      return fail_hip(ctx, e);
+    if (fl.box) {   // a box shrank below its cell grid: larger margin, redo the call
+      set_boxes(ctx, start);
+      margin *= 2.0;
+      if ((st = regrid(ctx, margin)) != SW_OK) return st;
+      failure = SW_EBOX_TOO_SMALL;
+      continue;
+    }
+    if ((e = launch_scatter_out(ctx->d, nsteps & 1, (float4*)x, (float4*)v, (float4*)f, s)) != hipSuccess)
+      return fail_hip(ctx, e);
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) return fail_hip(ctx, e);
+    ctx->npt = end;
+    set_boxes(ctx, end);
+    if ((e = hipMemcpy(ctx->d_reps, ctx->reps.data(), sizeof(RepInfo) * ctx->R, hipMemcpyHostToDevice)) !=
+        hipSuccess)
+      return fail_hip(ctx, e);
+    ctx->steps += nsteps;
+    return fl.overlap ? SW_EOVERLAP : SW_OK;
+  }
+  set_boxes(ctx, start);
+  return failure;
+}
+
+int sw_get_box(const sw_ctx* ctx, double* h_box) {
+  if (!ctx || !h_box) return SW_EINVAL;
+  std::memcpy(h_box, ctx->box.data(), sizeof(double) * 3 * ctx->R);
+  return SW_OK;
+}
+
+int sw_npt_state(sw_ctx* ctx, double* h_state, int set) {
+  if (!ctx || !h_state) return SW_EINVAL;
+  int st = ensure_npt(ctx);
+  if (st != SW_OK) return st;
+  for (int r = 0; r < ctx->R; ++r) {
+    double* o = h_state + (size_t)r * SW_NPT_STATE;
+    NptState& n = ctx->npt[r];
+    if (set) {
+      n.ve = o[0];
+      for (int k = 0; k < kNptChain; ++k) {
+        n.xi[k] = o[1 + k]; n.vxi[k] = o[5 + k]; n.eta[k] = o[9 + k]; n.veta[k] = o[13 + k];
+      }
+    } else {
+      o[0] = n.ve;
+      for (int k = 0; k < kNptChain; ++k) {
+        o[1 + k] = n.xi[k]; o[5 + k] = n.vxi[k]; o[9 + k] = n.eta[k]; o[13 + k] = n.veta[k];
+      }
+    }
+  }
+  return SW_OK;
+}
+
+}  // extern "C"

@@ -244,16 +244,12 @@ namespace {
 
 hipError_t obs_alloc(sw_ctx* c) {
   hipError_t e;
-  if (!c->obs_edges) {
-    if ((e = hipMalloc((void**)&c->obs_edges, sizeof(double) * (kObsMaxBins + 1))) != hipSuccess) return e;
-    c->allocs.push_back(c->obs_edges);
-    c->bytes += sizeof(double) * (kObsMaxBins + 1);
-  }
-  if (!c->obs_flags) {
-    if ((e = hipMalloc((void**)&c->obs_flags, sizeof(unsigned long long) * 2)) != hipSuccess) return e;
-    c->allocs.push_back(c->obs_flags);
-    c->bytes += sizeof(unsigned long long) * 2;
-  }
+  if (!c->obs_edges &&
+      (e = dalloc_raw(c, (void**)&c->obs_edges, sizeof(double) * (kObsMaxBins + 1), c->allocs)) != hipSuccess)
+    return e;
+  if (!c->obs_flags &&
+      (e = dalloc_raw(c, (void**)&c->obs_flags, sizeof(unsigned long long) * 2, c->allocs)) != hipSuccess)
+    return e;
   return hipSuccess;
 }
 
@@ -348,11 +344,8 @@ int sw_msd(sw_ctx* ctx, const float* x, int reset, double* msd, void* stream) {
   hipError_t e;
   const size_t n3 = (size_t)3 * std::max<long long>(ctx->N, 1);
   for (double** p : {&ctx->msd_last, &ctx->msd_acc}) {
-    if (!*p) {
-      if ((e = hipMalloc((void**)p, sizeof(double) * n3)) != hipSuccess) return fail_hip(ctx, e);
-      ctx->allocs.push_back(*p);
-      ctx->bytes += sizeof(double) * n3;
-    }
+    if (!*p && (e = dalloc_raw(ctx, (void**)p, sizeof(double) * n3, ctx->allocs)) != hipSuccess)
+      return fail_hip(ctx, e);
   }
   if (ctx->N > 0)
     hipLaunchKernelGGL(k_msd_update, dim3((unsigned)((ctx->N + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,

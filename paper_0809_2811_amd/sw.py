@@ -38,7 +38,11 @@ SW_Q_TIME_MOMENTS_NS, SW_Q_TIME_FORCES_NS, SW_Q_TIMED_STEPS = 8, 9, 10
 # symbols declared in include/sw.h
 EXPORTS = ("sw_params_mw", "sw_create", "sw_destroy", "sw_build_neighbors", "sw_get_neighbors",
            "sw_forces", "sw_step", "sw_grad", "sw_adjoint", "sw_set_tuning", "sw_get_tuning",
-           "sw_query", "sw_status_string", "sw_last_hip_error", "sw_rdf", "sw_adf", "sw_msd")
+           "sw_query", "sw_status_string", "sw_last_hip_error", "sw_rdf", "sw_adf", "sw_msd",
+           "sw_npt", "sw_get_box", "sw_npt_state")
+SW_NPT_WIDTH = 8
+SW_Q_MIN_CELL_EDGE = 11
+SW_NPT_STATE = 17
 
 
 class sw_params(ctypes.Structure):
@@ -91,6 +95,10 @@ def lib():
         L.sw_rdf.argtypes = [vp, fp, ip, P(ctypes.c_double), vp, vp]
         L.sw_adf.argtypes = [vp, fp, ip, dp, ip, P(ctypes.c_double), vp, P(ctypes.c_longlong), vp]
         L.sw_msd.argtypes = [vp, fp, ip, vp, vp]
+        L.sw_npt.argtypes = [vp, fp, fp, fp, P(sw_params), dp, dp, ip, P(ctypes.c_double), P(ctypes.c_double),
+                             dp, dp, ip, ip, vp, ip, vp]
+        L.sw_get_box.argtypes = [vp, P(ctypes.c_double)]
+        L.sw_npt_state.argtypes = [vp, P(ctypes.c_double), ip]
         _lib = L
     return _lib
 
@@ -264,6 +272,42 @@ def sw_msd(ctx: int, x, reset: bool, msd, R: int = 1):
                         _stream()), "sw_msd")
 
 
+def sw_npt(ctx: int, x, v, f, params: sw_params, mass: float, dt: float, nsteps: int, T0, p_bar,
+           tau_T: float, tau_P: float, chain: int, reset: bool, rows, every: int, R: int = 1):
+    import numpy as np
+    n = x.shape[0]
+    t0 = np.ascontiguousarray(np.broadcast_to(np.asarray(T0, dtype=np.float64), (R,)))
+    pb = np.ascontiguousarray(np.broadcast_to(np.asarray(p_bar, dtype=np.float64), (R,)))
+    dptr = lambda a: a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))  # noqa: E731
+    nrec = nsteps // every if every > 0 else 0
+    _check(lib().sw_npt(ctypes.c_void_p(ctx), _atoms(x, n, "x"), _atoms(v, n, "v"),
+                        None if f is None else _atoms(f, n, "f"), ctypes.byref(params), float(mass), float(dt),
+                        int(nsteps), dptr(t0), dptr(pb), float(tau_T), float(tau_P), int(chain), 1 if reset else 0,
+                        None if rows is None else _doubles(rows, (nrec, R, SW_NPT_WIDTH), "rows"), int(every),
+                        _stream()), "sw_npt")
+
+
+def sw_get_box(ctx: int, R: int = 1):
+    import numpy as np
+    b = np.zeros((R, 3), dtype=np.float64)
+    _check(lib().sw_get_box(ctypes.c_void_p(ctx), b.ctypes.data_as(ctypes.POINTER(ctypes.c_double))), "sw_get_box")
+    return b
+
+
+def sw_npt_state(ctx: int, R: int = 1, state=None):
+    """Read (state None) or replace the extended variables, [R][SW_NPT_STATE]."""
+    import numpy as np
+    if state is None:
+        out = np.zeros((R, SW_NPT_STATE), dtype=np.float64)
+        _check(lib().sw_npt_state(ctypes.c_void_p(ctx), out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), 0),
+               "sw_npt_state")
+        return out
+    st = np.ascontiguousarray(np.asarray(state, dtype=np.float64).reshape(R, SW_NPT_STATE))
+    _check(lib().sw_npt_state(ctypes.c_void_p(ctx), st.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), 1),
+           "sw_npt_state")
+    return st
+
+
 def sw_set_tuning(ctx: int, lanes_per_atom=8, graph_steps=0, persistent=0, rebuild_every=0, timing=0):
     t = sw_tuning(int(lanes_per_atom), int(graph_steps), int(persistent), int(rebuild_every), int(timing))
     _check(lib().sw_set_tuning(ctypes.c_void_p(ctx), ctypes.byref(t)), "sw_set_tuning")
@@ -371,6 +415,31 @@ class Context:
                    xbar0, vbar0, thbar, xS, vS, R=self.R)
         return dict(loss=loss, xbar0=xbar0, vbar0=vbar0, thbar=thbar, xS=xS, vS=vS)
 
+    def npt(self, x, v, nsteps: int, T0, p_bar=0.0, tau_T: float = 1000.0, tau_P: float = 2500.0, chain: int = 3,
+            reset: bool = False, every: int = 0, dt: float = 10.0, mass: float = 18.015,
+            params: Optional[sw_params] = None, f=None):
+        """Isothermal-isobaric steps (see sw_npt in include/sw.h); returns the
+        forces and, if every > 0, the records [nsteps // every][R][8]
+        (V, P_int bar, T, U, KE, pV, extended energy, H').  The box follows
+        (`box`)."""
+        torch = _torch()
+        params = params_mw() if params is None else params
+        f = torch.empty_like(x) if f is None else f
+        rows = None
+        if every > 0:
+            rows = torch.zeros((nsteps // every, self.R, SW_NPT_WIDTH), dtype=torch.float64, device=x.device)
+        sw_npt(self.handle, x, v, f, params, mass, dt, nsteps, T0, p_bar, tau_T, tau_P, chain, reset, rows, every,
+               R=self.R)
+        return f, rows
+
+    @property
+    def box(self):
+        """Current box edges [R][3] (A); isobaric runs change them."""
+        return sw_get_box(self.handle, R=self.R)
+
+    def npt_state(self, state=None):
+        return sw_npt_state(self.handle, R=self.R, state=state)
+
     def rdf(self, x, r_edges):
         """Ordered-pair counts per distance bin (edges in A, ascending), per
         replica: int64 tensor [R][len(r_edges) - 1] (see sw_rdf)."""
@@ -404,9 +473,7 @@ class Context:
     def max_search_radius(self) -> float:
         """Smallest binning-cell edge: the largest r_max / r_search the
         observables accept."""
-        import math
-        rl = self.cutoff + self.skin
-        return min(L / min(math.floor(L / rl), 1024) for box in self.boxes for L in box)
+        return sw_query(self.handle, SW_Q_MIN_CELL_EDGE) * 1e-6
 
     def query(self, what: int) -> int:
         return sw_query(self.handle, what)

@@ -1,0 +1,110 @@
+"""GPU isothermal-isobaric dynamics (sw_npt) against the FP64 NPT oracle over
+a short horizon, replica independence, conservation of the extended energy,
+the 298 K density at p = 0 (Table 1 of the paper: 0.997 g/cm^3), and a cell
+regrid when a compressed box outgrows its grid."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_0809_2811_amd import synth
+from tests.gpu_util import RC, f32, from_dev, liquid, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def ctx_for(offsets, boxes, skin=1.0, lpa=8):
+    from paper_0809_2811_amd import sw
+    return sw.Context(offsets, boxes, cutoff=RC, skin=skin, nbr_capacity=64, tuning=dict(lanes_per_atom=lpa))
+
+
+def min_image(d, L):
+    return d - L * np.round(d / L)
+
+
+@pytest.mark.parametrize("p_bar", [0.0, 1000.0])
+def test_npt_matches_oracle_short(p_bar):
+    x, v, L = liquid(1, sigma=0.0)
+    x, v = f32(x), f32(v)
+    ctx = ctx_for([0, len(x)], [L])
+    xd, vd = to_dev(x), to_dev(v)
+    _, rows = ctx.npt(xd, vd, 10, T0=298.0, p_bar=p_bar, tau_T=200.0, tau_P=500.0, chain=3, reset=True, every=1)
+    o = oracle.npt(x, v, L, 10, T0=298.0, p_bar=p_bar, tau_T=200.0, tau_P=500.0, chain=3)
+    box = ctx.box[0]
+    assert np.allclose(box, o["box"], rtol=2e-6, atol=0), (box, o["box"])
+    assert np.abs(min_image(from_dev(xd) - o["x"], o["box"])).max() < 1e-4
+    assert np.abs(from_dev(vd) - o["v"]).max() < 1e-4 * np.abs(o["v"]).max()
+    st = ctx.npt_state()[0]
+    assert abs(st[0] - o["state"][0]) < 1e-3 * np.abs(o["state"][0]) + 1e-12
+    assert np.allclose(st[5:8], o["state"][5:8], rtol=1e-3, atol=1e-9)
+    r = rows.cpu().numpy()[:, 0, :]
+    for k, tol in ((0, 2e-6), (2, 1e-4), (3, 2e-5), (4, 1e-4), (7, 2e-5)):
+        assert np.allclose(r[:, k], o["rows"][:, k], rtol=tol, atol=0), (k, r[:, k], o["rows"][:, k])
+    assert np.abs(r[:, 1] - o["rows"][:, 1]).max() < 2.0      # bar
+
+
+def test_npt_replicas_are_independent():
+    tab = synth.replica_table(n_replicas=3)
+    off, boxes = tab["offsets"], tab["boxes"]
+    x, v = f32(tab["x"]), f32(tab["v"])
+    T0 = [250.0, 280.0, 310.0]
+    P = [0.0, 500.0, -200.0]
+    ctx = ctx_for(off, boxes)
+    xd, vd = to_dev(x), to_dev(v)
+    ctx.npt(xd, vd, 30, T0=T0, p_bar=P, tau_T=500.0, tau_P=1000.0, reset=True)
+    for r in range(3):
+        a, b = off[r], off[r + 1]
+        c1 = ctx_for([0, b - a], [boxes[r]])
+        x1, v1 = to_dev(x[a:b]), to_dev(v[a:b])
+        c1.npt(x1, v1, 30, T0=T0[r], p_bar=P[r], tau_T=500.0, tau_P=1000.0, reset=True)
+        assert np.array_equal(from_dev(xd)[a:b], from_dev(x1)), r
+        assert np.array_equal(from_dev(vd)[a:b], from_dev(v1)), r
+        assert np.array_equal(ctx.box[r], c1.box[0]), r
+
+
+def test_npt_extended_energy_conserved():
+    from paper_0809_2811_amd import sw
+    x, v, L = liquid(2)
+    x, v = f32(x), f32(v)
+    ctx = ctx_for([0, len(x)], [L])
+    xd, vd = to_dev(x), to_dev(v)
+    _, rows = ctx.npt(xd, vd, 3000, T0=298.0, p_bar=0.0, reset=True, every=10)
+    H = rows.cpu().numpy()[:, 0, 7]
+    c2 = ctx_for([0, len(x)], [L])
+    _, th = c2.step(to_dev(x), to_dev(v), 3000, thermo_every=10)
+    th = th.cpu().numpy()[:, 0, :]
+    E = th[:, 0] + th[:, 1] + th[:, 2]
+    w = len(H) // 5
+    assert abs(H[-w:].mean() - H[:w].mean()) < 2e-5 * abs(H[0]) + 2.0 * abs(E[-w:].mean() - E[:w].mean())
+    assert np.ptp(H) < 3.0 * np.ptp(E)
+
+
+def test_npt_density_298K():
+    """p = 0, 298 K, 4096 atoms: 100 ps to relax, 200 ps averaged."""
+    x, v, L = liquid(2)
+    ctx = ctx_for([0, len(x)], [L])
+    xd, vd = to_dev(f32(x)), to_dev(f32(v))
+    ctx.npt(xd, vd, 10000, T0=298.0, p_bar=0.0, reset=True)
+    _, rows = ctx.npt(xd, vd, 20000, T0=298.0, p_bar=0.0, every=100)
+    r = rows.cpu().numpy()[:, 0, :]
+    rho = len(x) * oracle.M_WATER / 6.02214076e23 / (r[:, 0] * 1e-24)
+    assert abs(rho.mean() - 0.997) < 0.008, rho.mean()
+    assert abs(r[:, 2].mean() - 298.0) < 3.0
+    assert abs(r[:, 1].mean()) < 150.0          # bar
+
+
+def test_npt_regrids_a_compressed_box():
+    """A dilute start (0.92 g/cm^3) under 5 kbar compresses by several
+    percent; the cell grid is rebuilt when a cell edge would drop below
+    cutoff + skin, and the call completes."""
+    from paper_0809_2811_amd import sw
+    cfg = synth.lattice_at_density(8, 0.92, sigma=0.05, temperature=300.0, seed=21)
+    x, v, L = f32(cfg["x"]), f32(cfg["v"]), cfg["box"]
+    ctx = ctx_for([0, len(x)], [L])
+    edge0 = ctx.max_search_radius()
+    xd, vd = to_dev(x), to_dev(v)
+    ctx.npt(xd, vd, 3000, T0=300.0, p_bar=5000.0, tau_P=500.0, reset=True)
+    Lend = ctx.box[0, 0]
+    assert Lend < 0.97 * L[0]
+    assert ctx.max_search_radius() >= RC + 1.0
+    assert ctx.max_search_radius() < edge0
+    assert np.all(np.isfinite(from_dev(xd))) and np.all(from_dev(xd) >= 0) and np.all(from_dev(xd) <= Lend + 1e-3)
