@@ -108,3 +108,16 @@ def test_npt_regrids_a_compressed_box():
     assert ctx.max_search_radius() >= RC + 1.0
     assert ctx.max_search_radius() < edge0
     assert np.all(np.isfinite(from_dev(xd))) and np.all(from_dev(xd) >= 0) and np.all(from_dev(xd) <= Lend + 1e-3)
+
+
+@pytest.mark.slow
+def test_density_maximum():
+    """The paper's density anomaly (Sec. III, Table 1: maximum of 1.003 g/cm^3
+    at 250 K, p = 0): 9 replicas of 4096 atoms from 220 to 320 K on the
+    batched isobaric engine, 0.5 ns to relax and 1.5 ns averaged each."""
+    from paper_0809_2811_amd import scan
+    res = scan.density_scan([220, 230, 240, 250, 260, 270, 280, 300, 320], equil_steps=50000, sample_steps=150000)
+    assert res["interior"]
+    assert 235.0 < res["tmd"] < 265.0, res
+    assert abs(res["rho_max"] - 1.003) < 0.004, res
+    assert res["rho"][-1] < res["rho_max"] - 0.005 and res["rho"][0] < res["rho_max"] - 0.001
