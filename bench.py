@@ -209,8 +209,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=500)
     ap.add_argument("--skin", type=float, default=0.0, help="Verlet skin in A (0 = tuned)")
     ap.add_argument("--lpa", type=int, default=0, help="lanes per atom (0 = tuned default)")
-    ap.add_argument("--forms", default="large,batched,adjoint,observables",
-                    help="comma list of large,batched,adjoint,observables or none")
+    ap.add_argument("--forms", default="large,batched,adjoint,observables,npt",
+                    help="comma list of large,batched,adjoint,observables,npt or none")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="first run a plain FP32 copy-like kernel (out = -in) over this many MiB, three times: "
@@ -266,6 +266,8 @@ def main():
         line["forms"]["adjoint"] = bench_adjoint(line["ms_per_step"])
     if "observables" in forms:
         line["forms"]["observables"] = bench_observables(ctx, x)
+    if "npt" in forms:
+        line["forms"]["npt"] = bench_npt(line["ms_per_step"])
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline()
     print(json.dumps(line), flush=True)
@@ -398,6 +400,33 @@ def bench_observables(ctx, x, reps=20):
             fn()
         sync()
         out[f"{name}_ms"] = (time.perf_counter() - t0) * 1e3 / reps
+    return out
+
+
+def bench_npt(plain_ms_per_step, steps=5000, warm=1000):
+    """Isothermal-isobaric steps (Nose-Hoover chains of 3, tau_T 1 ps,
+    tau_P 2.5 ps, p = 0): the 4096-atom liquid alone, and nine replicas of it
+    at 220-320 K in one context (the density-maximum scan)."""
+    import torch
+    from paper_0809_2811_amd import scan, sw, synth
+    x0, v0, L0 = scan.start_liquid(2)
+    n = len(x0)
+    out = {"workload": f"npt: {n}-atom liquid at 298 K and p = 0; and 9 replicas of it at 220-320 K",
+           "unit": "atom-steps/s"}
+    for name, temps in (("single", [298.0]), ("batched", [220, 230, 240, 250, 260, 270, 280, 300, 320])):
+        R = len(temps)
+        x = torch.from_numpy(synth.to_float4(np.concatenate([x0] * R))).cuda()
+        v = torch.from_numpy(synth.to_float4(np.concatenate([v0] * R))).cuda()
+        ctx = sw.Context(np.arange(R + 1) * n, [L0] * R, cutoff=RC, skin=1.0, nbr_capacity=64)
+        ctx.npt(x, v, warm, T0=temps, reset=True)
+        sync()
+        t0 = time.perf_counter()
+        ctx.npt(x, v, steps, T0=temps)
+        sync()
+        dt = time.perf_counter() - t0
+        out[name] = {"value": R * n * steps / dt, "ms_per_step": dt * 1e3 / steps, "n_atoms": R * n}
+    out["value"] = out["batched"]["value"]
+    out["single_ratio_to_nve_step"] = out["single"]["ms_per_step"] / plain_ms_per_step
     return out
 
 
