@@ -256,7 +256,7 @@ int sw_npt_state(sw_ctx* ctx, double* h_state, int set);
 
 /* Execution options (chosen by the autotuner). */
 typedef struct sw_tuning {
-  int lanes_per_atom;   /* 4, 8, 16 or 32 lanes of a wavefront share one atom  */
+  int lanes_per_atom;   /* 4, 8, 16, 32 or 64 lanes of a wavefront per atom   */
   int graph_steps;      /* steps per captured hipGraph (0 = plain launches)    */
   int persistent;       /* 0: one launch per phase; 1: sw_step's steps run in one
                            cooperative persistent launch at full occupancy;

@@ -471,7 +471,8 @@ void sw_destroy(sw_ctx* ctx) {
 
 int sw_set_tuning(sw_ctx* ctx, const sw_tuning* t) {
   if (!ctx || !t) return SW_EINVAL;
-  if (t->lanes_per_atom != 4 && t->lanes_per_atom != 8 && t->lanes_per_atom != 16 && t->lanes_per_atom != 32)
+  if (t->lanes_per_atom != 4 && t->lanes_per_atom != 8 && t->lanes_per_atom != 16 && t->lanes_per_atom != 32 &&
+      t->lanes_per_atom != 64)
     return SW_EUNSUPPORTED;
   if (t->graph_steps < 0 || t->rebuild_every < 0 || t->timing < 0 || t->persistent < 0) return SW_EINVAL;
   ctx->tune = *t;

@@ -22,7 +22,7 @@ namespace swk {
 
 constexpr int kBlock = 256;        // threads per block of every atom kernel
 constexpr int kTile = 64;          // replicas are padded to multiples of this
-constexpr int kMaxLPA = 32;        // most lanes per atom of any kernel variant
+constexpr int kMaxLPA = 64;        // most lanes per atom of any kernel variant
 constexpr int kMinAPB = kBlock / kMaxLPA;   // fewest atoms per block: sizes per-block buffers
 constexpr int kNQ = 12;            // thermo quantities per replica
 // Row rebuild staging in LDS (moments kernel), per block: candidate and

@@ -262,12 +262,12 @@ __device__ void moments_tile(const Dev& d, const Phys& p, int par, int force_reb
     int cl[CPL], mc[CPL];
 #pragma unroll
     for (int q = 0; q < CPL; ++q) {
-      const int c = lane * CPL + q;
+      const int c = min(lane * CPL + q, 26);     // lanes past the 27 cells read cell 26, masked below
       int xx = cx + c / 9 - 1, yy = cy + (c / 3) % 3 - 1, zz = cz + c % 3 - 1;
       xx = xx < 0 ? xx + n0 : (xx >= n0 ? xx - n0 : xx);
       yy = yy < 0 ? yy + n1 : (yy >= n1 ? yy - n1 : yy);
       zz = zz < 0 ? zz + n2 : (zz >= n2 ? zz - n2 : zz);
-      cl[q] = G.cell_off + (xx * n1 + yy) * n2 + zz;   // a valid cell for every c < 36
+      cl[q] = G.cell_off + (xx * n1 + yy) * n2 + zz;
       mc[q] = gc[cl[q]];
     }
     // An unconditional use of every count keeps the compiler from sinking
@@ -1037,6 +1037,7 @@ hipError_t launch_persistent(const Dev& d, const Phys& p, int lpa, const PArgs& 
     case 8: return persistent_lpa<8>(d, p, a, blocks_per_cu, s, grid_out);
     case 16: return persistent_lpa<16>(d, p, a, blocks_per_cu, s, grid_out);
     case 32: return persistent_lpa<32>(d, p, a, blocks_per_cu, s, grid_out);
+    case 64: return persistent_lpa<64>(d, p, a, blocks_per_cu, s, grid_out);
   }
   return hipErrorInvalidValue;
 }
@@ -1074,6 +1075,7 @@ hipError_t launch_moments(const Dev& d, const Phys& p, int lpa, int par, int for
     case 8: return moments_lpa<8>(d, p, par, force_rebuild, energy, s, tm);
     case 16: return moments_lpa<16>(d, p, par, force_rebuild, energy, s, tm);
     case 32: return moments_lpa<32>(d, p, par, force_rebuild, energy, s, tm);
+    case 64: return moments_lpa<64>(d, p, par, force_rebuild, energy, s, tm);
   }
   return hipErrorInvalidValue;
 }
@@ -1085,6 +1087,7 @@ hipError_t launch_forces(const Dev& d, const Phys& p, int lpa, int mode, int vir
     case 8: return forces_lpa<8>(d, p, mode, vir, par, ring_row, s, tm);
     case 16: return forces_lpa<16>(d, p, mode, vir, par, ring_row, s, tm);
     case 32: return forces_lpa<32>(d, p, mode, vir, par, ring_row, s, tm);
+    case 64: return forces_lpa<64>(d, p, mode, vir, par, ring_row, s, tm);
   }
   return hipErrorInvalidValue;
 }

@@ -349,6 +349,7 @@ hipError_t launch_tan_moments(const Dev& d, const Tan& t, const Phys& p, int lpa
     case 8: return tan_launch<8>(d, t, p, w, par, nullptr, none, s, true);
     case 16: return tan_launch<16>(d, t, p, w, par, nullptr, none, s, true);
     case 32: return tan_launch<32>(d, t, p, w, par, nullptr, none, s, true);
+    case 64: return tan_launch<64>(d, t, p, w, par, nullptr, none, s, true);
   }
   return hipErrorInvalidValue;
 }
@@ -361,6 +362,7 @@ hipError_t launch_tan_forces(const Dev& d, const Tan& t, const Phys& p, int lpa,
     case 8: return tan_launch<8>(d, t, p, w, par, adj, pt, s, false);
     case 16: return tan_launch<16>(d, t, p, w, par, adj, pt, s, false);
     case 32: return tan_launch<32>(d, t, p, w, par, adj, pt, s, false);
+    case 64: return tan_launch<64>(d, t, p, w, par, adj, pt, s, false);
   }
   return hipErrorInvalidValue;
 }

@@ -93,7 +93,7 @@ def search(n_cells: int, rho: float = 1.0, skins=(0.5, 0.7, 1.0, 1.3), steps: in
     n = x0.shape[0]
     results = []
     for skin in skins:
-        for lpa in (4, 8, 16, 32):
+        for lpa in (4, 8, 16, 32, 64):
             tun = dict(DEFAULT, lanes_per_atom=lpa)
             ctx = sw.Context([0, n], [box], cutoff=RC, skin=skin, nbr_capacity=64, tuning=tun)
             dt = _timed(ctx, x0.clone(), v0.clone(), steps)
@@ -135,7 +135,7 @@ def search_replicas(steps: int = 300, skin: float = 1.0, write: bool = True):
     prep = sw.Context(off, boxes, cutoff=RC, skin=skin, nbr_capacity=64)
     prep.step(x0, v0, 500, thermostat=sw.SW_RESCALE, T0=[400.0] * len(boxes))
     results = []
-    for lpa in (4, 8, 16, 32):
+    for lpa in (4, 8, 16, 32, 64):
         for persistent, graph_steps in ((0, 0), (1, 0), (0, 50)):
             ctx = sw.Context(off, boxes, cutoff=RC, skin=skin, nbr_capacity=64,
                              tuning=dict(DEFAULT, lanes_per_atom=lpa, persistent=persistent, graph_steps=graph_steps))

@@ -27,7 +27,7 @@ def rel_err(a, b):
     return np.abs(a - b).max() / np.sqrt((b ** 2).sum(axis=-1).mean())
 
 
-@pytest.mark.parametrize("lpa", [4, 8, 16, 32])
+@pytest.mark.parametrize("lpa", [4, 8, 16, 32, 64])
 def test_hessian_vector_product(lpa):
     x, _, L = liquid(1, sigma=0.0)
     x = f32(x)

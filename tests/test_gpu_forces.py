@@ -39,21 +39,21 @@ def check(x, L, g, tol=TOL):
     return err
 
 
-@pytest.mark.parametrize("lpa", [4, 8, 16, 32])
+@pytest.mark.parametrize("lpa", [4, 8, 16, 32, 64])
 def test_ice_workload_forces(lpa):
     d = synth.config(0)
     x = f32(d["x"])
     check(x, d["box"], gpu_forces(x, d["box"], lpa=lpa))
 
 
-@pytest.mark.parametrize("lpa", [4, 8, 16, 32])
+@pytest.mark.parametrize("lpa", [4, 8, 16, 32, 64])
 def test_liquid_forces_512(lpa):
     x, _, L = liquid(1, sigma=0.0)
     x = f32(x)
     check(x, L, gpu_forces(x, L, lpa=lpa))
 
 
-@pytest.mark.parametrize("lpa", [8, 32])
+@pytest.mark.parametrize("lpa", [8, 32, 64])
 def test_liquid_forces_4096(lpa):
     x, _, L = liquid(2)
     x = f32(x)

@@ -38,7 +38,7 @@ def min_image(d, L):
     return d - L * np.round(d / L)
 
 
-@pytest.mark.parametrize("which,lpa", [("ice", 8), ("liquid", 8), ("liquid", 32), ("liquid4096", 32)])
+@pytest.mark.parametrize("which,lpa", [("ice", 8), ("liquid", 8), ("liquid", 32), ("liquid4096", 32), ("liquid4096", 64)])
 def test_ten_steps_match_oracle(which, lpa):
     """liquid4096 at 32 lanes per atom is also the regression case for the
     per-block partial sums, which must hold 8-atom blocks."""
