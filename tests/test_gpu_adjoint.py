@@ -175,3 +175,29 @@ def test_full_horizon_adjoint_consistent_across_checkpoints():
     assert np.all(np.isfinite(a["thbar"])) and np.all(np.isfinite(a["xbar0"]))
     for k in ("loss", "thbar", "xbar0", "vbar0", "xS", "vS"):
         assert np.array_equal(a[k], b[k]), k
+
+
+def test_gauss_newton_recovers_the_paper_parameters():
+    """Differentiable parameterisation (the fit of Sec. II.D as a gradient
+    problem): targets are the mean energy and three-body energy per atom of
+    8 short liquid trajectories at the paper's (lambda, epsilon); starting
+    from silicon's lambda = 21 and epsilon = 6.0, Gauss-Newton steps on the
+    adjoint Jacobian recover (23.15, 6.189)."""
+    import torch
+    from paper_0809_2811_amd import fit, synth, sw
+    x, v, L = liquid(1, sigma=0.0)
+    R = 8
+    xs, vs = [], []
+    for r in range(R):
+        xr, vr, _ = synth.tile(x, v, L, 1, sigma=0.02, seed=100 + r)
+        xs.append(xr); vs.append(vr)
+    ctx = sw.Context(np.arange(R + 1) * len(x), [L] * R, cutoff=RC, skin=0.8, nbr_capacity=48)
+    x0 = to_dev(f32(np.concatenate(xs)))
+    v0 = to_dev(f32(np.concatenate(vs)))
+    truth = dict(lambda_=23.15, epsilon=6.189, sigma=2.3925)
+    target, _ = fit.observables(ctx, x0, v0, truth)
+    path = fit.gauss_newton(ctx, x0, v0, target, dict(lambda_=21.0, epsilon=6.0, sigma=2.3925), iters=8)
+    th, res = path[-1]
+    assert abs(th["lambda_"] - 23.15) < 1e-3 * 23.15, path
+    assert abs(th["epsilon"] - 6.189) < 1e-3 * 6.189, path
+    assert np.abs(res).max() < 1e-6 * abs(target[0])
