@@ -258,13 +258,14 @@ class Displacement:
 # ---------------------------------------------------------------- NPT
 BAR = 1e5 * 1e-30 * 6.02214076e23 / 4184.0      # kcal/mol/A^3 per bar
 NPT_STATE = 17
-NPT_ROW = 8
+NPT_ROW = 11
 
 
 def npt(x, v, box, nsteps, T0, p_bar=0.0, tau_T=1000.0, tau_P=2500.0, chain=3, state=None, dt=10.0,
         mass=M_WATER, P=None):
-    """Nose-Hoover NPT (see ora_npt); returns the final x, v, box, extended
-    state and one row per step (V, P_int in bar, T, U, KE, pV, E_ext, H')."""
+    """Nose-Hoover NPT (see ora_npt; tau_P <= 0: fixed box, NVT); returns the
+    final x, v, box, extended state and one row per step (V, P_int in bar, T,
+    U, KE, pV, E_ext, H', P_xx, P_yy, P_zz in bar)."""
     x = _d(x).copy(); v = _d(v).copy(); L = _d(box).copy()
     st = np.zeros(NPT_STATE) if state is None else _d(state).copy()
     rows = np.zeros((max(nsteps, 1), NPT_ROW))
@@ -275,4 +276,5 @@ def npt(x, v, box, nsteps, T0, p_bar=0.0, tau_T=1000.0, tau_P=2500.0, chain=3, s
         raise ValueError(f"oracle npt: error {rc}")
     rows = rows[:nsteps].copy()
     rows[:, 1] /= BAR
+    rows[:, 8:11] /= BAR
     return dict(x=x, v=v, box=L, state=st, rows=rows)

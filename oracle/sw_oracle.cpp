@@ -548,9 +548,11 @@ int ora_adjoint(int n, const double* x0, const double* v0, const double* L, cons
 // drift: r <- r e^{v_e dt} + v dt e^{v_e dt/2} sinhc(v_e dt/2), L <- L e^{v_e dt};
 // baro: v_e += h [(1 + 3/Nf) sum m v^2 + W - 3 p V] / Wb; and a chain half step
 // of one Suzuki-Yoshida stage.  Pressure p in kcal/mol/A^3.
+// tauP <= 0 removes the barostat (fixed box, Nose-Hoover NVT, v_e = 0).
 // state: [0] v_e, [1..4] xi, [5..8] vxi, [9..12] eta, [13..16] veta (chain M <= 4).
 // rows (may be NULL): per step, after the step: V, P_int (kcal/mol/A^3), T, U, KE,
-// p V, the extended energies, H'.
+// p V, the extended energies, H', and the pressure tensor diagonal
+// P_aa = (sum m v_a^2 + W_aa) / V.
 namespace {
 double sinhc(double x) { return std::fabs(x) < 1e-4 ? 1.0 + x * x / 6.0 : std::sinh(x) / x; }
 
@@ -587,6 +589,8 @@ int ora_npt(int n, double* x, double* v, double* L, const double* P, double mass
     Q[k] = (k == 0 ? nf : 1.0) * kT * tauT * tauT;
     Qb[k] = kT * tauP * tauP;
   }
+  const bool baro = tauP > 0.0;
+  if (!baro) p_ext = 0.0;
   const double Wb = (nf + 3.0) * kT * tauP * tauP;
   double& ve = state[0];
   double *xi = state + 1, *vxi = state + 5, *eta = state + 9, *veta = state + 13;
@@ -594,7 +598,8 @@ int ora_npt(int n, double* x, double* v, double* L, const double* P, double mass
   Eval ev = eval_value(n, x, b, P);
   auto vir = [&]() { return ev.w2[0] + ev.w2[4] + ev.w2[8] + ev.w3[0] + ev.w3[4] + ev.w3[8]; };
   auto k2_of = [&]() { return 2.0 * kinetic(n, v, mass, nullptr); };
-  auto baro = [&](double k2) {
+  auto barostat = [&](double k2) {
+    if (!baro) return;
     const double V = b.L[0] * b.L[1] * b.L[2];
     ve += h * (alpha * k2 + vir() - 3.0 * p_ext * V) / Wb;
   };
@@ -606,20 +611,20 @@ int ora_npt(int n, double* x, double* v, double* L, const double* P, double mass
   auto chains = [&](double& k2, bool first) {
     double kb = Wb * ve * ve;
     if (first) {
-      ve *= chain_half(h, kb, 1.0, kT, Qb, eta, veta, M);
+      if (baro) ve *= chain_half(h, kb, 1.0, kT, Qb, eta, veta, M);
       const double s = chain_half(h, k2, nf, kT, Q, xi, vxi, M);
       for (int i = 0; i < 3 * n; ++i) v[i] *= s;
     } else {
       const double s = chain_half(h, k2, nf, kT, Q, xi, vxi, M);
       for (int i = 0; i < 3 * n; ++i) v[i] *= s;
       kb = Wb * ve * ve;
-      ve *= chain_half(h, kb, 1.0, kT, Qb, eta, veta, M);
+      if (baro) ve *= chain_half(h, kb, 1.0, kT, Qb, eta, veta, M);
     }
   };
   for (int s = 0; s < nsteps; ++s) {
     double k2 = k2_of();
     chains(k2, true);
-    baro(k2_of());
+    barostat(k2_of());
     kick();
     const double g = std::exp(ve * dt), d = dt * std::exp(0.5 * ve * dt) * sinhc(0.5 * ve * dt);
     for (int i = 0; i < 3 * n; ++i) x[i] = x[i] * g + v[i] * d;
@@ -627,19 +632,22 @@ int ora_npt(int n, double* x, double* v, double* L, const double* P, double mass
     wrap_positions(n, x, b);
     ev = eval_value(n, x, b, P);
     kick();
-    baro(k2_of());
+    barostat(k2_of());
     k2 = k2_of();
     chains(k2, false);
     if (rows) {
       const double V = b.L[0] * b.L[1] * b.L[2];
-      const double ke = 0.5 * k2_of(), U = ev.e[0] + ev.e[1];
-      double ext = 0.5 * Wb * ve * ve;
-      for (int k = 0; k < M; ++k)
-        ext += 0.5 * Q[k] * vxi[k] * vxi[k] + (k == 0 ? nf : 1.0) * kT * xi[k] + 0.5 * Qb[k] * veta[k] * veta[k] +
-               kT * eta[k];
-      double* row = rows + 8 * (size_t)s;
+      double kd[3];
+      const double ke = kinetic(n, v, mass, kd), U = ev.e[0] + ev.e[1];
+      double ext = baro ? 0.5 * Wb * ve * ve : 0.0;
+      for (int k = 0; k < M; ++k) {
+        ext += 0.5 * Q[k] * vxi[k] * vxi[k] + (k == 0 ? nf : 1.0) * kT * xi[k];
+        if (baro) ext += 0.5 * Qb[k] * veta[k] * veta[k] + kT * eta[k];
+      }
+      double* row = rows + 11 * (size_t)s;
       row[0] = V; row[1] = (2.0 * ke + vir()) / (3.0 * V); row[2] = 2.0 * ke / (nf * kBoltz); row[3] = U;
       row[4] = ke; row[5] = p_ext * V; row[6] = ext; row[7] = ke + U + p_ext * V + ext;
+      for (int c = 0; c < 3; ++c) row[8 + c] = (kd[c] + ev.w2[4 * c] + ev.w3[4 * c]) / V;
     }
   }
   for (int c = 0; c < 3; ++c) L[c] = b.L[c];

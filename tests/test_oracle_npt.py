@@ -61,3 +61,19 @@ def test_extended_energy_conserved_under_load():
     E = th[:, 0] + th[:, 1] + th[:, 2]
     assert np.abs(H - H[0]).max() < 2.0 * np.abs(E - E[0]).max()
     assert r["rows"][0, 5] > 100.0          # p V is a sizeable term
+
+
+def test_fixed_box_thermostat_and_tensor_trace():
+    """tau_P <= 0: Nose-Hoover NVT.  The box stays put, H' (now without
+    barostat terms) is conserved like the NVE energy, and the scalar
+    pressure is the mean of the tensor diagonal."""
+    x, v, L = liquid(1, sigma=0.0)
+    r = oracle.npt(x, v, L, 200, T0=280.0, tau_T=200.0, tau_P=0.0)
+    assert np.array_equal(r["box"], L)
+    assert r["state"][0] == 0.0 and np.all(r["state"][9:17] == 0.0)
+    H = r["rows"][:, 7]
+    _, _, _, th = oracle.vv(x, v, L, 200, dt=10.0)
+    E = th[:, 0] + th[:, 1] + th[:, 2]
+    assert np.abs(H - H[0]).max() < 2.0 * np.abs(E - E[0]).max()
+    assert np.allclose(r["rows"][:, 1], r["rows"][:, 8:11].mean(axis=1), rtol=1e-9, atol=1e-6)
+    assert abs(r["rows"][-50:, 2].mean() - 280.0) < 25.0       # pulled from 298 K toward 280 K
