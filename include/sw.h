@@ -237,13 +237,16 @@ int sw_msd(sw_ctx* ctx, const float* x, int reset, double* msd, void* stream);
  *  h_T0      host double[R] K;  h_p_bar host double[R] bar.
  *  chain     1..4 (the paper names no chain length; 3 is customary).
  *  reset     nonzero: extended variables start from zero (box kept).
+ *  tau_P_fs  barostat relaxation time; <= 0 turns the barostat off (fixed
+ *            box: Nose-Hoover NVT, as for the paper's slab runs).
  *  rows      device double[nsteps / every][R][SW_NPT_WIDTH] out, may be NULL:
  *            after each recorded step: V (A^3), P_int (bar), T (K), U, KE,
- *            p V, extended energy, conserved H' (kcal/mol).
+ *            p V, extended energy, conserved H' (kcal/mol), then the
+ *            pressure tensor diagonal P_xx, P_yy, P_zz (bar).
  * Cell grids are rebuilt with a margin when a box shrinks toward its
  * cutoff + skin edge; the call is then redone from its inputs.
  * Synchronises. */
-#define SW_NPT_WIDTH 8
+#define SW_NPT_WIDTH 11
 #define SW_NPT_STATE 17   /* v_e, xi[4], vxi[4], eta[4], veta[4] per replica */
 int sw_npt(sw_ctx* ctx, float* x, float* v, float* f, const sw_params* params, double mass,
            double dt, int nsteps, const double* h_T0, const double* h_p_bar, double tau_T_fs,

@@ -124,7 +124,7 @@ struct NptArgs {
   int par;               // parity of the positions this launch reads
   double* row;           // [R][kNptRow] record of the step closed here, or null
 };
-constexpr int kNptRow = 8;
+constexpr int kNptRow = 11;
 
 // Optional start/stop events recorded at a launch's dispatch.
 struct KTimer {

@@ -743,8 +743,9 @@ __global__ __launch_bounds__(kBlock) void k_npt_kick(Dev d, Phys p, NptArgs a) {
     Q[k] = (k == 0 ? nf : 1.0) * kT * a.tauT * a.tauT;
     Qb[k] = kT * a.tauP * a.tauP;
   }
+  const bool baro = a.tauP > 0.0;            // no barostat: fixed box (NVT)
   const double Wb = (nf + 3.0) * kT * a.tauP * a.tauP;
-  const double pext = a.pext[rep];
+  const double pext = baro ? a.pext[rep] : 0.0;
   const double* th = d.thermo_cur + (size_t)rep * kNQ;
   const double W = th[3] + th[4] + th[5];
   double k2 = 2.0 * th[2];
@@ -752,29 +753,35 @@ __global__ __launch_bounds__(kBlock) void k_npt_kick(Dev d, Phys p, NptArgs a) {
   const bool lead = i == R.ioff;
   if (a.mode & NPT_END) {
     const double V = st.L[0] * st.L[1] * st.L[2];
-    st.ve += h * (alpha * k2 + W - 3.0 * pext * V) / Wb;
+    if (baro) st.ve += h * (alpha * k2 + W - 3.0 * pext * V) / Wb;
     vs = chain_half(h, k2, nf, kT, Q, st.xi, st.vxi, M);
-    double kb2 = Wb * st.ve * st.ve;
-    st.ve *= chain_half(h, kb2, 1.0, kT, Qb, st.eta, st.veta, M);
+    if (baro) {
+      double kb2 = Wb * st.ve * st.ve;
+      st.ve *= chain_half(h, kb2, 1.0, kT, Qb, st.eta, st.veta, M);
+    }
     if (lead && a.row) {
-      double ext = 0.5 * Wb * st.ve * st.ve;
-      for (int k = 0; k < M; ++k)
-        ext += 0.5 * Q[k] * st.vxi[k] * st.vxi[k] + (k == 0 ? nf : 1.0) * kT * st.xi[k] +
-               0.5 * Qb[k] * st.veta[k] * st.veta[k] + kT * st.eta[k];
-      const double U = th[0] + th[1], ke = 0.5 * k2;
+      double ext = baro ? 0.5 * Wb * st.ve * st.ve : 0.0;
+      for (int k = 0; k < M; ++k) {
+        ext += 0.5 * Q[k] * st.vxi[k] * st.vxi[k] + (k == 0 ? nf : 1.0) * kT * st.xi[k];
+        if (baro) ext += 0.5 * Qb[k] * st.veta[k] * st.veta[k] + kT * st.eta[k];
+      }
+      const double U = th[0] + th[1], ke = 0.5 * k2, v2 = vs * vs;
       double* row = a.row + (size_t)rep * kNptRow;
       row[0] = V; row[1] = (k2 + W) / (3.0 * V) / kBar; row[2] = k2 / (nf * kBoltz); row[3] = U;
       row[4] = ke; row[5] = pext * V; row[6] = ext; row[7] = ke + U + pext * V + ext;
+      for (int c = 0; c < 3; ++c) row[8 + c] = (v2 * th[9 + c] + th[3 + c]) / V / kBar;   // P_aa
     }
   }
   float ka = 1.f, kb = 0.f, tx = 0.f, hs = 0.f;
   Geo G{};
   if (a.mode & NPT_BEGIN) {
-    double kb2 = Wb * st.ve * st.ve;
-    st.ve *= chain_half(h, kb2, 1.0, kT, Qb, st.eta, st.veta, M);
+    if (baro) {
+      double kb2 = Wb * st.ve * st.ve;
+      st.ve *= chain_half(h, kb2, 1.0, kT, Qb, st.eta, st.veta, M);
+    }
     vs *= chain_half(h, k2, nf, kT, Q, st.xi, st.vxi, M);
     const double V = st.L[0] * st.L[1] * st.L[2];
-    st.ve += h * (alpha * k2 + W - 3.0 * pext * V) / Wb;
+    if (baro) st.ve += h * (alpha * k2 + W - 3.0 * pext * V) / Wb;
     const double c = alpha * st.ve;
     ka = (float)exp(-c * h);
     kb = (float)(h * a.c_m * exp(-0.5 * c * h) * sinhc_d(0.5 * c * h));

@@ -69,7 +69,7 @@ int sw_npt(sw_ctx* ctx, float* x, float* v, float* f, const sw_params* params, d
            const double* h_T0, const double* h_p_bar, double tau_T_fs, double tau_P_fs, int chain, int reset,
            double* rows, int every, void* stream) {
   if (!ctx || !x || !v || !h_T0 || !h_p_bar || nsteps < 0) return SW_EINVAL;
-  if (!(tau_T_fs > 0.0) || !(tau_P_fs > 0.0) || chain < 1 || chain > kNptChain) return SW_EINVAL;
+  if (!(tau_T_fs > 0.0) || !std::isfinite(tau_P_fs) || chain < 1 || chain > kNptChain) return SW_EINVAL;
   if (rows && every <= 0) return SW_EINVAL;
   for (int r = 0; r < ctx->R; ++r)
     if (!(h_T0[r] > 0.0) || !std::isfinite(h_T0[r]) || !std::isfinite(h_p_bar[r])) return SW_EINVAL;

@@ -8,6 +8,7 @@ into the quantities the paper reports:
   n_c(R_c)  = 4 pi N/V int_0^{R_c} r^2 g(r) dr  = ordered pairs within R_c / N
   P(theta)  = 1/(N n_theta) < sum_k sum_{i<j in the n_c closest} delta(theta - theta_ikj) >
   D         = lim_{t -> inf} <|r(t) - r(0)|^2> / (6 t)   (Einstein relation)
+  gamma_lv  = L_z / 2 [<p_N> - <p_T>]   (slab with interfaces normal to z)
 """
 from __future__ import annotations
 
@@ -49,3 +50,13 @@ def diffusion_coefficient(t_fs, msd_A2, t_min_fs: float = 0.0) -> float:
     sel = t >= t_min_fs
     slope = np.polyfit(t[sel], m[sel], 1)[0]
     return slope / 6.0 * 0.1
+
+
+def surface_tension(p_xx, p_yy, p_zz, lz: float) -> float:
+    """Liquid-vapour surface tension in mN/m (= mJ/m^2) of a slab with its two
+    interfaces normal to z, from pressure-tensor samples in bar and the box
+    length L_z in A: gamma = L_z/2 [<p_zz> - (<p_xx> + <p_yy>)/2]
+    (1 bar A = 1e-5 N/m)."""
+    pn = float(np.mean(p_zz))
+    pt = 0.5 * (float(np.mean(p_xx)) + float(np.mean(p_yy)))
+    return 0.5 * lz * (pn - pt) * 1e-2

@@ -40,7 +40,7 @@ EXPORTS = ("sw_params_mw", "sw_create", "sw_destroy", "sw_build_neighbors", "sw_
            "sw_forces", "sw_step", "sw_grad", "sw_adjoint", "sw_set_tuning", "sw_get_tuning",
            "sw_query", "sw_status_string", "sw_last_hip_error", "sw_rdf", "sw_adf", "sw_msd",
            "sw_npt", "sw_get_box", "sw_npt_state")
-SW_NPT_WIDTH = 8
+SW_NPT_WIDTH = 11
 SW_Q_MIN_CELL_EDGE = 11
 SW_NPT_STATE = 17
 
@@ -419,8 +419,9 @@ class Context:
             reset: bool = False, every: int = 0, dt: float = 10.0, mass: float = 18.015,
             params: Optional[sw_params] = None, f=None):
         """Isothermal-isobaric steps (see sw_npt in include/sw.h); returns the
-        forces and, if every > 0, the records [nsteps // every][R][8]
-        (V, P_int bar, T, U, KE, pV, extended energy, H').  The box follows
+        forces and, if every > 0, the records [nsteps // every][R][11]
+        (V, P_int bar, T, U, KE, pV, extended energy, H', P_xx, P_yy, P_zz
+        bar).  tau_P <= 0: fixed box (Nose-Hoover NVT).  The box follows
         (`box`)."""
         torch = _torch()
         params = params_mw() if params is None else params

@@ -178,6 +178,24 @@ def replica_table(n_replicas: int = 64, n_min: int = 512, n_max: int = 8192,
                 mass=M_WATER, dt=10.0, nsteps=5000, skin=1.0, tau=1000.0)
 
 
+def slab_lattice(cells=(4, 4, 8), lxy: float = 30.0, rho_gcc: float = 1.0, lz: float = 100.0,
+                 temperature: float = 400.0, seed: int = SEED_CONFIG_BASE + 5):
+    """Start of the liquid-vapour slab workload (Sec. II.C: 1024 particles,
+    Lx = Ly = 30 A, Lz = 100 A): a diamond lattice of `cells`, stretched to
+    lxy x lxy x lz_liq at rho (to be melted in that box), and the slab box
+    with the liquid centred along z.  Returns x (in the liquid box), v, the
+    liquid box and the slab box."""
+    nx, ny, nz = cells
+    n = 8 * nx * ny * nz
+    lz_liq = n * M_WATER / (N_AVOGADRO * rho_gcc * 1e-24) / (lxy * lxy)
+    x, _ = diamond_lattice(nx, ny, nz, 1.0)
+    liq = np.array([lxy, lxy, lz_liq])
+    x = x / np.array([nx, ny, nz], dtype=np.float64) * liq
+    rng = np.random.default_rng(seed)
+    v = maxwell_boltzmann(n, temperature, M_WATER, rng)
+    return dict(x=x, v=v, liquid_box=liq, slab_box=np.array([lxy, lxy, lz]), z_shift=0.5 * (lz - lz_liq))
+
+
 def to_float4(x: np.ndarray) -> np.ndarray:
     """Pack [N,3] into the engine's [N,4] float32 layout (4th lane zero)."""
     out = np.zeros((len(x), 4), dtype=np.float32)

@@ -40,6 +40,23 @@ def test_npt_matches_oracle_short(p_bar):
     for k, tol in ((0, 2e-6), (2, 1e-4), (3, 2e-5), (4, 1e-4), (7, 2e-5)):
         assert np.allclose(r[:, k], o["rows"][:, k], rtol=tol, atol=0), (k, r[:, k], o["rows"][:, k])
     assert np.abs(r[:, 1] - o["rows"][:, 1]).max() < 2.0      # bar
+    assert np.abs(r[:, 8:11] - o["rows"][:, 8:11]).max() < 4.0   # bar, tensor diagonal
+
+
+def test_fixed_box_thermostat_matches_oracle():
+    x, v, L = liquid(1, sigma=0.0)
+    x, v = f32(x), f32(v)
+    ctx = ctx_for([0, len(x)], [L])
+    xd, vd = to_dev(x), to_dev(v)
+    _, rows = ctx.npt(xd, vd, 10, T0=280.0, tau_T=200.0, tau_P=0.0, reset=True, every=1)
+    o = oracle.npt(x, v, L, 10, T0=280.0, tau_T=200.0, tau_P=0.0)
+    assert np.array_equal(ctx.box[0], L)
+    assert np.abs(min_image(from_dev(xd) - o["x"], L)).max() < 1e-4
+    assert np.abs(from_dev(vd) - o["v"]).max() < 1e-4 * np.abs(o["v"]).max()
+    r = rows.cpu().numpy()[:, 0, :]
+    for k, tol in ((2, 1e-4), (3, 2e-5), (7, 2e-5)):
+        assert np.allclose(r[:, k], o["rows"][:, k], rtol=tol, atol=0), k
+    assert np.abs(r[:, 8:11] - o["rows"][:, 8:11]).max() < 4.0
 
 
 def test_npt_replicas_are_independent():
@@ -121,3 +138,27 @@ def test_density_maximum():
     assert 235.0 < res["tmd"] < 265.0, res
     assert abs(res["rho_max"] - 1.003) < 0.004, res
     assert res["rho"][-1] < res["rho_max"] - 0.005 and res["rho"][0] < res["rho_max"] - 0.001
+
+
+@pytest.mark.slow
+def test_slab_surface_tension_300K():
+    """Liquid-vapour slab of Sec. II.C (1024 particles, 30 x 30 x 100 A,
+    Nose-Hoover NVT at 300 K, 5 fs): gamma = Lz/2 [<p_N> - <p_T>] against the
+    paper's 66 +- 2 mJ/m^2, with a bound wide enough for 1 ns of averaging
+    (the paper averaged 20 ns)."""
+    from paper_0809_2811_amd import observables
+    s = synth.slab_lattice()
+    ctx = ctx_for([0, len(s["x"])], [s["liquid_box"]])
+    xd, vd = to_dev(f32(s["x"])), to_dev(f32(s["v"]))
+    ctx.npt(xd, vd, 4000, T0=400.0, tau_T=200.0, tau_P=0.0, dt=5.0, reset=True)      # melt
+    ctx.npt(xd, vd, 4000, T0=300.0, tau_T=200.0, tau_P=0.0, dt=5.0)
+    x = from_dev(xd)
+    x[:, 2] += s["z_shift"]
+    slab = ctx_for([0, len(x)], [s["slab_box"]])
+    xd = to_dev(f32(x))
+    slab.npt(xd, vd, 20000, T0=300.0, tau_T=1000.0, tau_P=0.0, dt=5.0, reset=True)    # 100 ps
+    _, rows = slab.npt(xd, vd, 200000, T0=300.0, tau_T=1000.0, tau_P=0.0, dt=5.0, every=10)
+    r = rows.cpu().numpy()[:, 0, :]
+    g = observables.surface_tension(r[:, 8], r[:, 9], r[:, 10], s["slab_box"][2])
+    assert 54.0 < g < 78.0, g
+    assert abs(r[:, 2].mean() - 300.0) < 3.0
