@@ -414,7 +414,7 @@ def bench_npt(plain_ms_per_step, steps=5000, warm=1000):
     tau_P 2.5 ps, p = 0): the 4096-atom liquid alone, and nine replicas of it
     at 220-320 K in one context (the density-maximum scan)."""
     import torch
-    from paper_0809_2811_amd import scan, sw, synth
+    from paper_0809_2811_amd import scan, sw, synth, tune
     x0, v0, L0 = scan.start_liquid(2)
     n = len(x0)
     out = {"workload": f"npt: {n}-atom liquid at 298 K and p = 0; and 9 replicas of it at 220-320 K",
@@ -423,14 +423,17 @@ def bench_npt(plain_ms_per_step, steps=5000, warm=1000):
         R = len(temps)
         x = torch.from_numpy(synth.to_float4(np.concatenate([x0] * R))).cuda()
         v = torch.from_numpy(synth.to_float4(np.concatenate([v0] * R))).cuda()
-        ctx = sw.Context(np.arange(R + 1) * n, [L0] * R, cutoff=RC, skin=1.0, nbr_capacity=48)
+        lpa = tune.best(R * n, 1.0, 1.0)["lanes_per_atom"]
+        ctx = sw.Context(np.arange(R + 1) * n, [L0] * R, cutoff=RC, skin=1.0, nbr_capacity=48,
+                         tuning=dict(lanes_per_atom=lpa))
         ctx.npt(x, v, warm, T0=temps, reset=True)
         sync()
         t0 = time.perf_counter()
         ctx.npt(x, v, steps, T0=temps)
         sync()
         dt = time.perf_counter() - t0
-        out[name] = {"value": R * n * steps / dt, "ms_per_step": dt * 1e3 / steps, "n_atoms": R * n}
+        out[name] = {"value": R * n * steps / dt, "ms_per_step": dt * 1e3 / steps, "n_atoms": R * n,
+                     "lanes_per_atom": lpa}
     out["value"] = out["batched"]["value"]
     out["single_ratio_to_nve_step"] = out["single"]["ms_per_step"] / plain_ms_per_step
     return out

@@ -58,7 +58,7 @@ struct sw_ctx {
   bool msd_ready = false;
   // isobaric dynamics (allocated on first use)
   swk::NptState* d_npt = nullptr;  // [2][R] double-buffered extended state
-  double* d_pext = nullptr;        // [R]
+  swk::NptConst* d_nptc = nullptr; // [R]
   float2* d_kick = nullptr;        // [R] isobaric kick coefficients (Dev::npt_kick)
   std::vector<swk::NptState> npt;  // host copy between calls
   bool npt_ready = false;

@@ -112,19 +112,36 @@ struct NptState {
   double eta[kNptChain], veta[kNptChain];  // barostat chain
 };
 enum { NPT_BEGIN = 1, NPT_STEP = 3, NPT_END = 2 };   // bit 1: open a step, bit 2: close the previous one
+// Per-replica constants of the extended system, fixed for one call (made on
+// the host from the target temperature, the relaxation times and the atom
+// count): the device chain arithmetic then has no division.
+struct NptConst {
+  double nf, kT, alpha;                    // particle degrees of freedom, k_B T0, 1 + 3 / nf
+  double Q[kNptChain], iQ[kNptChain];      // particle chain masses and their reciprocals
+  double Qb, iQb;                          // barostat chain mass (every link) and reciprocal
+  double Wb, iWb;                          // barostat mass and reciprocal
+  double pext;                             // external pressure (kcal/mol/A^3); 0 without barostat
+};
 struct NptArgs {
   const NptState* in;    // [R] state before this launch
   NptState* out;         // [R] state after it
   RepInfo* reps;         // writable view: box edges and scales follow the state
   float2* kick;          // [R] kick coefficients of the step opened here
-  const double* pext;    // [R] external pressure (kcal/mol/A^3)
+  const NptConst* cst;   // [R]
   double tauT, tauP, rl, rc, dt, c_m;
   int chain;             // chain length 1..kNptChain
+  int apb;               // atoms per block of the force launch: replicas of at most
+                         // kNptFusedBlocks such blocks sum its block partials here,
+                         // larger ones read the reduction launch's thermo_cur
   int mode;              // NPT_BEGIN / NPT_STEP / NPT_END
   int par;               // parity of the positions this launch reads
   double* row;           // [R][kNptRow] record of the step closed here, or null
 };
 constexpr int kNptRow = 11;
+// Largest count of force blocks per replica whose partials the isobaric kick
+// sums in every wave of the replica (the work grows with the square of the
+// replica size; larger replicas take their sums from a reduction launch).
+constexpr int kNptFusedBlocks = 512;
 
 // Optional start/stop events recorded at a launch's dispatch.
 struct KTimer {

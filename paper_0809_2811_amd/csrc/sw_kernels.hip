@@ -706,69 +706,160 @@ __global__ __launch_bounds__(kBlock) void k_thermostat(Dev d, Phys p, int par, i
 // of the replica's first atom stores the new state, box and kick
 // coefficients.
 
-__device__ __forceinline__ double sinhc_d(double x) { return fabs(x) < 1e-4 ? 1.0 + x * x / 6.0 : sinh(x) / x; }
+// exp and sinh(x)/x for the small arguments of the chain and box factors
+// (|x| of order h / tau): Taylor series by Horner's rule for |x| <= 1/16,
+// where the first omitted term is below 2^-60 relative (x^10 / 10! and
+// x^10 / 11!), else the library functions.  The chain is a serial run of
+// such factors, so a short dependent series is the step's critical path.
+__device__ __forceinline__ double exp_small(double x) {
+  if (fabs(x) > 0.0625) return exp(x);
+  double r = 1.0 / 362880.0;                                  // 1/9!
+  r = fma(r, x, 1.0 / 40320.0);
+  r = fma(r, x, 1.0 / 5040.0);
+  r = fma(r, x, 1.0 / 720.0);
+  r = fma(r, x, 1.0 / 120.0);
+  r = fma(r, x, 1.0 / 24.0);
+  r = fma(r, x, 1.0 / 6.0);
+  r = fma(r, x, 0.5);
+  r = fma(r, x, 1.0);
+  return fma(r, x, 1.0);
+}
+
+__device__ __forceinline__ double sinhc_d(double x) {
+  if (fabs(x) > 0.0625) return sinh(x) / x;
+  const double y = x * x;
+  double r = 1.0 / 362880.0;                                  // 1/9!
+  r = fma(r, y, 1.0 / 5040.0);
+  r = fma(r, y, 1.0 / 120.0);
+  r = fma(r, y, 1.0 / 6.0);
+  return fma(r, y, 1.0);
+}
 
 // One chain half step of length h on a subsystem with kinetic term k2 (twice
 // its kinetic energy) and nf degrees of freedom; returns the velocity scale.
-__device__ double chain_half(double h, double& k2, double nf, double kT, const double* Q, double* x, double* vx,
-                             int M) {
-  auto g = [&](int k) { return k == 0 ? (k2 - nf * kT) / Q[0] : (Q[k - 1] * vx[k - 1] * vx[k - 1] - kT) / Q[k]; };
-  vx[M - 1] += 0.5 * h * g(M - 1);
-  for (int k = M - 2; k >= 0; --k) {
-    const double e = exp(-0.25 * h * vx[k + 1]);
-    vx[k] = (vx[k] * e + 0.5 * h * g(k)) * e;
+// Q / iQ are the link masses and reciprocals; the chain length M is a
+// template argument, so every index is a constant, the chain stays in
+// registers, and the particle and barostat chains (independent within a
+// half step) form one straight-line block the scheduler can interleave.
+template <int M>
+__device__ __forceinline__ double chain_half(double h, double& k2, double nfkT, double kT, const double* Q,
+                                             const double* iQ, double* x, double* vx) {
+  auto g = [&](int k) { return k == 0 ? (k2 - nfkT) * iQ[0] : (Q[k - 1] * vx[k - 1] * vx[k - 1] - kT) * iQ[k]; };
+#pragma unroll
+  for (int k = kNptChain - 1; k >= 0; --k) {
+    if (k == M - 1) {
+      vx[k] += 0.5 * h * g(k);
+    } else if (k < M - 1) {
+      const double e = exp_small(-0.25 * h * vx[k + 1]);
+      vx[k] = (vx[k] * e + 0.5 * h * g(k)) * e;
+    }
   }
-  const double sc = exp(-h * vx[0]);
+  const double sc = exp_small(-h * vx[0]);
   k2 *= sc * sc;
-  for (int k = 0; k < M; ++k) x[k] += h * vx[k];
-  for (int k = 0; k < M - 1; ++k) {
-    const double e = exp(-0.25 * h * vx[k + 1]);
-    vx[k] = (vx[k] * e + 0.5 * h * g(k)) * e;
+#pragma unroll
+  for (int k = 0; k < kNptChain; ++k)
+    if (k < M) x[k] += h * vx[k];
+#pragma unroll
+  for (int k = 0; k < kNptChain; ++k) {
+    if (k < M - 1) {
+      const double e = exp_small(-0.25 * h * vx[k + 1]);
+      vx[k] = (vx[k] * e + 0.5 * h * g(k)) * e;
+    } else if (k == M - 1) {
+      vx[k] += 0.5 * h * g(k);
+    }
   }
-  vx[M - 1] += 0.5 * h * g(M - 1);
   return sc;
 }
 
+template <int M, bool BARO>
 __global__ __launch_bounds__(kBlock) void k_npt_kick(Dev d, Phys p, NptArgs a) {
   const int i = blockIdx.x * kBlock + threadIdx.x;
   if (i >= d.npad) return;
-  const int rep = d.tile_rep[i >> 6];
+  // The atom's records are loaded before the replica is known (the arrays
+  // are padded to npad, so the padding lanes read in bounds) and pinned
+  // here, so their round trip overlaps the replica lookup instead of
+  // following the chain arithmetic.
+  const float4 vi = d.v[i], Fi = d.f[i];
+  const uint4 ui = d.u[a.par][i], urefi = d.uref[i];
+  // one wave is one tile of one replica: the replica's records load as scalars
+  const int rep = __builtin_amdgcn_readfirstlane(d.tile_rep[i >> 6]);
+  asm volatile("" ::"v"(vi.x), "v"(Fi.x), "v"(ui.x), "v"(urefi.x));
   const RepInfo& R = d.reps[rep];
   NptState st = a.in[rep];
-  const int M = a.chain;
+  const NptConst C = a.cst[rep];
   const double h = 0.5 * a.dt;
-  const double nf = 3.0 * R.n - 3.0, kT = kBoltz * d.T0[rep], alpha = 1.0 + 3.0 / nf;
-  double Q[kNptChain], Qb[kNptChain];
-  for (int k = 0; k < kNptChain; ++k) {
-    Q[k] = (k == 0 ? nf : 1.0) * kT * a.tauT * a.tauT;
-    Qb[k] = kT * a.tauP * a.tauP;
+  const double nfkT = C.nf * C.kT;
+  const double Qb[kNptChain] = {C.Qb, C.Qb, C.Qb, C.Qb};
+  const double iQb[kNptChain] = {C.iQb, C.iQb, C.iQb, C.iQb};
+  static_assert(kNptChain == 4, "barostat chain constants are spelled out for four links");
+  constexpr bool baro = BARO;                // no barostat: fixed box (NVT)
+  double th[kNQ];
+  const bool rec_wave = a.row && (a.mode & NPT_END) && (i >> 6) == (R.ioff >> 6);
+  if ((R.ipad_end - R.ioff) / a.apb <= kNptFusedBlocks) {
+    // The replica's sums of the force launch's block partials, taken by
+    // every wave of the replica in one fixed order (lane-strided, then a
+    // butterfly, which leaves the same bits in every lane), so all waves
+    // hold identical totals.  The choice depends on the replica alone, so
+    // a replica's arithmetic is the same whatever shares its context.  The
+    // step needs the kinetic and virial sums (2..5); the wave that writes
+    // a record also sums the energies and the tensor diagonal.
+    const int lane = threadIdx.x & 63;
+    const int nbt = d.npad / a.apb, b0 = R.ioff / a.apb, b1 = R.ipad_end / a.apb;
+    constexpr int kJ = kNptFusedBlocks / 64;
+    // one batch of loads for a group of quantities, then the sums
+    auto sum_group = [&](const int* ks, int nk, double* out) {
+      double x[4][kJ];
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int j = 0; j < kJ; ++j)
+          x[q][j] = q < nk ? d.partial[(size_t)ks[q] * nbt + min(b0 + lane + 64 * j, b1 - 1)] : 0.0;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        double acc = 0.0;
+#pragma unroll
+        for (int j = 0; j < kJ; ++j)
+          if (b0 + lane + 64 * j < b1) acc += x[q][j];
+        for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+        if (q < nk) out[ks[q]] = acc;
+      }
+    };
+#pragma unroll
+    for (int k = 0; k < kNQ; ++k) th[k] = 0.0;
+    const int kin[4] = {2, 3, 4, 5}, rec1[4] = {0, 1, 9, 10}, rec2[4] = {11, 11, 11, 11};
+    sum_group(kin, 4, th);
+    if (rec_wave) {
+      sum_group(rec1, 4, th);
+      sum_group(rec2, 1, th);
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < kNQ; ++k) th[k] = d.thermo_cur[(size_t)rep * kNQ + k];
   }
-  const bool baro = a.tauP > 0.0;            // no barostat: fixed box (NVT)
-  const double Wb = (nf + 3.0) * kT * a.tauP * a.tauP;
-  const double pext = baro ? a.pext[rep] : 0.0;
-  const double* th = d.thermo_cur + (size_t)rep * kNQ;
   const double W = th[3] + th[4] + th[5];
   double k2 = 2.0 * th[2];
   double vs = 1.0;
   const bool lead = i == R.ioff;
   if (a.mode & NPT_END) {
     const double V = st.L[0] * st.L[1] * st.L[2];
-    if (baro) st.ve += h * (alpha * k2 + W - 3.0 * pext * V) / Wb;
-    vs = chain_half(h, k2, nf, kT, Q, st.xi, st.vxi, M);
+    if (baro) st.ve += h * (C.alpha * k2 + W - 3.0 * C.pext * V) * C.iWb;
+    vs = chain_half<M>(h, k2, nfkT, C.kT, C.Q, C.iQ, st.xi, st.vxi);
     if (baro) {
-      double kb2 = Wb * st.ve * st.ve;
-      st.ve *= chain_half(h, kb2, 1.0, kT, Qb, st.eta, st.veta, M);
+      double kb2 = C.Wb * st.ve * st.ve;
+      st.ve *= chain_half<M>(h, kb2, C.kT, C.kT, Qb, iQb, st.eta, st.veta);
     }
     if (lead && a.row) {
-      double ext = baro ? 0.5 * Wb * st.ve * st.ve : 0.0;
-      for (int k = 0; k < M; ++k) {
-        ext += 0.5 * Q[k] * st.vxi[k] * st.vxi[k] + (k == 0 ? nf : 1.0) * kT * st.xi[k];
-        if (baro) ext += 0.5 * Qb[k] * st.veta[k] * st.veta[k] + kT * st.eta[k];
+      double ext = baro ? 0.5 * C.Wb * st.ve * st.ve : 0.0;
+#pragma unroll
+      for (int k = 0; k < kNptChain; ++k) {
+        if (k >= M) continue;
+        ext += 0.5 * C.Q[k] * st.vxi[k] * st.vxi[k] + (k == 0 ? C.nf : 1.0) * C.kT * st.xi[k];
+        if (baro) ext += 0.5 * C.Qb * st.veta[k] * st.veta[k] + C.kT * st.eta[k];
       }
       const double U = th[0] + th[1], ke = 0.5 * k2, v2 = vs * vs;
       double* row = a.row + (size_t)rep * kNptRow;
-      row[0] = V; row[1] = (k2 + W) / (3.0 * V) / kBar; row[2] = k2 / (nf * kBoltz); row[3] = U;
-      row[4] = ke; row[5] = pext * V; row[6] = ext; row[7] = ke + U + pext * V + ext;
+      row[0] = V; row[1] = (k2 + W) / (3.0 * V) / kBar; row[2] = k2 / (C.nf * kBoltz); row[3] = U;
+      row[4] = ke; row[5] = C.pext * V; row[6] = ext; row[7] = ke + U + C.pext * V + ext;
       for (int c = 0; c < 3; ++c) row[8 + c] = (v2 * th[9 + c] + th[3 + c]) / V / kBar;   // P_aa
     }
   }
@@ -776,17 +867,17 @@ __global__ __launch_bounds__(kBlock) void k_npt_kick(Dev d, Phys p, NptArgs a) {
   Geo G{};
   if (a.mode & NPT_BEGIN) {
     if (baro) {
-      double kb2 = Wb * st.ve * st.ve;
-      st.ve *= chain_half(h, kb2, 1.0, kT, Qb, st.eta, st.veta, M);
+      double kb2 = C.Wb * st.ve * st.ve;
+      st.ve *= chain_half<M>(h, kb2, C.kT, C.kT, Qb, iQb, st.eta, st.veta);
     }
-    vs *= chain_half(h, k2, nf, kT, Q, st.xi, st.vxi, M);
+    vs *= chain_half<M>(h, k2, nfkT, C.kT, C.Q, C.iQ, st.xi, st.vxi);
     const double V = st.L[0] * st.L[1] * st.L[2];
-    if (baro) st.ve += h * (alpha * k2 + W - 3.0 * pext * V) / Wb;
-    const double c = alpha * st.ve;
-    ka = (float)exp(-c * h);
-    kb = (float)(h * a.c_m * exp(-0.5 * c * h) * sinhc_d(0.5 * c * h));
-    const double gr = exp(st.ve * a.dt);
-    tx = (float)(a.dt * exp(0.5 * st.ve * a.dt) * sinhc_d(0.5 * st.ve * a.dt));
+    if (baro) st.ve += h * (C.alpha * k2 + W - 3.0 * C.pext * V) * C.iWb;
+    const double c = C.alpha * st.ve;
+    ka = (float)exp_small(-c * h);
+    kb = (float)(h * a.c_m * exp_small(-0.5 * c * h) * sinhc_d(0.5 * c * h));
+    const double gr = exp_small(st.ve * a.dt);
+    tx = (float)(a.dt * exp_small(0.5 * st.ve * a.dt) * sinhc_d(0.5 * st.ve * a.dt));
     for (int k = 0; k < 3; ++k) st.L[k] *= gr;
     hs = (float)(0.5 * (st.L[0] / d.lref[rep] * a.rl - a.rc) - 1e-4);
     G = Geo{(float)(st.L[0] / kTwo32), (float)(st.L[1] / kTwo32), (float)(st.L[2] / kTwo32),
@@ -794,13 +885,12 @@ __global__ __launch_bounds__(kBlock) void k_npt_kick(Dev d, Phys p, NptArgs a) {
             R.nc[0], R.nc[1], R.nc[2], R.cell_off};
   }
   if (i < R.iend) {
-    float4 v = d.v[i];
+    float4 v = vi;
     const float fs = (float)vs;
     v.x *= fs; v.y *= fs; v.z *= fs;
     if (a.mode & NPT_BEGIN) {
-      const float4 F = d.f[i];
-      v.x = ka * v.x + kb * F.x; v.y = ka * v.y + kb * F.y; v.z = ka * v.z + kb * F.z;
-      drift_bin(d, G, rep, i, d.u[a.par][i], v, d.uref[i], tx, hs, a.par ^ 1);
+      v.x = ka * v.x + kb * Fi.x; v.y = ka * v.y + kb * Fi.y; v.z = ka * v.z + kb * Fi.z;
+      drift_bin(d, G, rep, i, ui, v, urefi, tx, hs, a.par ^ 1);
     }
     d.v[i] = v;
   }
@@ -978,7 +1068,7 @@ hipError_t moments_lpa(const Dev& d, const Phys& p, int par, int force_rebuild, 
 
 template <int LPA, int MODE>
 hipError_t forces_mode(const Dev& d, const Phys& p, int vir, int par, double* ring_row, hipStream_t s,
-                       const KTimer& tm) {
+                       const KTimer& tm, bool reduce = true) {
   constexpr int APB = kBlock / LPA;
   const unsigned grid = (unsigned)(d.npad / APB);
   if (!tm.start && !tm.stop) {
@@ -991,7 +1081,7 @@ hipError_t forces_mode(const Dev& d, const Phys& p, int vir, int par, double* ri
     hipExtLaunchKernelGGL((k_forces<LPA, MODE, false>), dim3(grid), dim3(kBlock), 0u, s, tm.start, tm.stop, 0u, d,
                           p, par);
   }
-  if (vir || MODE == MODE_KICK)
+  if (reduce && (vir || MODE == MODE_KICK))
     hipLaunchKernelGGL(k_reduce_thermo, dim3((unsigned)min(d.R * kNQ, 4096)), dim3(kBlock), 0, s, d, APB, ring_row);
   return hipGetLastError();
 }
@@ -1005,7 +1095,8 @@ hipError_t forces_lpa(const Dev& d, const Phys& p, int mode, int vir, int par, d
     case MODE_NVE: return forces_mode<LPA, MODE_NVE>(d, p, vir, par, ring_row, s, tm);
     case MODE_NVE_LAST: return forces_mode<LPA, MODE_NVE_LAST>(d, p, vir, par, ring_row, s, tm);
     case MODE_KICK: return forces_mode<LPA, MODE_KICK>(d, p, vir, par, ring_row, s, tm);
-    case MODE_NPT: return forces_mode<LPA, MODE_NPT>(d, p, 1, par, ring_row, s, tm);
+    // isobaric: sums always; vir = 0 leaves the block partials to the kick launch
+    case MODE_NPT: return forces_mode<LPA, MODE_NPT>(d, p, 1, par, ring_row, s, tm, vir != 0);
   }
   return hipErrorInvalidValue;
 }
@@ -1129,7 +1220,20 @@ hipError_t launch_fill_f32(float* p, float value, long long n, hipStream_t s) {
 }
 
 hipError_t launch_npt_kick(const Dev& d, const Phys& p, const NptArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(k_npt_kick, dim3(nblk(d.npad, kBlock)), dim3(kBlock), 0, s, d, p, a);
+  const dim3 grid(nblk(d.npad, kBlock)), block(kBlock);
+  static_assert(kNptChain == 4, "one kick instantiation per chain length");
+  const bool baro = a.tauP > 0.0;
+  switch (a.chain * 2 + (baro ? 1 : 0)) {
+    case 2: hipLaunchKernelGGL((k_npt_kick<1, false>), grid, block, 0, s, d, p, a); break;
+    case 3: hipLaunchKernelGGL((k_npt_kick<1, true>), grid, block, 0, s, d, p, a); break;
+    case 4: hipLaunchKernelGGL((k_npt_kick<2, false>), grid, block, 0, s, d, p, a); break;
+    case 5: hipLaunchKernelGGL((k_npt_kick<2, true>), grid, block, 0, s, d, p, a); break;
+    case 6: hipLaunchKernelGGL((k_npt_kick<3, false>), grid, block, 0, s, d, p, a); break;
+    case 7: hipLaunchKernelGGL((k_npt_kick<3, true>), grid, block, 0, s, d, p, a); break;
+    case 8: hipLaunchKernelGGL((k_npt_kick<4, false>), grid, block, 0, s, d, p, a); break;
+    case 9: hipLaunchKernelGGL((k_npt_kick<4, true>), grid, block, 0, s, d, p, a); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

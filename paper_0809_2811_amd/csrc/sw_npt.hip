@@ -31,7 +31,7 @@ int ensure_npt(sw_ctx* c) {
   if (!c->d_npt &&
       (e = dalloc_raw(c, (void**)&c->d_npt, sizeof(NptState) * 2 * c->R, c->allocs)) != hipSuccess)
     return e == hipErrorOutOfMemory ? SW_ENOMEM : fail_hip(c, e);
-  if (!c->d_pext && (e = dalloc_raw(c, (void**)&c->d_pext, sizeof(double) * c->R, c->allocs)) != hipSuccess)
+  if (!c->d_nptc && (e = dalloc_raw(c, (void**)&c->d_nptc, sizeof(NptConst) * c->R, c->allocs)) != hipSuccess)
     return e == hipErrorOutOfMemory ? SW_ENOMEM : fail_hip(c, e);
   if (!c->npt_ready) {
     c->npt.resize(c->R);
@@ -51,6 +51,27 @@ void set_boxes(sw_ctx* c, const std::vector<NptState>& st) {
       c->reps[r].scale[k] = (float)(L / kTwo32);
       c->reps[r].inv_scale[k] = (float)(kTwo32 / L);
     }
+}
+
+// Masses of the extended system for replica r (thermostat chain: Q_1 = N_f kT
+// tau_T^2, later links kT tau_T^2; barostat W = (N_f + 3) kT tau_P^2 and its
+// chain kT tau_P^2).
+NptConst npt_const(const sw_ctx* c, int r, double T0, double p_ext, double tauT, double tauP) {
+  NptConst k{};
+  k.nf = 3.0 * c->reps[r].n - 3.0;
+  k.kT = kBoltz * T0;
+  k.alpha = 1.0 + 3.0 / k.nf;
+  for (int j = 0; j < kNptChain; ++j) {
+    k.Q[j] = (j == 0 ? k.nf : 1.0) * k.kT * tauT * tauT;
+    k.iQ[j] = 1.0 / k.Q[j];
+  }
+  const bool baro = tauP > 0.0;
+  k.Qb = baro ? k.kT * tauP * tauP : 1.0;
+  k.iQb = 1.0 / k.Qb;
+  k.Wb = baro ? (k.nf + 3.0) * k.kT * tauP * tauP : 1.0;
+  k.iWb = 1.0 / k.Wb;
+  k.pext = baro ? p_ext : 0.0;
+  return k;
 }
 
 bool grid_fits(const sw_ctx* c, double margin) {
@@ -81,11 +102,18 @@ int sw_npt(sw_ctx* ctx, float* x, float* v, float* f, const sw_params* params, d
   if (reset)
     for (int r = 0; r < ctx->R; ++r) ctx->npt[r] = fresh_state(ctx, r);
   const std::vector<NptState> start = ctx->npt;
-  std::vector<double> pext(ctx->R);
-  for (int r = 0; r < ctx->R; ++r) pext[r] = h_p_bar[r] * kBar;
+  std::vector<NptConst> cst(ctx->R);
+  for (int r = 0; r < ctx->R; ++r) cst[r] = npt_const(ctx, r, h_T0[r], h_p_bar[r] * kBar, tau_T_fs, tau_P_fs);
   const std::vector<float2> unit(ctx->R, make_float2(1.f, 0.f));
   const int lpa = lpa_for(ctx);
   const double rl = ctx->cutoff + ctx->skin;
+  // small replicas: the kick launch sums the force blocks' partials itself;
+  // the force launches add a reduction launch only if some replica is larger
+  const int apb = kBlock / lpa;
+  int max_blocks = 0;
+  for (int r = 0; r < ctx->R; ++r)
+    max_blocks = std::max(max_blocks, (ctx->reps[r].ipad_end - ctx->reps[r].ioff) / apb);
+  const int sums = max_blocks > kNptFusedBlocks ? 1 : 0;
   double margin = kGridMargin;
   set_boxes(ctx, start);
   if (!grid_fits(ctx, 0.5 * margin) && (st = regrid(ctx, margin)) != SW_OK) return st;
@@ -97,7 +125,7 @@ int sw_npt(sw_ctx* ctx, float* x, float* v, float* f, const sw_params* params, d
             hipSuccess ||
         (e = hipMemcpyAsync(ctx->d_npt, start.data(), sizeof(NptState) * ctx->R, hipMemcpyHostToDevice, s)) !=
             hipSuccess ||
-        (e = hipMemcpyAsync(ctx->d_pext, pext.data(), sizeof(double) * ctx->R, hipMemcpyHostToDevice, s)) !=
+        (e = hipMemcpyAsync(ctx->d_nptc, cst.data(), sizeof(NptConst) * ctx->R, hipMemcpyHostToDevice, s)) !=
             hipSuccess ||
         (e = hipMemcpyAsync(ctx->d_T0, h_T0, sizeof(double) * ctx->R, hipMemcpyHostToDevice, s)) != hipSuccess ||
         (e = hipMemcpyAsync(ctx->d_kick, unit.data(), sizeof(float2) * ctx->R, hipMemcpyHostToDevice, s)) !=
@@ -107,11 +135,11 @@ int sw_npt(sw_ctx* ctx, float* x, float* v, float* f, const sw_params* params, d
     if ((e = sort_in(ctx, x, v, s)) != hipSuccess) return fail_hip(ctx, e);
     // forces, virial and kinetic sums at the initial state (kick = identity)
     if ((e = launch_moments(ctx->d, ph, lpa, 0, 1, 0, s)) != hipSuccess) return fail_hip(ctx, e);
-    if ((e = launch_forces(ctx->d, ph, lpa, MODE_NPT, 1, 0, nullptr, s)) != hipSuccess) return fail_hip(ctx, e);
+    if ((e = launch_forces(ctx->d, ph, lpa, MODE_NPT, sums, 0, nullptr, s)) != hipSuccess) return fail_hip(ctx, e);
     NptArgs a{};
     a.reps = ctx->d_reps;
     a.kick = ctx->d_kick;
-    a.pext = ctx->d_pext;
+    a.cst = ctx->d_nptc;
     a.tauT = tau_T_fs;
     a.tauP = tau_P_fs;
     a.rl = rl;
@@ -119,6 +147,7 @@ int sw_npt(sw_ctx* ctx, float* x, float* v, float* f, const sw_params* params, d
     a.dt = dt;
     a.c_m = kAcc / mass;
     a.chain = chain;
+    a.apb = apb;
     const size_t rowsz = (size_t)ctx->R * kNptRow;
     auto row_of = [&](int step) -> double* {   // record of 1-based step, or null
       return rows && step > 0 && step % every == 0 ? rows + (size_t)(step / every - 1) * rowsz : nullptr;
@@ -132,7 +161,7 @@ int sw_npt(sw_ctx* ctx, float* x, float* v, float* f, const sw_params* params, d
       if ((e = launch_npt_kick(ctx->d, ph, a, s)) != hipSuccess) return fail_hip(ctx, e);
       const int rec = row_of(t) != nullptr;
       if ((e = launch_moments(ctx->d, ph, lpa, t & 1, 0, rec, s)) != hipSuccess) return fail_hip(ctx, e);
-      if ((e = launch_forces(ctx->d, ph, lpa, MODE_NPT, 1, t & 1, nullptr, s)) != hipSuccess)
+      if ((e = launch_forces(ctx->d, ph, lpa, MODE_NPT, sums, t & 1, nullptr, s)) != hipSuccess)
         return fail_hip(ctx, e);
     }
     if (nsteps > 0) {   // close the last step

@@ -32,7 +32,7 @@ def density_scan(temperatures, reps: int = 2, p_bar: float = 0.0, equil_steps: i
                  sample_steps: int = 400000, every: int = 100, chunk: int = 50000, dt: float = 10.0,
                  skin: float = 1.0, tau_T: float = 1000.0, tau_P: float = 2500.0, log=None):
     import torch
-    from paper_0809_2811_amd import sw, synth
+    from paper_0809_2811_amd import sw, synth, tune
     x0, _, L0 = start_liquid(reps)
     n = len(x0)
     R = len(temperatures)
@@ -43,7 +43,8 @@ def density_scan(temperatures, reps: int = 2, p_bar: float = 0.0, equil_steps: i
         vs.append(synth.maxwell_boltzmann(n, float(T), M_WATER, rng))
     x = torch.from_numpy(synth.to_float4(np.concatenate(xs))).cuda()
     v = torch.from_numpy(synth.to_float4(np.concatenate(vs))).cuda()
-    ctx = sw.Context(np.arange(R + 1) * n, [L0] * R, cutoff=RC, skin=skin, nbr_capacity=64)
+    ctx = sw.Context(np.arange(R + 1) * n, [L0] * R, cutoff=RC, skin=skin, nbr_capacity=48,
+                     tuning=dict(lanes_per_atom=tune.best(R * n, 1.0, skin)["lanes_per_atom"]))
     T0 = [float(t) for t in temperatures]
     kw = dict(T0=T0, p_bar=p_bar, tau_T=tau_T, tau_P=tau_P, dt=dt)
     done = 0

@@ -43,6 +43,43 @@ def test_npt_matches_oracle_short(p_bar):
     assert np.abs(r[:, 8:11] - o["rows"][:, 8:11]).max() < 4.0   # bar, tensor diagonal
 
 
+def test_npt_large_replica_sums_match_oracle():
+    """4096 atoms at 64 lanes per atom: 1024 force blocks, so the per-replica
+    sums come from the reduction launch instead of the kick's own sums."""
+    x, v, L = liquid(2)
+    x, v = f32(x), f32(v)
+    ctx = ctx_for([0, len(x)], [L], lpa=64)
+    xd, vd = to_dev(x), to_dev(v)
+    _, rows = ctx.npt(xd, vd, 6, T0=298.0, p_bar=0.0, tau_T=200.0, tau_P=500.0, chain=3, reset=True, every=1)
+    o = oracle.npt(x, v, L, 6, T0=298.0, p_bar=0.0, tau_T=200.0, tau_P=500.0, chain=3)
+    assert np.allclose(ctx.box[0], o["box"], rtol=2e-6, atol=0)
+    assert np.abs(min_image(from_dev(xd) - o["x"], o["box"])).max() < 1e-4
+    assert np.abs(from_dev(vd) - o["v"]).max() < 1e-4 * np.abs(o["v"]).max()
+    r = rows.cpu().numpy()[:, 0, :]
+    for k, tol in ((0, 2e-6), (2, 1e-4), (3, 2e-5), (4, 1e-4), (7, 2e-5)):
+        assert np.allclose(r[:, k], o["rows"][:, k], rtol=tol, atol=0), (k, r[:, k], o["rows"][:, k])
+
+
+def test_npt_mixed_replica_sizes_are_independent():
+    """A 512-atom replica (kick-summed) beside a 4096-atom one (1024 force
+    blocks at 64 lanes per atom: reduction launch) gives the same bits as the
+    512-atom replica alone."""
+    xs, vs, Ls = [], [], []
+    for reps in (1, 2):
+        x, v, L = liquid(reps)
+        xs.append(f32(x)); vs.append(f32(v)); Ls.append(L)
+    off = [0, len(xs[0]), len(xs[0]) + len(xs[1])]
+    ctx = ctx_for(off, Ls, lpa=64)
+    xd, vd = to_dev(np.concatenate(xs)), to_dev(np.concatenate(vs))
+    ctx.npt(xd, vd, 20, T0=[290.0, 300.0], p_bar=[0.0, 100.0], tau_T=500.0, tau_P=1000.0, reset=True)
+    c1 = ctx_for([0, off[1]], [Ls[0]], lpa=64)
+    x1, v1 = to_dev(xs[0]), to_dev(vs[0])
+    c1.npt(x1, v1, 20, T0=290.0, p_bar=0.0, tau_T=500.0, tau_P=1000.0, reset=True)
+    assert np.array_equal(from_dev(xd)[:off[1]], from_dev(x1))
+    assert np.array_equal(from_dev(vd)[:off[1]], from_dev(v1))
+    assert np.array_equal(ctx.box[0], c1.box[0])
+
+
 def test_fixed_box_thermostat_matches_oracle():
     x, v, L = liquid(1, sigma=0.0)
     x, v = f32(x), f32(v)
