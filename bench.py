@@ -215,6 +215,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=500)
     ap.add_argument("--skin", type=float, default=0.0, help="Verlet skin in A (0 = tuned)")
     ap.add_argument("--lpa", type=int, default=0, help="lanes per atom (0 = tuned default)")
+    ap.add_argument("--graph-steps", type=int, default=-1,
+                    help="steps per captured block, 0 = stream launches (-1 = tuned); the launch form does not "
+                         "change what a kernel launch reads or writes")
     ap.add_argument("--forms", default="large,batched,adjoint,observables,npt",
                     help="comma list of large,batched,adjoint,observables,npt or none")
     ap.add_argument("--no-cpu", action="store_true")
@@ -244,6 +247,8 @@ def main():
     tuning.pop("skin", None)
     if args.lpa:
         tuning["lanes_per_atom"] = args.lpa
+    if args.graph_steps >= 0:
+        tuning["graph_steps"] = args.graph_steps
     args.skin = skin
     ctx, x, v = prepare_liquid(cfg, args.skin, tuning)
     if args.warmup > 0:
@@ -265,7 +270,7 @@ def main():
     forms = [f for f in args.forms.split(",") if f and f != "none"]
     line["forms"] = {}
     if "large" in forms:
-        line["forms"]["large_box"] = bench_large()
+        line["forms"]["large_box"] = bench_large(graph_steps=args.graph_steps)
     if "batched" in forms:
         line["forms"]["batched"] = bench_batched()
     if "adjoint" in forms:
@@ -279,7 +284,7 @@ def main():
     print(json.dumps(line), flush=True)
 
 
-def bench_large(steps=1000, skin=0.5):
+def bench_large(steps=1000, skin=0.5, graph_steps=-1):
     """262144 atoms (32^3 cells, 1.00 g/cm^3), 298 K liquid, 1000 NVE steps,
     rows rebuilt at least every 10 steps and whenever the skin check fires."""
     from paper_0809_2811_amd import synth, tune
@@ -288,6 +293,8 @@ def bench_large(steps=1000, skin=0.5):
     tuning = tune.best(n, 1.0, skin)
     tuning.pop("skin", None)
     tuning["rebuild_every"] = 10
+    if graph_steps >= 0:
+        tuning["graph_steps"] = graph_steps
     ctx, x, v = prepare_liquid(cfg, skin, tuning)
     ctx.step(x, v, 50)
     res = timed_nve(ctx, x, v, steps)
