@@ -299,10 +299,57 @@ __device__ void moments_tile(const Dev& d, const Phys& p, int par, int force_reb
       }
     }
     __syncthreads();
-    if (real) {
+    if (real && LPA >= 16) {
+      // Many lanes per atom (small boxes, few waves in flight: latency
+      // bound).  The cell of every candidate slot of a pass is found by a
+      // branch-free binary search (the largest c with pre[c] <= k) run for
+      // all the pass's slots level by level, one LDS round trip per level;
+      // steps past cell 26 read pre[27] = ncand, which no slot reaches, and
+      // slots past the end search for the last candidate and are rejected.
+      // Accepted entries are compacted with a ballot over the group.
       const int ncand = pre[27];
       const float rl2 = p.rl2;
-      // candidate slots k = lane + LPA*t, kCL per pass with independent loads
+      const int wl = threadIdx.x & 63;
+      const unsigned long long gmask = LPA == 64 ? ~0ull : ((1ull << LPA) - 1) << (wl & ~(LPA - 1));
+      const unsigned long long below = (1ull << wl) - 1;
+      int run = 0;                             // entries appended so far (lane 0 sees every pass)
+      constexpr int kCL = 6;
+      for (int k0 = lane; k0 < ncand; k0 += kCL * LPA) {
+        int c[kCL];
+#pragma unroll
+        for (int t = 0; t < kCL; ++t) c[t] = 0;
+#pragma unroll
+        for (int step = 16; step >= 1; step >>= 1) {
+#pragma unroll
+          for (int t = 0; t < kCL; ++t) {
+            const int nc = c[t] + step;
+            c[t] = pre[min(nc, 27)] <= min(k0 + t * LPA, ncand - 1) ? nc : c[t];
+          }
+        }
+        uint4 e[kCL];
+#pragma unroll
+        for (int t = 0; t < kCL; ++t)
+          e[t] = gm[(size_t)cid[c[t]] * ccap + (min(k0 + t * LPA, ncand - 1) - pre[c[t]])];
+#pragma unroll
+        for (int t = 0; t < kCL; ++t) {
+          const int j = (int)e[t].w;
+          const float3 dd = disp(ui, e[t], sc0, sc1, sc2);
+          const bool acc = k0 + t * LPA < ncand && j != i && dd.x * dd.x + dd.y * dd.y + dd.z * dd.z < rl2;
+          const unsigned long long m = __ballot(acc) & gmask;
+          if (acc) {
+            const int sl = run + __popcll(m & below);
+            if (sl < cap) cand[sl] = j;
+          }
+          run += __popcll(m);
+        }
+      }
+      if (lane == 0) cnt[g] = run;
+    } else if (real) {
+      // Few lanes per atom (large boxes, the CU full of waves: throughput
+      // bound).  Each slot searches its cell on its own and skips the search
+      // and the load past the end; appends take an LDS counter.
+      const int ncand = pre[27];
+      const float rl2 = p.rl2;
       constexpr int kCL = 8;
       for (int k0 = lane; k0 < ncand; k0 += kCL * LPA) {
         uint4 e[kCL];
