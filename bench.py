@@ -226,8 +226,8 @@ def main():
                          "the known-size reference for scaling HBM byte counters")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py runs on one GPU only: this engine has no multi-GPU path (see DESIGN.md for how "
-              "it would shard); run with --gpus 1", file=sys.stderr)
+        print("bench.py runs on one GPU only: this engine has no multi-GPU path; run with --gpus 1",
+              file=sys.stderr)
         sys.exit(2)
     import torch
     from paper_0809_2811_amd import synth, tune
