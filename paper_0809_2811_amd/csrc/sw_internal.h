@@ -28,8 +28,16 @@ constexpr int kNQ = 12;            // thermo quantities per replica
 // Row rebuild staging in LDS (moments kernel), per block: candidate and
 // sorted rows [2][APB][cap] ints, row counts [APB], per-atom cell prefix and
 // cell ids [APB][56].
+// LDS of one moments block (apb atoms per block, rows of cap slots): the
+// rebuild's candidate and sorted lists, counts, cell prefixes and ids, and
+// with 16 or more lanes per atom (apb <= 16) the candidates' positions,
+// 16-byte aligned after the int part.
+__host__ __device__ constexpr size_t moments_lds_ints(int apb, int cap) {
+  return 2 * (size_t)apb * cap + apb + 56 * (size_t)apb;
+}
 __host__ __device__ constexpr size_t moments_lds_bytes(int apb, int cap) {
-  return sizeof(int) * (2 * (size_t)apb * cap + apb + 56 * (size_t)apb);
+  return ((sizeof(int) * moments_lds_ints(apb, cap) + 15) & ~(size_t)15) +
+         (apb <= 16 ? 16 * (size_t)apb * cap : 0);
 }
 constexpr double kAcc = 4.184e-4;  // (A/fs^2) per ((kcal/mol/A)/(g/mol))
 constexpr double kBoltz = 8.314462618 / 4184.0;  // kcal/(mol K)

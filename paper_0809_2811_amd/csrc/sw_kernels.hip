@@ -210,7 +210,9 @@ __device__ __forceinline__ void clear_next(const Dev& d, int par, int b, int G) 
   for (int c = b * kBlock + threadIdx.x; c < d.ctot; c += G * kBlock) d.gcnt[par ^ 1][c] = 0;
 }
 
-// lds: [APB][cap] candidates, [APB][cap] sorted, [APB] counts, [APB][56] cell prefix and ids
+// lds: [APB][cap] candidates, [APB][cap] sorted, [APB] counts, [APB][56] cell
+// prefix and ids; with 16 or more lanes per atom also [APB][cap] candidate
+// positions (16-byte aligned)
 template <int LPA, bool ENERGY>
 __device__ void moments_tile(const Dev& d, const Phys& p, int par, int force_rebuild, int bid, int* lds) {
   constexpr int APB = kBlock / LPA;
@@ -239,12 +241,19 @@ __device__ void moments_tile(const Dev& d, const Phys& p, int par, int force_reb
   // each replica rebuilds on its own displacement record
   const bool rebuild = force_rebuild || d.dflag[par * d.R + rep] != 0;
   int nn = nn_row;
+  bool from_lds = false;                   // row slots name candidate positions in LDS
+  const uint4* lds_u = nullptr;
 
   if (rebuild) {                           // block-uniform
     int* cand = lds + g * cap;
     int* srt = lds + APB * cap + g * cap;
     int* cnt = lds + 2 * APB * cap;
     int* pre = lds + 2 * APB * cap + APB + g * 56;   // [28] prefix of cell counts
+    // candidate positions (16+ lanes per atom): the moments below read the
+    // rebuilt row's neighbour positions from here instead of gathering them
+    uint4* cand_u = reinterpret_cast<uint4*>(
+                        reinterpret_cast<char*>(lds) + ((sizeof(int) * moments_lds_ints(APB, cap) + 15) & ~(size_t)15)) +
+                    g * cap;
     int* cid = pre + 28;                             // [27] cell ids
     if (lane == 0) cnt[g] = 0;
     const int n0 = G.nc0, n1 = G.nc1, n2 = G.nc2;
@@ -338,7 +347,10 @@ __device__ void moments_tile(const Dev& d, const Phys& p, int par, int force_reb
           const unsigned long long m = __ballot(acc) & gmask;
           if (acc) {
             const int sl = run + __popcll(m & below);
-            if (sl < cap) cand[sl] = j;
+            if (sl < cap) {
+              cand[sl] = j;
+              cand_u[sl] = e[t];   // a cell entry holds the position of that parity
+            }
           }
           run += __popcll(m);
         }
@@ -384,11 +396,14 @@ __device__ void moments_tile(const Dev& d, const Phys& p, int par, int force_reb
     }
     total = min(total, cap);
     if (real) {
+      // Ascending neighbour index: the row and every later sum over it are
+      // independent of the order the cells were filled in.  With candidate
+      // positions in LDS the sorted list holds candidate slots, else indices.
       for (int k = lane; k < total; k += LPA) {
         const int vj = cand[k];
         int rank = 0;
         for (int q = 0; q < total; ++q) rank += cand[q] < vj;
-        srt[rank] = vj;
+        srt[rank] = LPA >= 16 ? k : vj;
         d.nl[(size_t)i * cap + rank] = vj;
       }
       if (lane == 0) {
@@ -399,6 +414,10 @@ __device__ void moments_tile(const Dev& d, const Phys& p, int par, int force_reb
     __syncthreads();
     nn = real ? total : 0;
     row = srt;
+    if (LPA >= 16) {
+      from_lds = true;
+      lds_u = cand_u;
+    }
 #pragma unroll
     for (int u = 0; u < kMU; ++u) jn[u] = srt[min(lane + u * LPA, cap - 1)];
     if (bid * APB == ioff && threadIdx.x == 0) {
@@ -420,7 +439,13 @@ __device__ void moments_tile(const Dev& d, const Phys& p, int par, int force_reb
     for (int u = 0; u < kMU; ++u) jn[u] = row[min(s0 + (kMU + u) * LPA, nn - 1)];
     uint4 uu[kMU];
 #pragma unroll
-    for (int u = 0; u < kMU; ++u) uu[u] = jj[u] >= 0 ? upm[jj[u]] : ui;
+    for (int u = 0; u < kMU; ++u) {
+      uu[u] = ui;
+      if (jj[u] >= 0) {
+        if (from_lds) uu[u] = lds_u[jj[u]];
+        else uu[u] = upm[jj[u]];
+      }
+    }
 #pragma unroll
     for (int u = 0; u < kMU; ++u) {
       const float3 dd = disp(ui, uu[u], sc0, sc1, sc2);
