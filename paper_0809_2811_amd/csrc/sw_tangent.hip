@@ -87,18 +87,27 @@ __global__ __launch_bounds__(kBlock) void k_tan_moments(Dev d, Tan t, Phys p, co
   const int bid = xcd_remap(blockIdx.x, gridDim.x);
   const int g = threadIdx.x / LPA, lane = threadIdx.x % LPA;
   const int i = bid * APB + g;
-  const RepInfo& R = d.reps[d.tile_rep[(bid * APB) >> 6]];
-  const bool real = i < R.iend;
+  // The atom's own records and its first row slot are loaded before the
+  // replica is known (arrays are padded to npad: padding lanes read in
+  // bounds and are masked), so they share one round trip with the lookup.
   const uint4 ui = d.u[par][i];
   const float4 wi = w[i];
-  const int nn = real ? d.nn[i] : 0;
+  const int nn_row = d.nn[i];
   const int* row = d.nl + (size_t)i * d.cap;
+  int jn = row[min(lane, d.cap - 1)];
+  const RepInfo& R = d.reps[d.tile_rep[(bid * APB) >> 6]];
+  const bool real = i < R.iend;
+  const int nn = real ? nn_row : 0;
   float T0 = 0.f, T1 = 0.f, T2 = 0.f, T3 = 0.f, T4 = 0.f, T5 = 0.f, V0 = 0.f, V1 = 0.f, V2 = 0.f, S = 0.f;
   for (int s = lane; s < nn; s += LPA) {
-    const int j = row[s];
-    const float3 dd = disp(ui, d.u[par][j], R.scale[0], R.scale[1], R.scale[2]);
+    const int j = jn;
+    jn = row[min(s + LPA, nn - 1)];   // the next slot, in flight during this one
+    const uint4 uj = d.u[par][j];
+    const float4 wj = w[j];            // read whatever the distance: one batch with the position
+    asm volatile("" ::"v"(uj.x), "v"(wj.x));
+    const float3 dd = disp(ui, uj, R.scale[0], R.scale[1], R.scale[2]);
     if (dd.x * dd.x + dd.y * dd.y + dd.z * dd.z < p.rc2) {
-      const Geo G = geometry(dd, sub3(w[j], wi), p);
+      const Geo G = geometry(dd, sub3(wj, wi), p);
       const D ex = G.eg * G.ux, ey = G.eg * G.uy, ez = G.eg * G.uz;
       T0 += (ex * G.ux).d; T1 += (ey * G.uy).d; T2 += (ez * G.uz).d;
       T3 += (ex * G.uy).d; T4 += (ex * G.uz).d; T5 += (ey * G.uz).d;
@@ -128,10 +137,18 @@ __global__ __launch_bounds__(kBlock) void k_tan_forces(Dev d, Tan t, Phys p, con
   const int bid = xcd_remap(blockIdx.x, gridDim.x);
   const int g = threadIdx.x / LPA, lane = threadIdx.x % LPA;
   const int i = bid * APB + g;
-  const RepInfo& R = d.reps[d.tile_rep[(bid * APB) >> 6]];
-  const bool real = i < R.iend;
+  // own records and the first row slot before the replica lookup (padded
+  // arrays: padding lanes read in bounds and are masked)
   const uint4 ui = d.u[par][i];
   const float4 wi = w[i];
+  const float4* m = d.mom + 3 * (size_t)i;
+  const float4* md = t.mdot + 3 * (size_t)i;
+  const float4 a0 = m[0], a1 = m[1], a2 = m[2], b0 = md[0], b1 = md[1], b2 = md[2];
+  const int nn_row = d.nn[i];
+  const int* row = d.nl + (size_t)i * d.cap;
+  int jn = row[min(lane, d.cap - 1)];
+  const RepInfo& R = d.reps[d.tile_rep[(bid * APB) >> 6]];
+  const bool real = i < R.iend;
   const float c0 = p.c0, c02 = p.c0 * p.c0;
   D Tm[6], Vm[3], Sm{0.f, 0.f};
   float E2i = 0.f, E3i = 0.f;
@@ -139,32 +156,34 @@ __global__ __launch_bounds__(kBlock) void k_tan_forces(Dev d, Tan t, Phys p, con
   for (int k = 0; k < 3; ++k) Vm[k] = D{0.f, 0.f};
   int nn = 0;
   if (real) {
-    const float4* m = d.mom + 3 * (size_t)i;
-    const float4* md = t.mdot + 3 * (size_t)i;
-    const float4 a0 = m[0], a1 = m[1], a2 = m[2], b0 = md[0], b1 = md[1], b2 = md[2];
     Tm[0] = {a0.x, b0.x}; Tm[1] = {a0.y, b0.y}; Tm[2] = {a0.z, b0.z}; Tm[3] = {a0.w, b0.w};
     Tm[4] = {a1.x, b1.x}; Tm[5] = {a1.y, b1.y}; Vm[0] = {a1.z, b1.z}; Vm[1] = {a1.w, b1.w};
     Vm[2] = {a2.x, b2.x}; Sm = {a2.y, b2.y};
     E2i = a2.z; E3i = a2.w;
-    nn = d.nn[i];
+    nn = nn_row;
   }
-  const int* row = d.nl + (size_t)i * d.cap;
   D fx{0.f, 0.f}, fy{0.f, 0.f}, fz{0.f, 0.f}, w2{0.f, 0.f}, w3{0.f, 0.f};
   float gx = 0.f, gy = 0.f, gz = 0.f;   // three-body force
   for (int s = lane; s < nn; s += LPA) {
-    const int j = row[s];
-    const float3 dd = disp(ui, d.u[par][j], R.scale[0], R.scale[1], R.scale[2]);
+    const int j = jn;
+    jn = row[min(s + LPA, nn - 1)];   // the next slot, in flight during this one
+    // the neighbour's position, tangent and moments in one batch, read
+    // whatever the distance (entries beyond the cutoff are ignored)
+    const uint4 uj = d.u[par][j];
+    const float4 wj = w[j];
+    const float4* mj = d.mom + 3 * (size_t)j;
+    const float4* mdj = t.mdot + 3 * (size_t)j;
+    const float4 na = mj[0], nb = mj[1], nc = mj[2], da = mdj[0], db = mdj[1], dc = mdj[2];
+    asm volatile("" ::"v"(uj.x), "v"(wj.x), "v"(na.x), "v"(nb.x), "v"(nc.x), "v"(da.x), "v"(db.x), "v"(dc.x));
+    const float3 dd = disp(ui, uj, R.scale[0], R.scale[1], R.scale[2]);
     if (dd.x * dd.x + dd.y * dd.y + dd.z * dd.z < p.rc2) {
-      const Geo G = geometry(dd, sub3(w[j], wi), p);
+      const Geo G = geometry(dd, sub3(wj, wi), p);
       const D idr2 = G.idr * G.idr;
       const D e1 = ex2D(p.sig_l2e * G.idr);
       const D sr = p.sig * G.ir, s2 = sr * sr, s4 = s2 * s2;
       const D poly = (p.B * s4) - 1.f;
       const D dphi = p.Aeps * (e1 * ((-4.f * p.B) * (s4 * G.ir) - p.sig * (poly * idr2)));
       const D gg = (-p.gsig) * idr2;
-      const float4* mj = d.mom + 3 * (size_t)j;
-      const float4* mdj = t.mdot + 3 * (size_t)j;
-      const float4 na = mj[0], nb = mj[1], nc = mj[2], da = mdj[0], db = mdj[1], dc = mdj[2];
       const D Ts0 = Tm[0] + D{na.x, da.x}, Ts1 = Tm[1] + D{na.y, da.y}, Ts2 = Tm[2] + D{na.z, da.z};
       const D Ts3 = Tm[3] + D{na.w, da.w}, Ts4 = Tm[4] + D{nb.x, db.x}, Ts5 = Tm[5] + D{nb.y, db.y};
       const D Dv0 = Vm[0] - D{nb.z, db.z}, Dv1 = Vm[1] - D{nb.w, db.w}, Dv2 = Vm[2] - D{nc.x, dc.x};
