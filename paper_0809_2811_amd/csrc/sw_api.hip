@@ -142,6 +142,8 @@ hipError_t alloc_all(sw_ctx* c) {
   c->d.npad = c->npad;
   c->d.ctot = c->ctot;
   c->d.R = c->R;
+  c->d.max_rep_pad = 0;
+  for (const RepInfo& R : c->reps) c->d.max_rep_pad = std::max(c->d.max_rep_pad, R.ipad_end - R.ioff);
   if ((e = hipMemcpy(c->d_reps, c->reps.data(), sizeof(RepInfo) * c->R, hipMemcpyHostToDevice)) != hipSuccess) return e;
   if ((e = hipMemcpy(c->d_tile_rep, c->tile_rep.data(), sizeof(int) * c->tile_rep.size(), hipMemcpyHostToDevice)) != hipSuccess) return e;
   if ((e = hipMemcpy(c->d_uoff, c->uoff.data(), sizeof(long long) * (c->R + 1), hipMemcpyHostToDevice)) != hipSuccess) return e;
@@ -297,7 +299,7 @@ hipError_t enqueue_step(sw_ctx* c, const Phys& ph, int lpa, int t, int nsteps, i
     if ((e = launch_forces(c->d, ph, lpa, mode, rec, par, row, s, tm_f)) != hipSuccess) return e;
   } else {
     if ((e = launch_forces(c->d, ph, lpa, MODE_KICK, rec, par, row, s, tm_f)) != hipSuccess) return e;
-    if ((e = launch_thermostat(c->d, ph, par, t == nsteps, s)) != hipSuccess) return e;
+    if ((e = launch_thermostat(c->d, ph, lpa, par, t == nsteps, s)) != hipSuccess) return e;
   }
   return hipSuccess;
 }

@@ -88,6 +88,7 @@ struct Dev {
   const float2* npt_kick;  // [R] (a, b) of the isobaric half kick v <- a v + b F
   double* lref;        // [R] box edge 0 at the replica's last row build
   int npad, cap, cc, ctot, R;
+  int max_rep_pad;     // largest padded replica size (atoms)
 };
 
 // Per-call physical constants, pre-folded for the kernels.
@@ -139,17 +140,21 @@ struct NptArgs {
   double tauT, tauP, rl, rc, dt, c_m;
   int chain;             // chain length 1..kNptChain
   int apb;               // atoms per block of the force launch: replicas of at most
-                         // kNptFusedBlocks such blocks sum its block partials here,
+                         // kFusedBlocks such blocks sum its block partials here,
                          // larger ones read the reduction launch's thermo_cur
   int mode;              // NPT_BEGIN / NPT_STEP / NPT_END
   int par;               // parity of the positions this launch reads
   double* row;           // [R][kNptRow] record of the step closed here, or null
 };
 constexpr int kNptRow = 11;
-// Largest count of force blocks per replica whose partials the isobaric kick
-// sums in every wave of the replica (the work grows with the square of the
-// replica size; larger replicas take their sums from a reduction launch).
-constexpr int kNptFusedBlocks = 512;
+// Largest count of force blocks per replica whose partials the kernel after
+// the force launch (isobaric kick, thermostat) sums in every wave of the
+// replica (the work grows with the square of the replica size; larger
+// replicas take their sums from a reduction launch).
+constexpr int kFusedBlocks = 512;
+// Whether some replica of d is too large for those in-kernel sums at apb
+// atoms per force block.
+inline bool needs_reduce_launch(const Dev& d, int apb) { return d.max_rep_pad / apb > kFusedBlocks; }
 
 // Optional start/stop events recorded at a launch's dispatch.
 struct KTimer {
@@ -166,7 +171,7 @@ hipError_t launch_moments(const Dev& d, const Phys& p, int lpa, int par, int for
                           int energy, hipStream_t s, const KTimer& tm = KTimer());
 hipError_t launch_forces(const Dev& d, const Phys& p, int lpa, int mode, int vir, int par,
                          double* ring_row, hipStream_t s, const KTimer& tm = KTimer());
-hipError_t launch_thermostat(const Dev& d, const Phys& p, int par, int last, hipStream_t s);
+hipError_t launch_thermostat(const Dev& d, const Phys& p, int lpa, int par, int last, hipStream_t s);
 hipError_t launch_scatter_out(const Dev& d, int par, float4* x_user, float4* v_user,
                               float4* f_user, hipStream_t s);
 hipError_t launch_copy_thermo(const Dev& d, double* energy, double* virial, hipStream_t s);

@@ -735,34 +735,82 @@ __global__ __launch_bounds__(kBlock) void k_reduce_thermo(Dev d, int apb, double
   for (int task = blockIdx.x; task < d.R * kNQ; task += gridDim.x) reduce_task(d, apb, ring_row, task);
 }
 
+// Sums over replica R of the force launch's block partials of quantities
+// ks[0..nk) (nk <= 4), for a replica of at most kFusedBlocks blocks of apb
+// atoms.  Every wave of the replica takes them in one fixed order: one
+// batch of loads, lane-strided sums, then a butterfly, which leaves the same
+// bits in every lane, so all waves of the replica hold identical totals.
+// All 64 lanes of the wave must call it.
+__device__ __forceinline__ void replica_sums(const Dev& d, int apb, const RepInfo& R, const int (&ks)[4], int nk,
+                                             double* out) {
+  constexpr int kJ = kFusedBlocks / 64;
+  const int lane = threadIdx.x & 63;
+  const int nbt = d.npad / apb, b0 = R.ioff / apb, b1 = R.ipad_end / apb;
+  double x[4][kJ];
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+#pragma unroll
+    for (int j = 0; j < kJ; ++j)
+      x[q][j] = q < nk ? d.partial[(size_t)ks[q] * nbt + min(b0 + lane + 64 * j, b1 - 1)] : 0.0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    double acc = 0.0;
+#pragma unroll
+    for (int j = 0; j < kJ; ++j)
+      if (b0 + lane + 64 * j < b1) acc += x[q][j];
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+    if (q < nk) out[ks[q]] = acc;
+  }
+}
+
+__device__ __forceinline__ bool fused_sums(const RepInfo& R, int apb) {
+  return (R.ipad_end - R.ioff) / apb <= kFusedBlocks;
+}
+
 // Thermostat on the full-step velocities, then (unless last) the next
 // half-kick and drift.
-__device__ __forceinline__ void thermostat_atom(const Dev& d, const Phys& p, int par, int last, int i) {
+// The kinetic energy comes from the force launch's partials (summed here
+// for replicas of at most kFusedBlocks force blocks of apb atoms, else from
+// the reduction launch).  All 64 lanes of a wave call it together.
+__device__ __forceinline__ void thermostat_atom(const Dev& d, const Phys& p, int par, int last, int i, int apb) {
   if (i < d.npad) {
-    const int rep = d.tile_rep[i >> 6];
+    // the atom's records before the replica lookup (padded arrays), pinned
+    // so their round trip overlaps it
+    const float4 vi = d.v[i], Fi = d.f[i];
+    const uint4 ui = d.u[par][i], urefi = d.uref[i];
+    const int rep = __builtin_amdgcn_readfirstlane(d.tile_rep[i >> 6]);
+    asm volatile("" ::"v"(vi.x), "v"(Fi.x), "v"(ui.x), "v"(urefi.x));
     const RepInfo& R = d.reps[rep];
+    double ke;
+    if (fused_sums(R, apb)) {
+      const int ks[4] = {2, 2, 2, 2};
+      double th[kNQ];
+      replica_sums(d, apb, R, ks, 1, th);
+      ke = th[2];
+    } else {
+      ke = d.thermo_cur[rep * kNQ + 2];
+    }
     if (i < R.iend) {
-      const double T = 2.0 * d.thermo_cur[rep * kNQ + 2] / R.ndof_kb;
+      const double T = 2.0 * ke / R.ndof_kb;
       const double T0 = d.T0[rep];
       double s = 1.0;
       if (T > 0.0) {
         s = p.thermostat == 1 ? sqrt(T0 / T) : sqrt(fmax(0.0, 1.0 + p.dt_d / p.tau_d * (T0 / T - 1.0)));
       }
-      float4 v = d.v[i];
+      float4 v = vi;
       const float sf = (float)s;
       v.x *= sf; v.y *= sf; v.z *= sf;
       if (!last) {
-        const float4 F = d.f[i];
-        v.x += p.hdt_cm * F.x; v.y += p.hdt_cm * F.y; v.z += p.hdt_cm * F.z;
-        drift_bin(d, geo_of(R), rep, i, d.u[par][i], v, d.uref[i], p.dt, p.half_skin, par ^ 1);
+        v.x += p.hdt_cm * Fi.x; v.y += p.hdt_cm * Fi.y; v.z += p.hdt_cm * Fi.z;
+        drift_bin(d, geo_of(R), rep, i, ui, v, urefi, p.dt, p.half_skin, par ^ 1);
       }
       d.v[i] = v;
     }
   }
 }
 
-__global__ __launch_bounds__(kBlock) void k_thermostat(Dev d, Phys p, int par, int last) {
-  thermostat_atom(d, p, par, last, blockIdx.x * kBlock + threadIdx.x);
+__global__ __launch_bounds__(kBlock) void k_thermostat(Dev d, Phys p, int par, int last, int apb) {
+  thermostat_atom(d, p, par, last, blockIdx.x * kBlock + threadIdx.x, apb);
 }
 
 // ----------------------------------------------------------------- isobaric
@@ -867,42 +915,18 @@ __global__ __launch_bounds__(kBlock) void k_npt_kick(Dev d, Phys p, NptArgs a) {
   constexpr bool baro = BARO;                // no barostat: fixed box (NVT)
   double th[kNQ];
   const bool rec_wave = a.row && (a.mode & NPT_END) && (i >> 6) == (R.ioff >> 6);
-  if ((R.ipad_end - R.ioff) / a.apb <= kNptFusedBlocks) {
-    // The replica's sums of the force launch's block partials, taken by
-    // every wave of the replica in one fixed order (lane-strided, then a
-    // butterfly, which leaves the same bits in every lane), so all waves
-    // hold identical totals.  The choice depends on the replica alone, so
-    // a replica's arithmetic is the same whatever shares its context.  The
-    // step needs the kinetic and virial sums (2..5); the wave that writes
-    // a record also sums the energies and the tensor diagonal.
-    const int lane = threadIdx.x & 63;
-    const int nbt = d.npad / a.apb, b0 = R.ioff / a.apb, b1 = R.ipad_end / a.apb;
-    constexpr int kJ = kNptFusedBlocks / 64;
-    // one batch of loads for a group of quantities, then the sums
-    auto sum_group = [&](const int* ks, int nk, double* out) {
-      double x[4][kJ];
-#pragma unroll
-      for (int q = 0; q < 4; ++q)
-#pragma unroll
-        for (int j = 0; j < kJ; ++j)
-          x[q][j] = q < nk ? d.partial[(size_t)ks[q] * nbt + min(b0 + lane + 64 * j, b1 - 1)] : 0.0;
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        double acc = 0.0;
-#pragma unroll
-        for (int j = 0; j < kJ; ++j)
-          if (b0 + lane + 64 * j < b1) acc += x[q][j];
-        for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
-        if (q < nk) out[ks[q]] = acc;
-      }
-    };
+  if (fused_sums(R, a.apb)) {
+    // The step needs the kinetic and virial sums (2..5); the wave that
+    // writes a record also sums the energies and the tensor diagonal.  The
+    // choice of in-kernel sums depends on the replica alone, so a replica's
+    // arithmetic is the same whatever shares its context.
 #pragma unroll
     for (int k = 0; k < kNQ; ++k) th[k] = 0.0;
     const int kin[4] = {2, 3, 4, 5}, rec1[4] = {0, 1, 9, 10}, rec2[4] = {11, 11, 11, 11};
-    sum_group(kin, 4, th);
+    replica_sums(d, a.apb, R, kin, 4, th);
     if (rec_wave) {
-      sum_group(rec1, 4, th);
-      sum_group(rec2, 1, th);
+      replica_sums(d, a.apb, R, rec1, 4, th);
+      replica_sums(d, a.apb, R, rec2, 1, th);
     }
   } else {
 #pragma unroll
@@ -1060,7 +1084,7 @@ __global__ __launch_bounds__(kBlock) void k_persistent(Dev d, Phys p, PArgs a) {
       if (!grid_sync(a, G, k)) return;
     }
     if (thermostat) {
-      for (int b = alo; b < ahi; ++b) thermostat_atom(d, p, par, last, b * kBlock + threadIdx.x);
+      for (int b = alo; b < ahi; ++b) thermostat_atom(d, p, par, last, b * kBlock + threadIdx.x, APB);
       if (!grid_sync(a, G, k)) return;
     }
   }
@@ -1153,7 +1177,8 @@ hipError_t forces_mode(const Dev& d, const Phys& p, int vir, int par, double* ri
     hipExtLaunchKernelGGL((k_forces<LPA, MODE, false>), dim3(grid), dim3(kBlock), 0u, s, tm.start, tm.stop, 0u, d,
                           p, par);
   }
-  if (reduce && (vir || MODE == MODE_KICK))
+  // the kick is followed by the thermostat launch, which sums small replicas itself
+  if (reduce && (vir || (MODE == MODE_KICK && needs_reduce_launch(d, APB))))
     hipLaunchKernelGGL(k_reduce_thermo, dim3((unsigned)min(d.R * kNQ, 4096)), dim3(kBlock), 0, s, d, APB, ring_row);
   return hipGetLastError();
 }
@@ -1262,8 +1287,8 @@ hipError_t launch_forces(const Dev& d, const Phys& p, int lpa, int mode, int vir
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_thermostat(const Dev& d, const Phys& p, int par, int last, hipStream_t s) {
-  hipLaunchKernelGGL(k_thermostat, dim3(nblk(d.npad, kBlock)), dim3(kBlock), 0, s, d, p, par, last);
+hipError_t launch_thermostat(const Dev& d, const Phys& p, int lpa, int par, int last, hipStream_t s) {
+  hipLaunchKernelGGL(k_thermostat, dim3(nblk(d.npad, kBlock)), dim3(kBlock), 0, s, d, p, par, last, kBlock / lpa);
   return hipGetLastError();
 }
 

@@ -110,10 +110,7 @@ int sw_npt(sw_ctx* ctx, float* x, float* v, float* f, const sw_params* params, d
   // small replicas: the kick launch sums the force blocks' partials itself;
   // the force launches add a reduction launch only if some replica is larger
   const int apb = kBlock / lpa;
-  int max_blocks = 0;
-  for (int r = 0; r < ctx->R; ++r)
-    max_blocks = std::max(max_blocks, (ctx->reps[r].ipad_end - ctx->reps[r].ioff) / apb);
-  const int sums = max_blocks > kNptFusedBlocks ? 1 : 0;
+  const int sums = needs_reduce_launch(ctx->d, apb) ? 1 : 0;
   double margin = kGridMargin;
   set_boxes(ctx, start);
   if (!grid_fits(ctx, 0.5 * margin) && (st = regrid(ctx, margin)) != SW_OK) return st;
