@@ -41,6 +41,15 @@ __device__ __forceinline__ Geo geo_of(const RepInfo& R) {
              R.nc[0], R.nc[1], R.nc[2], R.cell_off};
 }
 
+// One of the two parity buffers of a device view.  A select of the two
+// pointers, not an index: indexing the by-value kernel argument with a
+// run-time parity becomes a scalar load that waits for the parity's own
+// load, one more round trip at every kernel start.
+template <class T>
+__device__ __forceinline__ T pick(T const (&a)[2], int k) {
+  return k ? a[1] : a[0];
+}
+
 // Drift by tx*v in fraction units (tx = dt, or its isobaric equivalent),
 // bin into grid `gp`, and raise the replica's rebuild flag if the atom is now
 // more than hs (half the effective skin) away from its row-build position.
@@ -57,11 +66,11 @@ __device__ __forceinline__ void drift_bin(const Dev& d, const Geo& G, int rep, i
   u.z += (unsigned)__float2int_rn(fminf(fmaxf(mz, -lim), lim));
   const float3 dd = disp(uref, u, G.sc0, G.sc1, G.sc2);
   const bool moved = dd.x * dd.x + dd.y * dd.y + dd.z * dd.z > hs * hs;
-  d.u[gp][i] = u;
+  pick(d.u, gp)[i] = u;
   const int c = G.cell_off + cell_of(u, G.nc0, G.nc1, G.nc2);
-  const int slot = atomicAdd(&d.gcnt[gp][c], 1);
+  const int slot = atomicAdd(&pick(d.gcnt, gp)[c], 1);
   if (moved) d.dflag[gp * d.R + rep] = 1;
-  if (slot < d.cc) d.gmem[gp][(size_t)c * d.cc + slot] = make_uint4(u.x, u.y, u.z, (unsigned)i);
+  if (slot < d.cc) pick(d.gmem, gp)[(size_t)c * d.cc + slot] = make_uint4(u.x, u.y, u.z, (unsigned)i);
   else atomicOr(&d.flags[F_CELL_OVER], 1);
 }
 
@@ -207,7 +216,7 @@ __global__ __launch_bounds__(kBlock) void k_bin(Dev d, int par, int check, float
 // block of a moments launch (or phase) takes a grid-stride share.
 __device__ __forceinline__ void clear_next(const Dev& d, int par, int b, int G) {
   for (int r = b * kBlock + threadIdx.x; r < d.R; r += G * kBlock) d.dflag[(par ^ 1) * d.R + r] = 0;
-  for (int c = b * kBlock + threadIdx.x; c < d.ctot; c += G * kBlock) d.gcnt[par ^ 1][c] = 0;
+  for (int c = b * kBlock + threadIdx.x; c < d.ctot; c += G * kBlock) pick(d.gcnt, par ^ 1)[c] = 0;
 }
 
 // lds: [APB][cap] candidates, [APB][cap] sorted, [APB] counts, [APB][56] cell
@@ -221,23 +230,27 @@ __device__ void moments_tile(const Dev& d, const Phys& p, int par, int force_reb
   constexpr int kMU = LPA >= 32 ? 1 : (32 / LPA < 4 ? 32 / LPA : 4);
   const int g = threadIdx.x / LPA, lane = threadIdx.x % LPA;
   const int i = bid * APB + g;
-  const int rep = d.tile_rep[(bid * APB) >> 6];
-  const RepInfo& R = d.reps[rep];
   // Every load that does not depend on another is issued up front, before
-  // the kernel's first store: geometry, own position, rebuild flag, row
-  // length and the first batch of row slots (slots below the capacity are
-  // always addressable; they are masked by the row length later).
+  // the kernel's first store: own position, row length and the first batch
+  // of row slots (slots below the capacity are always addressable; they are
+  // masked by the row length later; the atom arrays are padded to npad, so
+  // padding atoms read in bounds too), and the tile's replica (a per-lane
+  // load that joins the batch; a context of one replica needs none).  Then
+  // the replica's geometry and rebuild flag.
+  const int cap = d.cap;
+  const int* row = d.nl + (size_t)i * cap;
+  const uint4 ui = pick(d.u, par)[i];
+  int jn[kMU];
+#pragma unroll
+  for (int u = 0; u < kMU; ++u) jn[u] = row[min(lane + u * LPA, cap - 1)];
+  const int nn_all = d.nn[i];
+  const int rep = d.R == 1 ? 0 : __builtin_amdgcn_readfirstlane(d.tile_rep[i >> 6]);
+  const RepInfo& R = d.reps[rep];
   const Geo G = geo_of(R);
   const int iend = R.iend, ioff = R.ioff;
   const float sc0 = G.sc0, sc1 = G.sc1, sc2 = G.sc2;
   const bool real = i < iend;
-  const uint4 ui = d.u[par][i];
-  const int cap = d.cap;
-  const int* row = d.nl + (size_t)i * cap;
-  int jn[kMU];
-#pragma unroll
-  for (int u = 0; u < kMU; ++u) jn[u] = row[min(lane + u * LPA, cap - 1)];
-  const int nn_row = real ? d.nn[i] : 0;
+  const int nn_row = real ? nn_all : 0;
   // each replica rebuilds on its own displacement record
   const bool rebuild = force_rebuild || d.dflag[par * d.R + rep] != 0;
   int nn = nn_row;
@@ -260,8 +273,8 @@ __device__ void moments_tile(const Dev& d, const Phys& p, int par, int force_reb
     const int cx = (int)__umulhi(ui.x, (unsigned)n0);
     const int cy = (int)__umulhi(ui.y, (unsigned)n1);
     const int cz = (int)__umulhi(ui.z, (unsigned)n2);
-    const int* gc = d.gcnt[par];
-    const uint4* gm = d.gmem[par];
+    const int* gc = pick(d.gcnt, par);
+    const uint4* gm = pick(d.gmem, par);
     const int ccap = d.cc;
     // Lane l owns the contiguous cells [l*CPL, (l+1)*CPL): their counts are
     // one batch of loads, and a shuffle scan over the group gives every
@@ -428,7 +441,7 @@ __device__ void moments_tile(const Dev& d, const Phys& p, int par, int force_reb
 
   float T0 = 0.f, T1 = 0.f, T2 = 0.f, T3 = 0.f, T4 = 0.f, T5 = 0.f;
   float V0 = 0.f, V1 = 0.f, V2 = 0.f, S = 0.f, P = 0.f, E2 = 0.f;
-  const uint4* upm = d.u[par];
+  const uint4* upm = pick(d.u, par);
   // pipelined like the force loop: a batch of slots' positions, then the
   // arithmetic, with the next batch's slots read in between
   for (int s0 = lane; s0 < nn; s0 += kMU * LPA) {
@@ -527,44 +540,44 @@ __device__ void forces_tile(const Dev& d, const Phys& p, int par, int bid) {
   constexpr int APB = kBlock / LPA;
   const int g = threadIdx.x / LPA, lane = threadIdx.x % LPA;
   const int i = bid * APB + g;
-  const int rep = d.tile_rep[(bid * APB) >> 6];
+  // Software pipelined.  Everything that does not depend on a previous load
+  // is issued first as one batch: own position, moments and row length, the
+  // first kFU row slots of every lane (read whatever the row length, since
+  // slots below the capacity are always addressable, and masked once it is
+  // known), the velocity and row-build position the integrator needs, and
+  // the tile's replica (a per-lane load, so it joins the batch; a context of
+  // one replica needs none).  The atom arrays are padded to npad, so these
+  // reads are in bounds for padding atoms too, whose values are masked.
+  // Then, per kFU slots, the neighbours' positions and moments are one batch
+  // of independent loads before any arithmetic.  The per-lane order of
+  // neighbours is the plain stride order.
+  constexpr int kFU = LPA >= 32 ? 1 : 2;   // a batch spans at most 32 slots (one row line)
+  const int cap = d.cap;
+  const int* row = d.nl + (size_t)i * cap;
+  const uint4* up = pick(d.u, par);
+  const uint4 ui = up[i];
+  const float4* m = d.mom + 3 * (size_t)i;
+  const float4 ma = m[0], mb = m[1], mc = m[2];
+  const int nn_row = d.nn[i];
+  int jn[kFU];
+#pragma unroll
+  for (int u = 0; u < kFU; ++u) jn[u] = row[min(lane + u * LPA, cap - 1)];
+  const float4 vi = MODE != MODE_FORCES ? d.v[i] : make_float4(0.f, 0.f, 0.f, 0.f);
+  const uint4 urefi = (MODE == MODE_START || MODE == MODE_NVE) ? d.uref[i] : make_uint4(0u, 0u, 0u, 0u);
+  const int rep = d.R == 1 ? 0 : __builtin_amdgcn_readfirstlane(d.tile_rep[i >> 6]);
   const RepInfo& R = d.reps[rep];
   const Geo G = geo_of(R);
   const float sc0 = G.sc0, sc1 = G.sc1, sc2 = G.sc2;
   const bool real = i < R.iend;
-  const uint4 ui = d.u[par][i];
   const float c0 = p.c0, c02 = p.c0 * p.c0;
 
   float Tm0 = 0.f, Tm1 = 0.f, Tm2 = 0.f, Tm3 = 0.f, Tm4 = 0.f, Tm5 = 0.f, Vm0 = 0.f, Vm1 = 0.f, Vm2 = 0.f,
         Sm = 0.f, E2i = 0.f, E3i = 0.f;
   int nn = 0;
-  const int* row = d.nl + (size_t)i * d.cap;
-  const uint4* up = d.u[par];
-  // Software pipelined.  Everything that does not depend on a previous load
-  // is issued first as one batch: own moments, row length, the first kFU
-  // row slots of every lane (read whatever the row length, since slots below
-  // the capacity are always addressable, and masked once it is known), and
-  // the velocity and row-build position the integrator needs.  Then, per
-  // kFU slots, the neighbours' positions and moments are one batch of
-  // independent loads before any arithmetic.  The per-lane order of
-  // neighbours is the plain stride order.
-  constexpr int kFU = LPA >= 32 ? 1 : 2;   // a batch spans at most 32 slots (one row line)
-  const int cap = d.cap;
-  int jn[kFU];
-#pragma unroll
-  for (int u = 0; u < kFU; ++u) jn[u] = row[min(lane + u * LPA, cap - 1)];
-  float4 vi = make_float4(0.f, 0.f, 0.f, 0.f);
-  uint4 urefi = make_uint4(0u, 0u, 0u, 0u);
   if (real) {
-    const float4* m = d.mom + 3 * (size_t)i;
-    const float4 a = m[0], b = m[1], c = m[2];
-    Tm0 = a.x; Tm1 = a.y; Tm2 = a.z; Tm3 = a.w; Tm4 = b.x; Tm5 = b.y;
-    Vm0 = b.z; Vm1 = b.w; Vm2 = c.x; Sm = c.y; E2i = c.z; E3i = c.w;
-    nn = d.nn[i];
-    if (MODE != MODE_FORCES && lane == 0) {
-      vi = d.v[i];
-      if (MODE == MODE_START || MODE == MODE_NVE) urefi = d.uref[i];
-    }
+    Tm0 = ma.x; Tm1 = ma.y; Tm2 = ma.z; Tm3 = ma.w; Tm4 = mb.x; Tm5 = mb.y;
+    Vm0 = mb.z; Vm1 = mb.w; Vm2 = mc.x; Sm = mc.y; E2i = mc.z; E3i = mc.w;
+    nn = nn_row;
   }
   float fx = 0.f, fy = 0.f, fz = 0.f;
   float w0 = 0.f, w1 = 0.f, w2 = 0.f, w3 = 0.f, w4 = 0.f, w5 = 0.f;
@@ -777,7 +790,7 @@ __device__ __forceinline__ void thermostat_atom(const Dev& d, const Phys& p, int
     // the atom's records before the replica lookup (padded arrays), pinned
     // so their round trip overlaps it
     const float4 vi = d.v[i], Fi = d.f[i];
-    const uint4 ui = d.u[par][i], urefi = d.uref[i];
+    const uint4 ui = pick(d.u, par)[i], urefi = d.uref[i];
     const int rep = __builtin_amdgcn_readfirstlane(d.tile_rep[i >> 6]);
     asm volatile("" ::"v"(vi.x), "v"(Fi.x), "v"(ui.x), "v"(urefi.x));
     const RepInfo& R = d.reps[rep];
@@ -900,7 +913,7 @@ __global__ __launch_bounds__(kBlock) void k_npt_kick(Dev d, Phys p, NptArgs a) {
   // here, so their round trip overlaps the replica lookup instead of
   // following the chain arithmetic.
   const float4 vi = d.v[i], Fi = d.f[i];
-  const uint4 ui = d.u[a.par][i], urefi = d.uref[i];
+  const uint4 ui = pick(d.u, a.par)[i], urefi = d.uref[i];
   // one wave is one tile of one replica: the replica's records load as scalars
   const int rep = __builtin_amdgcn_readfirstlane(d.tile_rep[i >> 6]);
   asm volatile("" ::"v"(vi.x), "v"(Fi.x), "v"(ui.x), "v"(urefi.x));
