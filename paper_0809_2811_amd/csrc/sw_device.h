@@ -44,6 +44,15 @@ static __device__ __forceinline__ float wave_max(float v) {
   return v;
 }
 
+// One of the two parity buffers of a device view.  A select of the two
+// pointers, not an index: indexing the by-value kernel argument with a
+// run-time parity becomes a scalar load that waits for the parity's own
+// load, one more round trip at every kernel start.
+template <class T>
+static __device__ __forceinline__ T pick(T const (&a)[2], int k) {
+  return k ? a[1] : a[0];
+}
+
 static __device__ __forceinline__ float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
 static __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 static __device__ __forceinline__ float ex2(float x) { return __builtin_amdgcn_exp2f(x); }

@@ -41,15 +41,6 @@ __device__ __forceinline__ Geo geo_of(const RepInfo& R) {
              R.nc[0], R.nc[1], R.nc[2], R.cell_off};
 }
 
-// One of the two parity buffers of a device view.  A select of the two
-// pointers, not an index: indexing the by-value kernel argument with a
-// run-time parity becomes a scalar load that waits for the parity's own
-// load, one more round trip at every kernel start.
-template <class T>
-__device__ __forceinline__ T pick(T const (&a)[2], int k) {
-  return k ? a[1] : a[0];
-}
-
 // Drift by tx*v in fraction units (tx = dt, or its isobaric equivalent),
 // bin into grid `gp`, and raise the replica's rebuild flag if the atom is now
 // more than hs (half the effective skin) away from its row-build position.
@@ -791,7 +782,7 @@ __device__ __forceinline__ void thermostat_atom(const Dev& d, const Phys& p, int
     // so their round trip overlaps it
     const float4 vi = d.v[i], Fi = d.f[i];
     const uint4 ui = pick(d.u, par)[i], urefi = d.uref[i];
-    const int rep = __builtin_amdgcn_readfirstlane(d.tile_rep[i >> 6]);
+    const int rep = d.R == 1 ? 0 : __builtin_amdgcn_readfirstlane(d.tile_rep[i >> 6]);
     asm volatile("" ::"v"(vi.x), "v"(Fi.x), "v"(ui.x), "v"(urefi.x));
     const RepInfo& R = d.reps[rep];
     double ke;
@@ -915,7 +906,7 @@ __global__ __launch_bounds__(kBlock) void k_npt_kick(Dev d, Phys p, NptArgs a) {
   const float4 vi = d.v[i], Fi = d.f[i];
   const uint4 ui = pick(d.u, a.par)[i], urefi = d.uref[i];
   // one wave is one tile of one replica: the replica's records load as scalars
-  const int rep = __builtin_amdgcn_readfirstlane(d.tile_rep[i >> 6]);
+  const int rep = d.R == 1 ? 0 : __builtin_amdgcn_readfirstlane(d.tile_rep[i >> 6]);
   asm volatile("" ::"v"(vi.x), "v"(Fi.x), "v"(ui.x), "v"(urefi.x));
   const RepInfo& R = d.reps[rep];
   NptState st = a.in[rep];

@@ -90,19 +90,20 @@ __global__ __launch_bounds__(kBlock) void k_tan_moments(Dev d, Tan t, Phys p, co
   // The atom's own records and its first row slot are loaded before the
   // replica is known (arrays are padded to npad: padding lanes read in
   // bounds and are masked), so they share one round trip with the lookup.
-  const uint4 ui = d.u[par][i];
+  const uint4 ui = pick(d.u, par)[i];
   const float4 wi = w[i];
   const int nn_row = d.nn[i];
   const int* row = d.nl + (size_t)i * d.cap;
   int jn = row[min(lane, d.cap - 1)];
-  const RepInfo& R = d.reps[d.tile_rep[(bid * APB) >> 6]];
+  const int rep = d.R == 1 ? 0 : __builtin_amdgcn_readfirstlane(d.tile_rep[i >> 6]);
+  const RepInfo& R = d.reps[rep];
   const bool real = i < R.iend;
   const int nn = real ? nn_row : 0;
   float T0 = 0.f, T1 = 0.f, T2 = 0.f, T3 = 0.f, T4 = 0.f, T5 = 0.f, V0 = 0.f, V1 = 0.f, V2 = 0.f, S = 0.f;
   for (int s = lane; s < nn; s += LPA) {
     const int j = jn;
     jn = row[min(s + LPA, nn - 1)];   // the next slot, in flight during this one
-    const uint4 uj = d.u[par][j];
+    const uint4 uj = pick(d.u, par)[j];
     const float4 wj = w[j];            // read whatever the distance: one batch with the position
     asm volatile("" ::"v"(uj.x), "v"(wj.x));
     const float3 dd = disp(ui, uj, R.scale[0], R.scale[1], R.scale[2]);
@@ -139,7 +140,7 @@ __global__ __launch_bounds__(kBlock) void k_tan_forces(Dev d, Tan t, Phys p, con
   const int i = bid * APB + g;
   // own records and the first row slot before the replica lookup (padded
   // arrays: padding lanes read in bounds and are masked)
-  const uint4 ui = d.u[par][i];
+  const uint4 ui = pick(d.u, par)[i];
   const float4 wi = w[i];
   const float4* m = d.mom + 3 * (size_t)i;
   const float4* md = t.mdot + 3 * (size_t)i;
@@ -147,7 +148,8 @@ __global__ __launch_bounds__(kBlock) void k_tan_forces(Dev d, Tan t, Phys p, con
   const int nn_row = d.nn[i];
   const int* row = d.nl + (size_t)i * d.cap;
   int jn = row[min(lane, d.cap - 1)];
-  const RepInfo& R = d.reps[d.tile_rep[(bid * APB) >> 6]];
+  const int rep = d.R == 1 ? 0 : __builtin_amdgcn_readfirstlane(d.tile_rep[i >> 6]);
+  const RepInfo& R = d.reps[rep];
   const bool real = i < R.iend;
   const float c0 = p.c0, c02 = p.c0 * p.c0;
   D Tm[6], Vm[3], Sm{0.f, 0.f};
@@ -169,7 +171,7 @@ __global__ __launch_bounds__(kBlock) void k_tan_forces(Dev d, Tan t, Phys p, con
     jn = row[min(s + LPA, nn - 1)];   // the next slot, in flight during this one
     // the neighbour's position, tangent and moments in one batch, read
     // whatever the distance (entries beyond the cutoff are ignored)
-    const uint4 uj = d.u[par][j];
+    const uint4 uj = pick(d.u, par)[j];
     const float4 wj = w[j];
     const float4* mj = d.mom + 3 * (size_t)j;
     const float4* mdj = t.mdot + 3 * (size_t)j;
