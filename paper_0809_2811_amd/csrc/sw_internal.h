@@ -212,6 +212,9 @@ struct Adj {
   float aU, a3;      // loss weights
   int S;             // trajectory steps (loss normalisation 1 / (n_r (S + 1)))
   int last;          // last frame: do not form the next direction
+  double coef_d;     // the frame weight coef_cm in double, applied to the w.F sums below
+  double* tacc;      // [kTQ][nblocks] per-block sums over the sweep's frames (w.F terms
+                     // weighted by coef_d); one reduction after the sweep
 };
 hipError_t launch_gather_vec(const Dev& d, const float4* user, float4* internal, hipStream_t s);
 hipError_t launch_scatter_vec(const Dev& d, const float4* internal, float4* user, hipStream_t s);

@@ -257,7 +257,13 @@ __global__ __launch_bounds__(kBlock) void k_tan_forces(Dev d, Tan t, Phys p, con
   if (threadIdx.x < kTQ) {
     double acc = 0.0;
     for (int k = 0; k < APB; ++k) acc += red[k * kTQ + threadIdx.x];
-    t.tpartial[(size_t)threadIdx.x * (d.npad / APB) + bid] = acc;
+    const size_t slot = (size_t)threadIdx.x * (d.npad / APB) + bid;
+    if (ADJ) {
+      // each block owns its slot: the frames of a sweep add up in frame order
+      a.tacc[slot] += (threadIdx.x >= 4 ? a.coef_d : 1.0) * acc;
+    } else {
+      t.tpartial[slot] = acc;
+    }
   }
 }
 
@@ -355,9 +361,12 @@ hipError_t tan_launch(const Dev& d, const Tan& t, const Phys& p, const float4* w
     hipLaunchKernelGGL((k_tan_moments<LPA>), dim3(grid), dim3(kBlock), 0, s, d, t, p, w, par);
   } else {
     Adj a = adj ? *adj : Adj{};
-    if (adj) hipLaunchKernelGGL((k_tan_forces<LPA, true>), dim3(grid), dim3(kBlock), 0, s, d, t, p, w, par, a);
-    else hipLaunchKernelGGL((k_tan_forces<LPA, false>), dim3(grid), dim3(kBlock), 0, s, d, t, p, w, par, a);
-    hipLaunchKernelGGL(k_reduce_tan, dim3((unsigned)std::min(d.R, 4096)), dim3(kBlock), 0, s, d, t, APB, pt);
+    if (adj) {   // an adjoint frame accumulates; the sweep reduces once at its end
+      hipLaunchKernelGGL((k_tan_forces<LPA, true>), dim3(grid), dim3(kBlock), 0, s, d, t, p, w, par, a);
+    } else {
+      hipLaunchKernelGGL((k_tan_forces<LPA, false>), dim3(grid), dim3(kBlock), 0, s, d, t, p, w, par, a);
+      hipLaunchKernelGGL(k_reduce_tan, dim3((unsigned)std::min(d.R, 4096)), dim3(kBlock), 0, s, d, t, APB, pt);
+    }
   }
   return hipGetLastError();
 }
@@ -375,7 +384,15 @@ hipError_t launch_tan_moments(const Dev& d, const Tan& t, const Phys& p, int lpa
   return hipErrorInvalidValue;
 }
 
-// Tangent forces, then the per-replica sums and the parameter terms of pt.
+// Per-replica sums of t.tpartial (block partials of a force launch at lpa
+// lanes per atom, or a sweep's accumulated sums) and the parameter terms of pt.
+hipError_t launch_tan_reduce(const Dev& d, const Tan& t, int lpa, const PTerm& pt, hipStream_t s) {
+  hipLaunchKernelGGL(k_reduce_tan, dim3((unsigned)std::min(d.R, 4096)), dim3(kBlock), 0, s, d, t, kBlock / lpa, pt);
+  return hipGetLastError();
+}
+
+// Tangent forces, then (outside an adjoint sweep) the per-replica sums and
+// the parameter terms of pt.
 hipError_t launch_tan_forces(const Dev& d, const Tan& t, const Phys& p, int lpa, const float4* w, int par,
                              const Adj* adj, const PTerm& pt, hipStream_t s) {
   switch (lpa) {
@@ -604,7 +621,7 @@ int sw_adjoint(sw_ctx* ctx, const float* x0, const float* v0, const sw_params* p
     uint4 *ck_u = nullptr, *ck_uref = nullptr, *fs_u = nullptr, *fs_cells = nullptr;
     float4 *ck_v = nullptr, *xb = nullptr, *vb[2] = {nullptr, nullptr};
     int *ck_nl = nullptr, *ck_nn = nullptr, *fs_cnt = nullptr;
-    double* thb = nullptr;
+    double *thb = nullptr, *tacc = nullptr;
     hipError_t e;
     const size_t nf = (size_t)K + 1;
     if ((e = B.get(&ck_u, np * nseg)) != hipSuccess || (e = B.get(&ck_v, np * nseg)) != hipSuccess ||
@@ -613,7 +630,8 @@ int sw_adjoint(sw_ctx* ctx, const float* x0, const float* v0, const sw_params* p
         (e = B.get(&fs_cnt, (size_t)ctx->ctot * nf)) != hipSuccess ||
         (e = B.get(&fs_cells, (size_t)ctx->ctot * ctx->cc * nf)) != hipSuccess ||
         (e = B.get(&xb, np)) != hipSuccess || (e = B.get(&vb[0], np)) != hipSuccess ||
-        (e = B.get(&vb[1], np)) != hipSuccess || (e = B.get(&thb, (size_t)ctx->R * 3)) != hipSuccess)
+        (e = B.get(&vb[1], np)) != hipSuccess || (e = B.get(&thb, (size_t)ctx->R * 3)) != hipSuccess ||
+        (e = B.get(&tacc, (np / kMinAPB + 1) * kTQ)) != hipSuccess)
       return e == hipErrorOutOfMemory ? SW_ENOMEM : fail_hip(ctx, e);
     const FrameStore fs{fs_u, fs_cnt, fs_cells};
     if ((e = reset_flags(ctx, s)) != hipSuccess) return fail_hip(ctx, e);
@@ -657,6 +675,8 @@ int sw_adjoint(sw_ctx* ctx, const float* x0, const float* v0, const sw_params* p
     if ((e = launch_gather_vec(ctx->d, (const float4*)vbar_S, vb[0], s)) != hipSuccess) return fail_hip(ctx, e);
     if ((e = launch_fill_f64(thb, 0.0, 3 * (long long)ctx->R, s)) != hipSuccess) return fail_hip(ctx, e);
     if ((e = launch_fill_f64(loss, 0.0, ctx->R, s)) != hipSuccess) return fail_hip(ctx, e);
+    if ((e = launch_fill_f64(tacc, 0.0, (long long)(np / kMinAPB + 1) * kTQ, s)) != hipSuccess)
+      return fail_hip(ctx, e);
     for (int j = nseg - 1; j >= 0; --j) {
       const int c = j * K, len = std::min(K, S - c);
       if (j < nseg - 1) {   // recompute the segment into the frame store
@@ -671,12 +691,17 @@ int sw_adjoint(sw_ctx* ctx, const float* x0, const float* v0, const sw_params* p
         dv.gcnt[0] = fs.cnt + (size_t)k * ctx->ctot;
         dv.gmem[0] = fs.cells + (size_t)k * ctx->ctot * ctx->cc;
         const double coef = (sf == S || sf == 0) ? 0.5 * dt : dt;
-        const Adj a{xb, vb[cur ^ 1], (float)(coef * c_m), (float)dt, (float)aU, (float)a3, S, sf == 0};
-        const PTerm pt{params->lambda, params->epsilon, params->sigma, nullptr, nullptr, thb, loss,
-                       coef * c_m, aU, a3, S};
-        if ((e = tangent_frame(ctx, dv, ph, lpa, vb[cur], &a, pt, s)) != hipSuccess) return fail_hip(ctx, e);
+        const Adj a{xb, vb[cur ^ 1], (float)(coef * c_m), (float)dt, (float)aU, (float)a3, S, sf == 0,
+                    coef * c_m, tacc};
+        if ((e = tangent_frame(ctx, dv, ph, lpa, vb[cur], &a, PTerm{}, s)) != hipSuccess) return fail_hip(ctx, e);
         if (sf > 0) cur ^= 1;
       }
+    }
+    {   // parameter adjoint and loss from the sums of all frames (weights already applied)
+      Tan tr = ctx->t;
+      tr.tpartial = tacc;
+      const PTerm pt{params->lambda, params->epsilon, params->sigma, nullptr, nullptr, thb, loss, 1.0, aU, a3, S};
+      if ((e = launch_tan_reduce(ctx->d, tr, lpa, pt, s)) != hipSuccess) return fail_hip(ctx, e);
     }
     if ((e = launch_scatter_vec(ctx->d, xb, (float4*)xbar0, s)) != hipSuccess) return fail_hip(ctx, e);
     if ((e = launch_scatter_vec(ctx->d, vb[cur], (float4*)vbar0, s)) != hipSuccess) return fail_hip(ctx, e);
