@@ -107,6 +107,23 @@ def test_berendsen_matches_oracle():
     assert np.abs(thg[:, 2] - tho[:, 2]).max() < 1e-5 * tho[:, 2].max()
 
 
+@pytest.mark.parametrize("reps,lpa,every", [(1, 8, 4), (2, 64, 1), (2, 64, 4)])
+def test_berendsen_kinetic_sums_match_oracle(reps, lpa, every):
+    """The thermostat's kinetic energy comes from the kernel's own sums (a
+    512-atom replica: 16 force blocks) or, for a 4096-atom replica at 64 lanes
+    per atom (1024 blocks), from the reduction launch; steps between thermo
+    records run without that launch."""
+    from paper_0809_2811_amd import sw
+    x, v, L = liquid(reps)
+    x, v = f32(x), f32(v)
+    xg, vg, _, thg, _ = run_gpu(x, v, L, 8, lpa=lpa, thermo_every=every, thermostat=sw.SW_BERENDSEN, T0=350.0,
+                                tau_fs=150.0)
+    xo, vo, _, tho = oracle.vv(x, v, L, 8, dt=10.0, thermostat=2, T0=350.0, tau=150.0)
+    assert np.abs(vg - vo).max() < 1e-4 * np.abs(vo).max()
+    assert np.abs(min_image(xg - xo, L)).max() < 1e-4
+    assert np.abs(thg[:, 2] - tho[every - 1::every, 2]).max() < 1e-5 * tho[:, 2].max()
+
+
 def test_step_is_deterministic():
     x, v, L = liquid(2)
     a = run_gpu(f32(x), f32(v), L, 50, thermo_every=10)
