@@ -431,8 +431,9 @@ def bench_npt(plain_ms_per_step, steps=5000, warm=1000):
         x = torch.from_numpy(synth.to_float4(np.concatenate([x0] * R))).cuda()
         v = torch.from_numpy(synth.to_float4(np.concatenate([v0] * R))).cuda()
         lpa = tune.best(R * n, 1.0, 1.0)["lanes_per_atom"]
+        # captured 50-step blocks: faster for isobaric steps at both sizes (16.9 vs 17.8 us, 37.4 vs 37.9 us)
         ctx = sw.Context(np.arange(R + 1) * n, [L0] * R, cutoff=RC, skin=1.0, nbr_capacity=48,
-                         tuning=dict(lanes_per_atom=lpa))
+                         tuning=dict(lanes_per_atom=lpa, graph_steps=50))
         ctx.npt(x, v, warm, T0=temps, reset=True)
         sync()
         t0 = time.perf_counter()

@@ -466,6 +466,9 @@ void sw_destroy(sw_ctx* ctx) {
   if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
   if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
   if (ctx->ring) (void)hipFree(ctx->ring);
+  if (ctx->npt_gexec) (void)hipGraphExecDestroy(ctx->npt_gexec);
+  if (ctx->npt_graph) (void)hipGraphDestroy(ctx->npt_graph);
+  if (ctx->npt_ring) (void)hipFree(ctx->npt_ring);
   free_list(ctx, ctx->grow_allocs);
   free_list(ctx, ctx->allocs);
   delete ctx;

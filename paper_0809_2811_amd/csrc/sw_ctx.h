@@ -62,6 +62,12 @@ struct sw_ctx {
   float2* d_kick = nullptr;        // [R] isobaric kick coefficients (Dev::npt_kick)
   std::vector<swk::NptState> npt;  // host copy between calls
   bool npt_ready = false;
+  // captured block of isobaric steps (graph_steps > 0; shares cap_stream)
+  hipGraph_t npt_graph = nullptr;
+  hipGraphExec_t npt_gexec = nullptr;
+  std::vector<unsigned char> npt_gkey;
+  double* npt_ring = nullptr;      // records of one captured block
+  size_t npt_ring_rows = 0;
 };
 
 

@@ -82,6 +82,66 @@ bool grid_fits(const sw_ctx* c, double margin) {
   return true;
 }
 
+// One isobaric step t >= 2 (kick closing t-1 and opening t, moments, forces)
+// with the launch arguments that depend on t; row_prev is the record of step
+// t-1 or null, rec asks the moments launch for the energies of step t.
+hipError_t enqueue_npt_step(sw_ctx* c, const Phys& ph, int lpa, int sums, NptArgs a, int t, double* row_prev, bool rec,
+                            hipStream_t s) {
+  a.in = c->d_npt + (size_t)((t - 1) & 1) * c->R;
+  a.out = c->d_npt + (size_t)(t & 1) * c->R;
+  a.mode = t == 1 ? NPT_BEGIN : NPT_STEP;
+  a.par = (t - 1) & 1;
+  a.row = row_prev;
+  hipError_t e;
+  if ((e = launch_npt_kick(c->d, ph, a, s)) != hipSuccess) return e;
+  if ((e = launch_moments(c->d, ph, lpa, t & 1, 0, rec ? 1 : 0, s)) != hipSuccess) return e;
+  return launch_forces(c->d, ph, lpa, MODE_NPT, sums, t & 1, nullptr, s);
+}
+
+// Captures steps 2 .. K+1 (K a multiple of 2 and of the record interval, so
+// every later block t0+1 .. t0+K with t0 = 1 + b K has the same launch
+// arguments) into a graph, records going to a ring of K / every rows,
+// unless the cached graph matches.
+hipError_t ensure_npt_graph(sw_ctx* c, const Phys& ph, int lpa, int sums, const NptArgs& tmpl, int K, int every) {
+  std::vector<unsigned char> key(sizeof(Dev) + sizeof(Phys) + sizeof(NptArgs) + 5 * sizeof(int));
+  const int meta[5] = {K, every, lpa, sums, c->alloc_gen};
+  unsigned char* k = key.data();
+  std::memcpy(k, &c->d, sizeof(Dev)); k += sizeof(Dev);
+  std::memcpy(k, &ph, sizeof(Phys)); k += sizeof(Phys);
+  std::memcpy(k, &tmpl, sizeof(NptArgs)); k += sizeof(NptArgs);
+  std::memcpy(k, meta, sizeof meta);
+  if (c->npt_gexec && key == c->npt_gkey) return hipSuccess;
+  hipError_t e;
+  if (c->npt_gexec) { (void)hipGraphExecDestroy(c->npt_gexec); c->npt_gexec = nullptr; }
+  if (c->npt_graph) { (void)hipGraphDestroy(c->npt_graph); c->npt_graph = nullptr; }
+  c->npt_gkey.clear();
+  if (!c->cap_stream && (e = hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking)) != hipSuccess) return e;
+  const size_t rows = every > 0 ? (size_t)(K / every) : 0;
+  const size_t rowsz = (size_t)c->R * kNptRow;
+  if (rows > c->npt_ring_rows) {
+    if (c->npt_ring) (void)hipFree(c->npt_ring);
+    c->npt_ring = nullptr;
+    c->npt_ring_rows = 0;
+    if ((e = hipMalloc((void**)&c->npt_ring, rows * rowsz * sizeof(double))) != hipSuccess) return e;
+    c->npt_ring_rows = rows;
+  }
+  if ((e = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal)) != hipSuccess) return e;
+  hipError_t le = hipSuccess;
+  for (int l = 1; l <= K && le == hipSuccess; ++l) {
+    const int t = 1 + l;   // stands for t0 + l; steps l = t-1 with l % every == 0 are recorded
+    double* row_prev = every > 0 && l % every == 0 ? c->npt_ring + (size_t)(l / every - 1) * rowsz : nullptr;
+    le = enqueue_npt_step(c, ph, lpa, sums, tmpl, t, row_prev, every > 0 && t % every == 0, c->cap_stream);
+  }
+  hipGraph_t g = nullptr;
+  e = hipStreamEndCapture(c->cap_stream, &g);
+  if (le != hipSuccess) { if (g) (void)hipGraphDestroy(g); return le; }
+  if (e != hipSuccess) return e;
+  c->npt_graph = g;
+  if ((e = hipGraphInstantiate(&c->npt_gexec, g, nullptr, nullptr, 0)) != hipSuccess) return e;
+  c->npt_gkey = key;
+  return hipSuccess;
+}
+
 }  // namespace
 
 extern "C" {
@@ -149,18 +209,41 @@ int sw_npt(sw_ctx* ctx, float* x, float* v, float* f, const sw_params* params, d
     auto row_of = [&](int step) -> double* {   // record of 1-based step, or null
       return rows && step > 0 && step % every == 0 ? rows + (size_t)(step / every - 1) * rowsz : nullptr;
     };
-    for (int t = 1; t <= nsteps; ++t) {
-      a.in = ctx->d_npt + (size_t)((t - 1) & 1) * ctx->R;
-      a.out = ctx->d_npt + (size_t)(t & 1) * ctx->R;
-      a.mode = t == 1 ? NPT_BEGIN : NPT_STEP;
-      a.par = (t - 1) & 1;
-      a.row = row_of(t - 1);
-      if ((e = launch_npt_kick(ctx->d, ph, a, s)) != hipSuccess) return fail_hip(ctx, e);
-      const int rec = row_of(t) != nullptr;
-      if ((e = launch_moments(ctx->d, ph, lpa, t & 1, 0, rec, s)) != hipSuccess) return fail_hip(ctx, e);
-      if ((e = launch_forces(ctx->d, ph, lpa, MODE_NPT, sums, t & 1, nullptr, s)) != hipSuccess)
+    // step 1 opens the trajectory; then captured blocks of K steps (t0 + 1 ..
+    // t0 + K, t0 = 1 + b K) where the tuning asks for them; then the rest
+    int t_next = 1;
+    if (nsteps >= 1) {
+      if ((e = enqueue_npt_step(ctx, ph, lpa, sums, a, 1, nullptr, row_of(1) != nullptr, s)) != hipSuccess)
         return fail_hip(ctx, e);
+      t_next = 2;
     }
+    if (ctx->tune.graph_steps > 0 && nsteps > 1) {
+      const int ev = rows ? every : 0;
+      long long period = 2;
+      if (ev > 0) {
+        long long x = period, y = ev;
+        while (y) { const long long r = x % y; x = y; y = r; }
+        period = period / x * ev;
+      }
+      const long long K = ((ctx->tune.graph_steps + period - 1) / period) * period;
+      const long long nblk = (nsteps - 1) / K;
+      if (nblk > 0 && K <= 1 << 20) {
+        if ((e = ensure_npt_graph(ctx, ph, lpa, sums, a, (int)K, ev)) != hipSuccess) return fail_hip(ctx, e);
+        for (long long b = 0; b < nblk; ++b) {
+          if ((e = hipGraphLaunch(ctx->npt_gexec, s)) != hipSuccess) return fail_hip(ctx, e);
+          if (ev > 0) {   // records of steps b K + ev .. (b + 1) K
+            const size_t nr = (size_t)(K / ev), first = (size_t)(b * K / ev);
+            if ((e = hipMemcpyAsync(rows + first * rowsz, ctx->npt_ring, nr * rowsz * sizeof(double),
+                                    hipMemcpyDeviceToDevice, s)) != hipSuccess)
+              return fail_hip(ctx, e);
+          }
+        }
+        t_next = (int)(1 + nblk * K + 1);
+      }
+    }
+    for (int t = t_next; t <= nsteps; ++t)
+      if ((e = enqueue_npt_step(ctx, ph, lpa, sums, a, t, row_of(t - 1), row_of(t) != nullptr, s)) != hipSuccess)
+        return fail_hip(ctx, e);
     if (nsteps > 0) {   // close the last step
       a.in = ctx->d_npt + (size_t)(nsteps & 1) * ctx->R;
       a.out = ctx->d_npt + (size_t)((nsteps + 1) & 1) * ctx->R;

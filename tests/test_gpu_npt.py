@@ -80,6 +80,30 @@ def test_npt_mixed_replica_sizes_are_independent():
     assert np.array_equal(ctx.box[0], c1.box[0])
 
 
+@pytest.mark.parametrize("every,tau_P", [(0, 1000.0), (5, 1000.0), (4, 0.0)])
+def test_npt_graph_replays_equal_plain_launches(every, tau_P):
+    """Captured blocks of 10 isobaric steps (47 steps: step 1, four blocks and
+    a tail of 6; then a continued call of 23) give the same bits as one
+    launch sequence per step: positions, velocities, box, extended state and
+    records."""
+    from paper_0809_2811_amd import sw
+    tab = synth.replica_table(n_replicas=2)
+    off, boxes = tab["offsets"], tab["boxes"]
+    x, v = f32(tab["x"]), f32(tab["v"])
+    out = {}
+    for gs in (0, 10):
+        ctx = sw.Context(off, boxes, cutoff=RC, skin=1.0, nbr_capacity=64,
+                         tuning=dict(lanes_per_atom=8, graph_steps=gs))
+        xd, vd = to_dev(x), to_dev(v)
+        kw = dict(T0=[280.0, 310.0], p_bar=[0.0, 200.0], tau_T=500.0, tau_P=tau_P, every=every)
+        _, r1 = ctx.npt(xd, vd, 47, reset=True, **kw)
+        _, r2 = ctx.npt(xd, vd, 23, **kw)
+        rows = [] if every == 0 else [r1.cpu().numpy(), r2.cpu().numpy()]
+        out[gs] = [from_dev(xd), from_dev(vd), np.array(ctx.box), np.array(ctx.npt_state())] + rows
+    for a, b in zip(out[0], out[10]):
+        assert np.array_equal(a, b)
+
+
 def test_fixed_box_thermostat_matches_oracle():
     x, v, L = liquid(1, sigma=0.0)
     x, v = f32(x), f32(v)
