@@ -101,6 +101,33 @@ def test_benchmark_launch_configuration_matches_oracle():
         assert abs(a[3][0, k] - tho[99, k]) <= 1e-5 * etot, (k, a[3][0, k], tho[99, k])
 
 
+def test_large_box_launch_configuration_matches_oracle():
+    """262144 atoms (198.7 A box) in the benchmark's large-box launch form:
+    8 lanes per atom, 0.5 A skin, rows rebuilt at least every 10 steps,
+    captured blocks of 10 steps.  11 steps (one replayed block, then one
+    stream-launched step): every atom against the FP64 oracle, and the same
+    bits as plain launches."""
+    from paper_0809_2811_amd import sw
+    x, v, L = liquid(8)
+    x, v = f32(x), f32(v)
+    assert len(x) == 262144
+
+    def run(gs):
+        ctx = sw.Context([0, len(x)], [L], cutoff=RC, skin=0.5, nbr_capacity=48,
+                         tuning=dict(lanes_per_atom=8, graph_steps=gs, rebuild_every=10))
+        xd, vd = to_dev(x), to_dev(v)
+        f, _ = ctx.step(xd, vd, 11)
+        return from_dev(xd), from_dev(vd), from_dev(f)
+
+    xg, vg, fg = run(10)
+    for p, q in zip((xg, vg, fg), run(0)):
+        assert np.array_equal(p, q)
+    xo, vo, fo, _ = oracle.vv(x, v, L, 11, dt=10.0)
+    assert np.abs(min_image(xg - xo, L)).max() < 1e-4
+    assert np.abs(vg - vo).max() < 1e-4 * np.abs(vo).max()
+    assert force_error(fg, fo) < 1e-4
+
+
 def test_zero_steps_returns_forces():
     x, v, L = liquid(1, sigma=0.0)
     x, v = f32(x), f32(v)
