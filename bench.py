@@ -218,8 +218,8 @@ def main():
     ap.add_argument("--graph-steps", type=int, default=-1,
                     help="steps per captured block, 0 = stream launches (-1 = tuned); the launch form does not "
                          "change what a kernel launch reads or writes")
-    ap.add_argument("--forms", default="large,batched,adjoint,observables,npt",
-                    help="comma list of large,batched,adjoint,observables,npt or none")
+    ap.add_argument("--forms", default="large,share,batched,adjoint,observables,npt",
+                    help="comma list of large,share,batched,adjoint,observables,npt or none")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="first run a plain FP32 copy-like kernel (out = -in) over this many MiB, three times: "
@@ -271,6 +271,8 @@ def main():
     line["forms"] = {}
     if "large" in forms:
         line["forms"]["large_box"] = bench_large(graph_steps=args.graph_steps)
+    if "share" in forms:
+        line["forms"]["share"] = bench_share()
     if "batched" in forms:
         line["forms"]["batched"] = bench_batched()
     if "adjoint" in forms:
@@ -282,6 +284,29 @@ def main():
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline()
     print(json.dumps(line), flush=True)
+
+
+def bench_share(steps=1000, skin=0.5):
+    """One GPU's owned share of the large box decomposed over 8 GPUs (2x2x2
+    bricks): 32768 atoms (16^3 cells at 1.00 g/cm^3), the large box's
+    protocol (melt, 0.5 A skin, rows rebuilt at least every 10 steps).  A
+    periodic box stands in for the brick; its ghost shell (~10k atoms) and
+    the halo exchanges are not modelled."""
+    from paper_0809_2811_amd import synth, tune
+    cfg = synth.lattice_at_density(16, 1.0, sigma=0.05, temperature=400.0, seed=synth.SEED_CONFIG_BASE + 2)
+    cfg.update(melt_T=400.0, melt_steps=2000, T=298.0)
+    n = len(cfg["x"])
+    tuning = tune.best(n, 1.0, skin)
+    tuning.pop("skin", None)
+    tuning["rebuild_every"] = 10
+    ctx, x, v = prepare_liquid(cfg, skin, tuning)
+    ctx.step(x, v, 50)
+    res = timed_nve(ctx, x, v, steps)
+    return {"value": n * steps / res["seconds"], "unit": "atom-steps/s", "steps": steps,
+            "ms_per_step": res["seconds"] * 1e3 / steps, "n_atoms": n, "skin_A": skin,
+            "rebuilds": res["rebuilds"], "tuning": tuning,
+            "workload": "share: 32768 atoms (one GPU's owned brick of the 262144-atom box on 8 GPUs, as a periodic "
+                        "box), 298 K liquid, NVE dt=10 fs, 0.5 A skin, rows rebuilt at least every 10 steps"}
 
 
 def bench_large(steps=1000, skin=0.5, graph_steps=-1):
