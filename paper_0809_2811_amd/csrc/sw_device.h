@@ -57,4 +57,50 @@ static __device__ __forceinline__ float rsq(float x) { return __builtin_amdgcn_r
 static __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 static __device__ __forceinline__ float ex2(float x) { return __builtin_amdgcn_exp2f(x); }
 
+// Dual numbers (value, derivative along a tangent direction) and the leg
+// geometry of one neighbour in them: the tangent kernels' arithmetic.
+struct D {
+  float v, d;
+};
+static __device__ __forceinline__ D operator+(D a, D b) { return {a.v + b.v, a.d + b.d}; }
+static __device__ __forceinline__ D operator-(D a, D b) { return {a.v - b.v, a.d - b.d}; }
+static __device__ __forceinline__ D operator*(D a, D b) { return {a.v * b.v, a.d * b.v + a.v * b.d}; }
+static __device__ __forceinline__ D operator*(float s, D a) { return {s * a.v, s * a.d}; }
+static __device__ __forceinline__ D operator+(D a, float s) { return {a.v + s, a.d}; }
+static __device__ __forceinline__ D operator-(D a, float s) { return {a.v - s, a.d}; }
+static __device__ __forceinline__ D neg(D a) { return {-a.v, -a.d}; }
+static __device__ __forceinline__ D rsqD(D a) {
+  const float r = rsq(a.v);
+  return {r, -0.5f * r * r * r * a.d};
+}
+static __device__ __forceinline__ D rcpD(D a) {
+  const float r = rcp(a.v);
+  return {r, -r * r * a.d};
+}
+static __device__ __forceinline__ D ex2D(D a) {
+  const float e = ex2(a.v);
+  return {e, e * 0.69314718055994531f * a.d};
+}
+
+struct Leg {
+  D ux, uy, uz, r, ir, idr, eg;
+};
+
+// Leg geometry of one neighbour as dual numbers: difference dd, tangent dt.
+static __device__ __forceinline__ Leg leg_dual(const float3& dd, const float3& dt, const Phys& p) {
+  const D dx{dd.x, dt.x}, dy{dd.y, dt.y}, dz{dd.z, dt.z};
+  const D r2 = dx * dx + dy * dy + dz * dz;
+  Leg G;
+  G.ir = rsqD(r2);
+  G.r = r2 * G.ir;
+  G.ux = dx * G.ir; G.uy = dy * G.ir; G.uz = dz * G.ir;
+  G.idr = rcpD(G.r - p.rc);
+  G.eg = ex2D(p.gsig_l2e * G.idr);
+  return G;
+}
+
+static __device__ __forceinline__ float3 sub3(const float4& a, const float4& b) {
+  return make_float3(a.x - b.x, a.y - b.y, a.z - b.z);
+}
+
 }  // namespace swk

@@ -171,6 +171,10 @@ hipError_t launch_moments(const Dev& d, const Phys& p, int lpa, int par, int for
                           int energy, hipStream_t s, const KTimer& tm = KTimer());
 hipError_t launch_forces(const Dev& d, const Phys& p, int lpa, int mode, int vir, int par,
                          double* ring_row, hipStream_t s, const KTimer& tm = KTimer());
+// Moments with energies at parity 0 and, in the same launch, their tangent
+// along w (mdot [Npad][3]); rows rebuilt if forced or flagged.
+hipError_t launch_moments_tan(const Dev& d, const Phys& p, int lpa, int force_rebuild, const float4* w,
+                              float4* mdot, hipStream_t s);
 hipError_t launch_thermostat(const Dev& d, const Phys& p, int lpa, int par, int last, hipStream_t s);
 hipError_t launch_scatter_out(const Dev& d, int par, float4* x_user, float4* v_user,
                               float4* f_user, hipStream_t s);

@@ -213,8 +213,9 @@ __device__ __forceinline__ void clear_next(const Dev& d, int par, int b, int G) 
 // lds: [APB][cap] candidates, [APB][cap] sorted, [APB] counts, [APB][56] cell
 // prefix and ids; with 16 or more lanes per atom also [APB][cap] candidate
 // positions (16-byte aligned)
-template <int LPA, bool ENERGY>
-__device__ void moments_tile(const Dev& d, const Phys& p, int par, int force_rebuild, int bid, int* lds) {
+template <int LPA, bool ENERGY, bool TAN = false>
+__device__ void moments_tile(const Dev& d, const Phys& p, int par, int force_rebuild, int bid, int* lds,
+                             const float4* __restrict__ tw = nullptr, float4* __restrict__ tmd = nullptr) {
   constexpr int APB = kBlock / LPA;
   // row slots per lane per batch: a batch spans at most 32 slots, one
   // 128-byte line of the row
@@ -407,7 +408,7 @@ __device__ void moments_tile(const Dev& d, const Phys& p, int par, int force_reb
         const int vj = cand[k];
         int rank = 0;
         for (int q = 0; q < total; ++q) rank += cand[q] < vj;
-        srt[rank] = LPA >= 16 ? k : vj;
+        srt[rank] = (LPA >= 16 && !TAN) ? k : vj;
         d.nl[(size_t)i * cap + rank] = vj;
       }
       if (lane == 0) {
@@ -418,7 +419,7 @@ __device__ void moments_tile(const Dev& d, const Phys& p, int par, int force_reb
     __syncthreads();
     nn = real ? total : 0;
     row = srt;
-    if (LPA >= 16) {
+    if (LPA >= 16 && !TAN) {   // the tangent mode gathers by atom index (it also reads w[j])
       from_lds = true;
       lds_u = cand_u;
     }
@@ -432,6 +433,10 @@ __device__ void moments_tile(const Dev& d, const Phys& p, int par, int force_reb
 
   float T0 = 0.f, T1 = 0.f, T2 = 0.f, T3 = 0.f, T4 = 0.f, T5 = 0.f;
   float V0 = 0.f, V1 = 0.f, V2 = 0.f, S = 0.f, P = 0.f, E2 = 0.f;
+  // tangent mode: the moments' derivatives along the direction w as well
+  // (the dual-number arithmetic of the tangent kernels, same per-lane order)
+  float dT0 = 0.f, dT1 = 0.f, dT2 = 0.f, dT3 = 0.f, dT4 = 0.f, dT5 = 0.f, dV0 = 0.f, dV1 = 0.f, dV2 = 0.f, dS = 0.f;
+  const float4 wi = TAN ? tw[i] : make_float4(0.f, 0.f, 0.f, 0.f);
   const uint4* upm = pick(d.u, par);
   // pipelined like the force loop: a batch of slots' positions, then the
   // arithmetic, with the next batch's slots read in between
@@ -442,12 +447,15 @@ __device__ void moments_tile(const Dev& d, const Phys& p, int par, int force_reb
 #pragma unroll
     for (int u = 0; u < kMU; ++u) jn[u] = row[min(s0 + (kMU + u) * LPA, nn - 1)];
     uint4 uu[kMU];
+    float4 wu[kMU];
 #pragma unroll
     for (int u = 0; u < kMU; ++u) {
       uu[u] = ui;
+      wu[u] = wi;
       if (jj[u] >= 0) {
         if (from_lds) uu[u] = lds_u[jj[u]];
         else uu[u] = upm[jj[u]];
+        if (TAN) wu[u] = tw[jj[u]];
       }
     }
 #pragma unroll
@@ -468,6 +476,13 @@ __device__ void moments_tile(const Dev& d, const Phys& p, int par, int force_reb
           const float e1 = ex2(p.sig_l2e * idr);
           const float sr = p.sig * ir, s2 = sr * sr;
           E2 += 0.5f * p.Aeps * (p.B * s2 * s2 - 1.f) * e1;
+        }
+        if (TAN) {
+          const Leg L = leg_dual(dd, sub3(wu[u], wi), p);
+          const D dx = L.eg * L.ux, dy = L.eg * L.uy, dz = L.eg * L.uz;
+          dT0 += (dx * L.ux).d; dT1 += (dy * L.uy).d; dT2 += (dz * L.uz).d;
+          dT3 += (dx * L.uy).d; dT4 += (dx * L.uz).d; dT5 += (dy * L.uz).d;
+          dV0 += dx.d; dV1 += dy.d; dV2 += dz.d; dS += L.eg.d;
         }
       }
     }
@@ -490,6 +505,18 @@ __device__ void moments_tile(const Dev& d, const Phys& p, int par, int force_reb
     m[1] = make_float4(T4, T5, V0, V1);
     m[2] = make_float4(V2, S, E2, E3);
   }
+  if (TAN) {
+    dT0 = group_sum<LPA>(dT0); dT1 = group_sum<LPA>(dT1); dT2 = group_sum<LPA>(dT2);
+    dT3 = group_sum<LPA>(dT3); dT4 = group_sum<LPA>(dT4); dT5 = group_sum<LPA>(dT5);
+    dV0 = group_sum<LPA>(dV0); dV1 = group_sum<LPA>(dV1); dV2 = group_sum<LPA>(dV2);
+    dS = group_sum<LPA>(dS);
+    if (real && lane == 0) {
+      float4* m = tmd + 3 * (size_t)i;
+      m[0] = make_float4(dT0, dT1, dT2, dT3);
+      m[1] = make_float4(dT4, dT5, dV0, dV1);
+      m[2] = make_float4(dV2, dS, 0.f, 0.f);
+    }
+  }
 }
 
 template <int LPA, bool ENERGY>
@@ -497,6 +524,17 @@ __global__ __launch_bounds__(kBlock) void k_moments(Dev d, Phys p, int par, int 
   extern __shared__ int lds[];
   moments_tile<LPA, ENERGY>(d, p, par, force_rebuild, xcd_remap(blockIdx.x, gridDim.x), lds);
   clear_next(d, par, blockIdx.x, gridDim.x);
+}
+
+// Moments with energies and their tangent along w (positions of parity 0):
+// the primal moments of k_moments and the tangent moments of the tangent
+// pass in one launch.
+template <int LPA>
+__global__ __launch_bounds__(kBlock) void k_moments_tan(Dev d, Phys p, int force_rebuild, const float4* __restrict__ w,
+                                                        float4* __restrict__ mdot) {
+  extern __shared__ int lds[];
+  moments_tile<LPA, true, true>(d, p, 0, force_rebuild, xcd_remap(blockIdx.x, gridDim.x), lds, w, mdot);
+  clear_next(d, 0, blockIdx.x, gridDim.x);
 }
 
 // ----------------------------------------------------------------- forces
@@ -1277,6 +1315,21 @@ hipError_t launch_moments(const Dev& d, const Phys& p, int lpa, int par, int for
     case 64: return moments_lpa<64>(d, p, par, force_rebuild, energy, s, tm);
   }
   return hipErrorInvalidValue;
+}
+
+hipError_t launch_moments_tan(const Dev& d, const Phys& p, int lpa, int force_rebuild, const float4* w, float4* mdot,
+                              hipStream_t s) {
+  const unsigned grid = (unsigned)(d.npad / (kBlock / lpa));
+  const uint32_t lds = (uint32_t)moments_lds_bytes(kBlock / lpa, d.cap);
+  switch (lpa) {
+    case 4: hipLaunchKernelGGL(k_moments_tan<4>, dim3(grid), dim3(kBlock), lds, s, d, p, force_rebuild, w, mdot); break;
+    case 8: hipLaunchKernelGGL(k_moments_tan<8>, dim3(grid), dim3(kBlock), lds, s, d, p, force_rebuild, w, mdot); break;
+    case 16: hipLaunchKernelGGL(k_moments_tan<16>, dim3(grid), dim3(kBlock), lds, s, d, p, force_rebuild, w, mdot); break;
+    case 32: hipLaunchKernelGGL(k_moments_tan<32>, dim3(grid), dim3(kBlock), lds, s, d, p, force_rebuild, w, mdot); break;
+    case 64: hipLaunchKernelGGL(k_moments_tan<64>, dim3(grid), dim3(kBlock), lds, s, d, p, force_rebuild, w, mdot); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
 }
 
 hipError_t launch_forces(const Dev& d, const Phys& p, int lpa, int mode, int vir, int par, double* ring_row,

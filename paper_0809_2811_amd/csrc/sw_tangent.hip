@@ -35,98 +35,6 @@
 namespace swk {
 namespace {
 
-struct D {
-  float v, d;
-};
-__device__ __forceinline__ D operator+(D a, D b) { return {a.v + b.v, a.d + b.d}; }
-__device__ __forceinline__ D operator-(D a, D b) { return {a.v - b.v, a.d - b.d}; }
-__device__ __forceinline__ D operator*(D a, D b) { return {a.v * b.v, a.d * b.v + a.v * b.d}; }
-__device__ __forceinline__ D operator*(float s, D a) { return {s * a.v, s * a.d}; }
-__device__ __forceinline__ D operator+(D a, float s) { return {a.v + s, a.d}; }
-__device__ __forceinline__ D operator-(D a, float s) { return {a.v - s, a.d}; }
-__device__ __forceinline__ D neg(D a) { return {-a.v, -a.d}; }
-__device__ __forceinline__ D rsqD(D a) {
-  const float r = rsq(a.v);
-  return {r, -0.5f * r * r * r * a.d};
-}
-__device__ __forceinline__ D rcpD(D a) {
-  const float r = rcp(a.v);
-  return {r, -r * r * a.d};
-}
-__device__ __forceinline__ D ex2D(D a) {
-  const float e = ex2(a.v);
-  return {e, e * 0.69314718055994531f * a.d};
-}
-
-struct Geo {
-  D ux, uy, uz, r, ir, idr, eg;
-};
-
-// Leg geometry of one neighbour as dual numbers.
-__device__ __forceinline__ Geo geometry(const float3& dd, const float3& dt, const Phys& p) {
-  const D dx{dd.x, dt.x}, dy{dd.y, dt.y}, dz{dd.z, dt.z};
-  const D r2 = dx * dx + dy * dy + dz * dz;
-  Geo G;
-  G.ir = rsqD(r2);
-  G.r = r2 * G.ir;
-  G.ux = dx * G.ir; G.uy = dy * G.ir; G.uz = dz * G.ir;
-  G.idr = rcpD(G.r - p.rc);
-  G.eg = ex2D(p.gsig_l2e * G.idr);
-  return G;
-}
-
-__device__ __forceinline__ float3 sub3(const float4& a, const float4& b) {
-  return make_float3(a.x - b.x, a.y - b.y, a.z - b.z);
-}
-
-// Tangent of the per-centre moments T, V, S along w.
-template <int LPA>
-__global__ __launch_bounds__(kBlock) void k_tan_moments(Dev d, Tan t, Phys p, const float4* __restrict__ w,
-                                                        int par) {
-  constexpr int APB = kBlock / LPA;
-  const int bid = xcd_remap(blockIdx.x, gridDim.x);
-  const int g = threadIdx.x / LPA, lane = threadIdx.x % LPA;
-  const int i = bid * APB + g;
-  // The atom's own records and its first row slot are loaded before the
-  // replica is known (arrays are padded to npad: padding lanes read in
-  // bounds and are masked), so they share one round trip with the lookup.
-  const uint4 ui = pick(d.u, par)[i];
-  const float4 wi = w[i];
-  const int nn_row = d.nn[i];
-  const int* row = d.nl + (size_t)i * d.cap;
-  int jn = row[min(lane, d.cap - 1)];
-  const int rep = d.R == 1 ? 0 : __builtin_amdgcn_readfirstlane(d.tile_rep[i >> 6]);
-  const RepInfo& R = d.reps[rep];
-  const bool real = i < R.iend;
-  const int nn = real ? nn_row : 0;
-  float T0 = 0.f, T1 = 0.f, T2 = 0.f, T3 = 0.f, T4 = 0.f, T5 = 0.f, V0 = 0.f, V1 = 0.f, V2 = 0.f, S = 0.f;
-  for (int s = lane; s < nn; s += LPA) {
-    const int j = jn;
-    jn = row[min(s + LPA, nn - 1)];   // the next slot, in flight during this one
-    const uint4 uj = pick(d.u, par)[j];
-    const float4 wj = w[j];            // read whatever the distance: one batch with the position
-    asm volatile("" ::"v"(uj.x), "v"(wj.x));
-    const float3 dd = disp(ui, uj, R.scale[0], R.scale[1], R.scale[2]);
-    if (dd.x * dd.x + dd.y * dd.y + dd.z * dd.z < p.rc2) {
-      const Geo G = geometry(dd, sub3(wj, wi), p);
-      const D ex = G.eg * G.ux, ey = G.eg * G.uy, ez = G.eg * G.uz;
-      T0 += (ex * G.ux).d; T1 += (ey * G.uy).d; T2 += (ez * G.uz).d;
-      T3 += (ex * G.uy).d; T4 += (ex * G.uz).d; T5 += (ey * G.uz).d;
-      V0 += ex.d; V1 += ey.d; V2 += ez.d; S += G.eg.d;
-    }
-  }
-  T0 = group_sum<LPA>(T0); T1 = group_sum<LPA>(T1); T2 = group_sum<LPA>(T2);
-  T3 = group_sum<LPA>(T3); T4 = group_sum<LPA>(T4); T5 = group_sum<LPA>(T5);
-  V0 = group_sum<LPA>(V0); V1 = group_sum<LPA>(V1); V2 = group_sum<LPA>(V2);
-  S = group_sum<LPA>(S);
-  if (real && lane == 0) {
-    float4* m = t.mdot + 3 * (size_t)i;
-    m[0] = make_float4(T0, T1, T2, T3);
-    m[1] = make_float4(T4, T5, V0, V1);
-    m[2] = make_float4(V2, S, 0.f, 0.f);
-  }
-}
-
 // Forces and their tangent along w, virial traces and their tangent; with
 // ADJ the per-atom adjoint update of one frame.
 template <int LPA, bool ADJ>
@@ -179,7 +87,7 @@ __global__ __launch_bounds__(kBlock) void k_tan_forces(Dev d, Tan t, Phys p, con
     asm volatile("" ::"v"(uj.x), "v"(wj.x), "v"(na.x), "v"(nb.x), "v"(nc.x), "v"(da.x), "v"(db.x), "v"(dc.x));
     const float3 dd = disp(ui, uj, R.scale[0], R.scale[1], R.scale[2]);
     if (dd.x * dd.x + dd.y * dd.y + dd.z * dd.z < p.rc2) {
-      const Geo G = geometry(dd, sub3(wj, wi), p);
+      const Leg G = leg_dual(dd, sub3(wj, wi), p);
       const D idr2 = G.idr * G.idr;
       const D e1 = ex2D(p.sig_l2e * G.idr);
       const D sr = p.sig * G.ir, s2 = sr * sr, s4 = s2 * s2;
@@ -354,34 +262,17 @@ inline unsigned nb(long long n) { return (unsigned)((n + kBlock - 1) / kBlock); 
 
 template <int LPA>
 hipError_t tan_launch(const Dev& d, const Tan& t, const Phys& p, const float4* w, int par, const Adj* adj,
-                      const PTerm& pt, hipStream_t s, bool moments) {
+                      const PTerm& pt, hipStream_t s) {
   constexpr int APB = kBlock / LPA;
   const unsigned grid = (unsigned)(d.npad / APB);
-  if (moments) {
-    hipLaunchKernelGGL((k_tan_moments<LPA>), dim3(grid), dim3(kBlock), 0, s, d, t, p, w, par);
+  Adj a = adj ? *adj : Adj{};
+  if (adj) {   // an adjoint frame accumulates; the sweep reduces once at its end
+    hipLaunchKernelGGL((k_tan_forces<LPA, true>), dim3(grid), dim3(kBlock), 0, s, d, t, p, w, par, a);
   } else {
-    Adj a = adj ? *adj : Adj{};
-    if (adj) {   // an adjoint frame accumulates; the sweep reduces once at its end
-      hipLaunchKernelGGL((k_tan_forces<LPA, true>), dim3(grid), dim3(kBlock), 0, s, d, t, p, w, par, a);
-    } else {
-      hipLaunchKernelGGL((k_tan_forces<LPA, false>), dim3(grid), dim3(kBlock), 0, s, d, t, p, w, par, a);
-      hipLaunchKernelGGL(k_reduce_tan, dim3((unsigned)std::min(d.R, 4096)), dim3(kBlock), 0, s, d, t, APB, pt);
-    }
+    hipLaunchKernelGGL((k_tan_forces<LPA, false>), dim3(grid), dim3(kBlock), 0, s, d, t, p, w, par, a);
+    hipLaunchKernelGGL(k_reduce_tan, dim3((unsigned)std::min(d.R, 4096)), dim3(kBlock), 0, s, d, t, APB, pt);
   }
   return hipGetLastError();
-}
-
-hipError_t launch_tan_moments(const Dev& d, const Tan& t, const Phys& p, int lpa, const float4* w, int par,
-                              hipStream_t s) {
-  const PTerm none{};
-  switch (lpa) {
-    case 4: return tan_launch<4>(d, t, p, w, par, nullptr, none, s, true);
-    case 8: return tan_launch<8>(d, t, p, w, par, nullptr, none, s, true);
-    case 16: return tan_launch<16>(d, t, p, w, par, nullptr, none, s, true);
-    case 32: return tan_launch<32>(d, t, p, w, par, nullptr, none, s, true);
-    case 64: return tan_launch<64>(d, t, p, w, par, nullptr, none, s, true);
-  }
-  return hipErrorInvalidValue;
 }
 
 // Per-replica sums of t.tpartial (block partials of a force launch at lpa
@@ -396,11 +287,11 @@ hipError_t launch_tan_reduce(const Dev& d, const Tan& t, int lpa, const PTerm& p
 hipError_t launch_tan_forces(const Dev& d, const Tan& t, const Phys& p, int lpa, const float4* w, int par,
                              const Adj* adj, const PTerm& pt, hipStream_t s) {
   switch (lpa) {
-    case 4: return tan_launch<4>(d, t, p, w, par, adj, pt, s, false);
-    case 8: return tan_launch<8>(d, t, p, w, par, adj, pt, s, false);
-    case 16: return tan_launch<16>(d, t, p, w, par, adj, pt, s, false);
-    case 32: return tan_launch<32>(d, t, p, w, par, adj, pt, s, false);
-    case 64: return tan_launch<64>(d, t, p, w, par, adj, pt, s, false);
+    case 4: return tan_launch<4>(d, t, p, w, par, adj, pt, s);
+    case 8: return tan_launch<8>(d, t, p, w, par, adj, pt, s);
+    case 16: return tan_launch<16>(d, t, p, w, par, adj, pt, s);
+    case 32: return tan_launch<32>(d, t, p, w, par, adj, pt, s);
+    case 64: return tan_launch<64>(d, t, p, w, par, adj, pt, s);
   }
   return hipErrorInvalidValue;
 }
@@ -544,8 +435,7 @@ hipError_t load_ckpt(sw_ctx* c, const Ckpt& k, uint4* u_dst, bool rows, hipStrea
 hipError_t tangent_frame(sw_ctx* c, const Dev& dv, const Phys& ph, int lpa, const float4* w, const Adj* adj,
                          const PTerm& pt, hipStream_t s) {
   hipError_t e;
-  if ((e = launch_moments(dv, ph, lpa, 0, 1, 1, s)) != hipSuccess) return e;
-  if ((e = launch_tan_moments(dv, c->t, ph, lpa, w, 0, s)) != hipSuccess) return e;
+  if ((e = launch_moments_tan(dv, ph, lpa, 1, w, c->t.mdot, s)) != hipSuccess) return e;
   return launch_tan_forces(dv, c->t, ph, lpa, w, 0, adj, pt, s);
 }
 
@@ -558,8 +448,7 @@ hipError_t tangent_pass(sw_ctx* c, const Phys& ph, int lpa, const float4* w, con
   if ((e = launch_fill_i32(d.gcnt[0], 0, c->ctot, s)) != hipSuccess) return e;
   if ((e = launch_fill_i32(d.dflag, 0, 2 * c->R, s)) != hipSuccess) return e;
   if ((e = launch_bin(d, 0, rebuild ? 0 : 1, ph.half_skin, s)) != hipSuccess) return e;
-  if ((e = launch_moments(d, ph, lpa, 0, rebuild ? 1 : 0, 1, s)) != hipSuccess) return e;
-  if ((e = launch_tan_moments(d, c->t, ph, lpa, w, 0, s)) != hipSuccess) return e;
+  if ((e = launch_moments_tan(d, ph, lpa, rebuild ? 1 : 0, w, c->t.mdot, s)) != hipSuccess) return e;
   return launch_tan_forces(d, c->t, ph, lpa, w, 0, nullptr, pt, s);
 }
 
