@@ -48,8 +48,6 @@ FLOP_PER_ATOM = 30.0
 MOM_FLOP_PER_ACTIVE = 44.0
 MOM_FLOP_PER_ATOM = 20.0
 REBUILD_FLOP_PER_CAND = 12.0
-COUNTERS = os.path.join(ROOT, "paper_0809_2811_amd", "hbm_counters.json")
-KERNEL_SOURCES = ("sw_kernels.hip", "sw_device.h", "sw_internal.h")
 
 
 def number_density(rho_gcc=1.0, mass=18.015):
@@ -82,12 +80,8 @@ def moments_kernel_work(n_atoms, rho_gcc, skin, box, rebuild_frac):
 
 
 def kernel_sources_digest():
-    import hashlib
-    h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, "paper_0809_2811_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()
+    from paper_0809_2811_amd import hbm_counters
+    return hbm_counters.kernel_sources_digest()
 
 
 def measured_traffic(kernel, workload):
@@ -95,17 +89,8 @@ def measured_traffic(kernel, workload):
     counter's reading for a plain copy of known size) recorded for this
     kernel and workload, or None when no record exists or the kernel sources
     changed since the counters were taken."""
-    try:
-        with open(COUNTERS) as fh:
-            rec = json.load(fh)
-    except (OSError, ValueError):
-        return None
-    if rec.get("kernel_sources_sha256") != kernel_sources_digest():
-        return None
-    ent = rec.get("kernels", {}).get(f"{workload}/{kernel}")
-    if not ent:
-        return None
-    return ent["fetch_bytes"] * rec["fetch_scale"] + ent["write_bytes"] * rec["write_scale"]
+    from paper_0809_2811_amd import hbm_counters
+    return hbm_counters.measured_traffic(kernel, workload)
 
 
 def sync():
