@@ -167,7 +167,11 @@ int sw_grad(sw_ctx* ctx, const float* x, const float* w, const sw_params* params
  *  xbar0, vbar0 device float[N][4] out: dL/dx0, dL/dv0.
  *  thbar    device double[R][3] out: dL/d(lambda, epsilon, sigma).
  *  xS, vS   device float[N][4] out (may be NULL): final state.
- * Synchronises. */
+ * Work buffers (a checkpoint per segment, ckpt_every + 1 frames of positions
+ * and cells, adjoint vectors) are device memory the context allocates on
+ * first use, keeps for later calls (grown when a call needs more) and frees
+ * in sw_destroy.  Synchronises once, at the end (a row or cell overflow is
+ * found there and the call reruns itself with grown capacities). */
 int sw_adjoint(sw_ctx* ctx, const float* x0, const float* v0, const sw_params* params,
                double mass, double dt, int nsteps, int ckpt_every, double aU, double a3,
                const float* xbar_S, const float* vbar_S, double* loss, float* xbar0,

@@ -469,6 +469,7 @@ void sw_destroy(sw_ctx* ctx) {
   if (ctx->npt_gexec) (void)hipGraphExecDestroy(ctx->npt_gexec);
   if (ctx->npt_graph) (void)hipGraphDestroy(ctx->npt_graph);
   if (ctx->npt_ring) (void)hipFree(ctx->npt_ring);
+  for (void* p : ctx->adj_buf) (void)hipFree(p);
   free_list(ctx, ctx->grow_allocs);
   free_list(ctx, ctx->allocs);
   delete ctx;

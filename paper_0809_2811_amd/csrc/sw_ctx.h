@@ -50,6 +50,10 @@ struct sw_ctx {
   std::unordered_map<void*, size_t> sizes;   // live device allocations
   std::vector<void*> allocs;       // everything freed by free_all
   std::vector<void*> grow_allocs;  // capacity-dependent buffers
+  // adjoint work buffers (checkpoints, frame stores, adjoint vectors), kept
+  // between calls and grown on demand; slot k is the k-th buffer a call asks for
+  std::vector<void*> adj_buf;
+  std::vector<size_t> adj_bytes;
   // observables (allocated on first use)
   double* obs_edges = nullptr;     // bin edges of the last histogram call
   unsigned long long* obs_flags = nullptr;   // [0] centres short of neighbours, [1] candidate overflow

@@ -326,16 +326,29 @@ using namespace swh;
 namespace {
 
 // Device buffers of one sw_adjoint call.
+// The adjoint's work buffers, held by the context between calls: the k-th
+// request of a call gets slot k, reallocated only when it must grow (no
+// allocation or free, and so no device synchronisation, once sizes settle).
 struct AdjBuffers {
-  std::vector<void*> list;
+  sw_ctx* c;
+  size_t k = 0;
   template <class T>
   hipError_t get(T** p, size_t n) {
-    hipError_t e = hipMalloc((void**)p, std::max<size_t>(n, 1) * sizeof(T));
-    if (e == hipSuccess) list.push_back((void*)*p);
-    return e;
-  }
-  ~AdjBuffers() {
-    for (void* p : list) (void)hipFree(p);
+    const size_t bytes = std::max<size_t>(n, 1) * sizeof(T);
+    if (k == c->adj_buf.size()) {
+      c->adj_buf.push_back(nullptr);
+      c->adj_bytes.push_back(0);
+    }
+    if (c->adj_bytes[k] < bytes) {
+      if (c->adj_buf[k]) (void)hipFree(c->adj_buf[k]);
+      c->adj_buf[k] = nullptr;
+      c->adj_bytes[k] = 0;
+      hipError_t e = hipMalloc(&c->adj_buf[k], bytes);
+      if (e != hipSuccess) return e;
+      c->adj_bytes[k] = bytes;
+    }
+    *p = (T*)c->adj_buf[k++];
+    return hipSuccess;
   }
 };
 
@@ -506,7 +519,7 @@ int sw_adjoint(sw_ctx* ctx, const float* x0, const float* v0, const sw_params* p
   const size_t np = ctx->npad;
   const double c_m = kAcc / mass;
   for (int attempt = 0; attempt < 6; ++attempt) {
-    AdjBuffers B;
+    AdjBuffers B{ctx};
     uint4 *ck_u = nullptr, *ck_uref = nullptr, *fs_u = nullptr, *fs_cells = nullptr;
     float4 *ck_v = nullptr, *xb = nullptr, *vb[2] = {nullptr, nullptr};
     int *ck_nl = nullptr, *ck_nn = nullptr, *fs_cnt = nullptr;
@@ -543,12 +556,9 @@ int sw_adjoint(sw_ctx* ctx, const float* x0, const float* v0, const sw_params* p
       if ((e = run_segment(ctx, ph, lpa, len, j == 0, last ? &fs : nullptr, s)) != hipSuccess)
         return fail_hip(ctx, e);
     }
-    Flags fl;
-    if ((e = read_flags(ctx, s, &fl)) != hipSuccess) return fail_hip(ctx, e);
-    if (fl.nbr_over || fl.cell_over) {
-      if ((st = grow(ctx, fl)) != SW_OK) return st;
-      continue;
-    }
+    // Row or cell overflow in the forward run is read with the flags at the
+    // end (truncated rows and cells stay in bounds); the call is then rerun
+    // with grown capacities, so the host never waits in between.
     {
       const int len_last = S - (nseg - 1) * K;
       Dev dS = ctx->d;
@@ -596,6 +606,7 @@ int sw_adjoint(sw_ctx* ctx, const float* x0, const float* v0, const sw_params* p
     if ((e = launch_scatter_vec(ctx->d, vb[cur], (float4*)vbar0, s)) != hipSuccess) return fail_hip(ctx, e);
     if ((e = hipMemcpyAsync(thbar, thb, sizeof(double) * 3 * ctx->R, hipMemcpyDeviceToDevice, s)) != hipSuccess)
       return fail_hip(ctx, e);
+    Flags fl;
     if ((e = read_flags(ctx, s, &fl)) != hipSuccess) return fail_hip(ctx, e);
     if (fl.nbr_over || fl.cell_over) {
       if ((st = grow(ctx, fl)) != SW_OK) return st;
