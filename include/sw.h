@@ -266,8 +266,11 @@ typedef struct sw_tuning {
   int lanes_per_atom;   /* 4, 8, 16, 32 or 64 lanes of a wavefront per atom   */
   int graph_steps;      /* sw_step and sw_npt replay captured hipGraph blocks of
                            at least this many steps (rounded up to a multiple
-                           of 2 and of the record interval); 0 = plain
-                           launches.  Results are the same bits either way.    */
+                           of 2 and of the record interval); any value > 0 also
+                           makes sw_adjoint capture its forward and reverse
+                           sweeps on the first call of a configuration and
+                           replay them on later calls; 0 = plain launches.
+                           Results are the same bits either way.               */
   int persistent;       /* 0: one launch per phase; 1: sw_step's steps run in one
                            cooperative persistent launch at full occupancy;
                            k > 1: the same with at most k blocks per CU         */

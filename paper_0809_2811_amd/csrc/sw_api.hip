@@ -469,6 +469,8 @@ void sw_destroy(sw_ctx* ctx) {
   if (ctx->npt_gexec) (void)hipGraphExecDestroy(ctx->npt_gexec);
   if (ctx->npt_graph) (void)hipGraphDestroy(ctx->npt_graph);
   if (ctx->npt_ring) (void)hipFree(ctx->npt_ring);
+  if (ctx->adj_gexec) (void)hipGraphExecDestroy(ctx->adj_gexec);
+  if (ctx->adj_graph) (void)hipGraphDestroy(ctx->adj_graph);
   for (void* p : ctx->adj_buf) (void)hipFree(p);
   free_list(ctx, ctx->grow_allocs);
   free_list(ctx, ctx->allocs);

@@ -54,6 +54,10 @@ struct sw_ctx {
   // between calls and grown on demand; slot k is the k-th buffer a call asks for
   std::vector<void*> adj_buf;
   std::vector<size_t> adj_bytes;
+  // captured adjoint core (graph_steps > 0), keyed by everything it reads
+  hipGraph_t adj_graph = nullptr;
+  hipGraphExec_t adj_gexec = nullptr;
+  std::vector<unsigned char> adj_gkey;
   // observables (allocated on first use)
   double* obs_edges = nullptr;     // bin edges of the last histogram call
   unsigned long long* obs_flags = nullptr;   // [0] centres short of neighbours, [1] candidate overflow

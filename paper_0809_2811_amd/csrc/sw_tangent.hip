@@ -30,6 +30,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstring>
 #include <vector>
 
 namespace swk {
@@ -520,10 +521,10 @@ int sw_adjoint(sw_ctx* ctx, const float* x0, const float* v0, const sw_params* p
   const double c_m = kAcc / mass;
   for (int attempt = 0; attempt < 6; ++attempt) {
     AdjBuffers B{ctx};
-    uint4 *ck_u = nullptr, *ck_uref = nullptr, *fs_u = nullptr, *fs_cells = nullptr;
-    float4 *ck_v = nullptr, *xb = nullptr, *vb[2] = {nullptr, nullptr};
+    uint4 *ck_u = nullptr, *ck_uref = nullptr, *fs_u = nullptr, *fs_cells = nullptr, *st_u = nullptr;
+    float4 *ck_v = nullptr, *xb = nullptr, *vb[2] = {nullptr, nullptr}, *st_v = nullptr;
     int *ck_nl = nullptr, *ck_nn = nullptr, *fs_cnt = nullptr;
-    double *thb = nullptr, *tacc = nullptr;
+    double *thb = nullptr, *tacc = nullptr, *lossb = nullptr;
     hipError_t e;
     const size_t nf = (size_t)K + 1;
     if ((e = B.get(&ck_u, np * nseg)) != hipSuccess || (e = B.get(&ck_v, np * nseg)) != hipSuccess ||
@@ -533,78 +534,127 @@ int sw_adjoint(sw_ctx* ctx, const float* x0, const float* v0, const sw_params* p
         (e = B.get(&fs_cells, (size_t)ctx->ctot * ctx->cc * nf)) != hipSuccess ||
         (e = B.get(&xb, np)) != hipSuccess || (e = B.get(&vb[0], np)) != hipSuccess ||
         (e = B.get(&vb[1], np)) != hipSuccess || (e = B.get(&thb, (size_t)ctx->R * 3)) != hipSuccess ||
-        (e = B.get(&tacc, (np / kMinAPB + 1) * kTQ)) != hipSuccess)
+        (e = B.get(&tacc, (np / kMinAPB + 1) * kTQ)) != hipSuccess || (e = B.get(&lossb, (size_t)ctx->R)) != hipSuccess ||
+        (e = B.get(&st_u, np)) != hipSuccess || (e = B.get(&st_v, np)) != hipSuccess)
       return e == hipErrorOutOfMemory ? SW_ENOMEM : fail_hip(ctx, e);
     const FrameStore fs{fs_u, fs_cnt, fs_cells};
+    // caller inputs into internal order (eager: the core below touches only
+    // buffers the context owns, so a captured core serves any caller tensors)
     if ((e = reset_flags(ctx, s)) != hipSuccess) return fail_hip(ctx, e);
     if ((e = sort_in(ctx, x0, v0, s)) != hipSuccess) return fail_hip(ctx, e);
+    if ((e = launch_gather_vec(ctx->d, (const float4*)xbar_S, xb, s)) != hipSuccess) return fail_hip(ctx, e);
+    if ((e = launch_gather_vec(ctx->d, (const float4*)vbar_S, vb[0], s)) != hipSuccess) return fail_hip(ctx, e);
     auto ckpt = [&](int j) {
       return Ckpt{ck_u + (size_t)j * np, ck_v + (size_t)j * np, ck_nl + (size_t)j * np * ctx->cap,
                   ck_nn + (size_t)j * np, ck_uref + (size_t)j * np};
     };
-    // forward with a checkpoint at every segment start; the last segment
-    // runs into the frame store, so the reverse sweep needs no recompute of it
-    for (int j = 0; j < nseg; ++j) {
-      const int c = j * K, len = std::min(K, S - c);
-      if (j > 0 && (e = save_ckpt(ctx, ckpt(j), s)) != hipSuccess) return fail_hip(ctx, e);
-      if (j == 0) {   // rows of the first segment are built by run_segment itself
-        if ((e = launch_copy_u(ctx->d, ctx->d.u[0], ck_u, s)) != hipSuccess) return fail_hip(ctx, e);
-        if ((e = launch_copy_v(ctx->d, ctx->d.v, ck_v, s)) != hipSuccess) return fail_hip(ctx, e);
+    // The core: forward, final state staged, reverse sweep, sums of all frames.
+    auto core = [&](hipStream_t q) -> hipError_t {
+      hipError_t r;
+      // forward with a checkpoint at every segment start; the last segment
+      // runs into the frame store, so the reverse sweep needs no recompute of it
+      for (int j = 0; j < nseg; ++j) {
+        const int c = j * K, len = std::min(K, S - c);
+        if (j > 0 && (r = save_ckpt(ctx, ckpt(j), q)) != hipSuccess) return r;
+        if (j == 0) {   // rows of the first segment are built by run_segment itself
+          if ((r = launch_copy_u(ctx->d, ctx->d.u[0], ck_u, q)) != hipSuccess) return r;
+          if ((r = launch_copy_v(ctx->d, ctx->d.v, ck_v, q)) != hipSuccess) return r;
+        }
+        const bool last = j == nseg - 1;
+        if (last && (r = launch_copy_u(ctx->d, ctx->d.u[0], fs.u, q)) != hipSuccess) return r;
+        if ((r = run_segment(ctx, ph, lpa, len, j == 0, last ? &fs : nullptr, q)) != hipSuccess) return r;
       }
-      const bool last = j == nseg - 1;
-      if (last && (e = launch_copy_u(ctx->d, ctx->d.u[0], fs.u, s)) != hipSuccess) return fail_hip(ctx, e);
-      if ((e = run_segment(ctx, ph, lpa, len, j == 0, last ? &fs : nullptr, s)) != hipSuccess)
-        return fail_hip(ctx, e);
-    }
-    // Row or cell overflow in the forward run is read with the flags at the
-    // end (truncated rows and cells stay in bounds); the call is then rerun
-    // with grown capacities, so the host never waits in between.
-    {
+      // Row or cell overflow in the forward run is read with the flags at the
+      // end (truncated rows and cells stay in bounds); the call then reruns
+      // with grown capacities, so the host never waits in between.
       const int len_last = S - (nseg - 1) * K;
-      Dev dS = ctx->d;
-      dS.u[0] = fs.u + (size_t)len_last * np;
-      if (xS && (e = launch_scatter_out(dS, 0, (float4*)xS, nullptr, nullptr, s)) != hipSuccess)
-        return fail_hip(ctx, e);
-      if (vS && (e = launch_scatter_out(dS, 0, nullptr, (float4*)vS, nullptr, s)) != hipSuccess)
-        return fail_hip(ctx, e);
-    }
-    // reverse sweep
-    int cur = 0;
-    if ((e = launch_gather_vec(ctx->d, (const float4*)xbar_S, xb, s)) != hipSuccess) return fail_hip(ctx, e);
-    if ((e = launch_gather_vec(ctx->d, (const float4*)vbar_S, vb[0], s)) != hipSuccess) return fail_hip(ctx, e);
-    if ((e = launch_fill_f64(thb, 0.0, 3 * (long long)ctx->R, s)) != hipSuccess) return fail_hip(ctx, e);
-    if ((e = launch_fill_f64(loss, 0.0, ctx->R, s)) != hipSuccess) return fail_hip(ctx, e);
-    if ((e = launch_fill_f64(tacc, 0.0, (long long)(np / kMinAPB + 1) * kTQ, s)) != hipSuccess)
-      return fail_hip(ctx, e);
-    for (int j = nseg - 1; j >= 0; --j) {
-      const int c = j * K, len = std::min(K, S - c);
-      if (j < nseg - 1) {   // recompute the segment into the frame store
-        if ((e = load_ckpt(ctx, ckpt(j), fs.u, j > 0, s)) != hipSuccess) return fail_hip(ctx, e);
-        if ((e = run_segment(ctx, ph, lpa, len, j == 0, &fs, s)) != hipSuccess) return fail_hip(ctx, e);
+      if ((r = launch_copy_u(ctx->d, fs.u + (size_t)len_last * np, st_u, q)) != hipSuccess) return r;
+      if ((r = launch_copy_v(ctx->d, ctx->d.v, st_v, q)) != hipSuccess) return r;
+      // reverse sweep
+      int cur = 0;
+      if ((r = launch_fill_f64(thb, 0.0, 3 * (long long)ctx->R, q)) != hipSuccess) return r;
+      if ((r = launch_fill_f64(lossb, 0.0, ctx->R, q)) != hipSuccess) return r;
+      if ((r = launch_fill_f64(tacc, 0.0, (long long)(np / kMinAPB + 1) * kTQ, q)) != hipSuccess) return r;
+      for (int j = nseg - 1; j >= 0; --j) {
+        const int c = j * K, len = std::min(K, S - c);
+        if (j < nseg - 1) {   // recompute the segment into the frame store
+          if ((r = load_ckpt(ctx, ckpt(j), fs.u, j > 0, q)) != hipSuccess) return r;
+          if ((r = run_segment(ctx, ph, lpa, len, j == 0, &fs, q)) != hipSuccess) return r;
+        }
+        const int s_lo = j == 0 ? 0 : c + 1;
+        for (int sf = c + len; sf >= s_lo; --sf) {
+          const int k = sf - c;
+          Dev dv = ctx->d;   // frame sf: its positions and cells in parity slot 0
+          dv.u[0] = fs.u + (size_t)k * np;
+          dv.gcnt[0] = fs.cnt + (size_t)k * ctx->ctot;
+          dv.gmem[0] = fs.cells + (size_t)k * ctx->ctot * ctx->cc;
+          const double coef = (sf == S || sf == 0) ? 0.5 * dt : dt;
+          const Adj a{xb, vb[cur ^ 1], (float)(coef * c_m), (float)dt, (float)aU, (float)a3, S, sf == 0,
+                      coef * c_m, tacc};
+          if ((r = tangent_frame(ctx, dv, ph, lpa, vb[cur], &a, PTerm{}, q)) != hipSuccess) return r;
+          if (sf > 0) cur ^= 1;
+        }
       }
-      const int s_lo = j == 0 ? 0 : c + 1;
-      for (int sf = c + len; sf >= s_lo; --sf) {
-        const int k = sf - c;
-        Dev dv = ctx->d;   // frame sf: its positions and cells in parity slot 0
-        dv.u[0] = fs.u + (size_t)k * np;
-        dv.gcnt[0] = fs.cnt + (size_t)k * ctx->ctot;
-        dv.gmem[0] = fs.cells + (size_t)k * ctx->ctot * ctx->cc;
-        const double coef = (sf == S || sf == 0) ? 0.5 * dt : dt;
-        const Adj a{xb, vb[cur ^ 1], (float)(coef * c_m), (float)dt, (float)aU, (float)a3, S, sf == 0,
-                    coef * c_m, tacc};
-        if ((e = tangent_frame(ctx, dv, ph, lpa, vb[cur], &a, PTerm{}, s)) != hipSuccess) return fail_hip(ctx, e);
-        if (sf > 0) cur ^= 1;
-      }
-    }
-    {   // parameter adjoint and loss from the sums of all frames (weights already applied)
+      // parameter adjoint and loss from the sums of all frames (weights already applied)
       Tan tr = ctx->t;
       tr.tpartial = tacc;
-      const PTerm pt{params->lambda, params->epsilon, params->sigma, nullptr, nullptr, thb, loss, 1.0, aU, a3, S};
-      if ((e = launch_tan_reduce(ctx->d, tr, lpa, pt, s)) != hipSuccess) return fail_hip(ctx, e);
+      const PTerm pt{params->lambda, params->epsilon, params->sigma, nullptr, nullptr, thb, lossb, 1.0, aU, a3, S};
+      return launch_tan_reduce(ctx->d, tr, lpa, pt, q);
+    };
+    if (ctx->tune.graph_steps > 0) {
+      // replay a captured core when everything it reads is unchanged
+      const double sc[9] = {aU, a3, dt, mass, c_m, params->lambda, params->epsilon, params->sigma, (double)S};
+      const int meta[5] = {K, nseg, lpa, ctx->alloc_gen, ctx->R};
+      std::vector<unsigned char> key(sizeof(Dev) + sizeof(Tan) + sizeof(Phys) + sizeof sc + sizeof meta +
+                                     sizeof(void*) * ctx->adj_buf.size());
+      unsigned char* kp = key.data();
+      std::memcpy(kp, &ctx->d, sizeof(Dev)); kp += sizeof(Dev);
+      std::memcpy(kp, &ctx->t, sizeof(Tan)); kp += sizeof(Tan);
+      std::memcpy(kp, &ph, sizeof(Phys)); kp += sizeof(Phys);
+      std::memcpy(kp, sc, sizeof sc); kp += sizeof sc;
+      std::memcpy(kp, meta, sizeof meta); kp += sizeof meta;
+      std::memcpy(kp, ctx->adj_buf.data(), sizeof(void*) * ctx->adj_buf.size());
+      if (!(ctx->adj_gexec && key == ctx->adj_gkey)) {
+        if (ctx->adj_gexec) { (void)hipGraphExecDestroy(ctx->adj_gexec); ctx->adj_gexec = nullptr; }
+        if (ctx->adj_graph) { (void)hipGraphDestroy(ctx->adj_graph); ctx->adj_graph = nullptr; }
+        ctx->adj_gkey.clear();
+        if (!ctx->cap_stream && (e = hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking)) != hipSuccess)
+          return fail_hip(ctx, e);
+        if ((e = hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal)) != hipSuccess)
+          return fail_hip(ctx, e);
+        const hipError_t ce = core(ctx->cap_stream);
+        hipGraph_t g = nullptr;
+        e = hipStreamEndCapture(ctx->cap_stream, &g);
+        if (ce != hipSuccess || e != hipSuccess) {
+          if (g) (void)hipGraphDestroy(g);
+          return fail_hip(ctx, ce != hipSuccess ? ce : e);
+        }
+        if ((e = hipGraphInstantiate(&ctx->adj_gexec, g, nullptr, nullptr, 0)) != hipSuccess) {
+          (void)hipGraphDestroy(g);
+          ctx->adj_gexec = nullptr;
+          return fail_hip(ctx, e);
+        }
+        ctx->adj_graph = g;
+        ctx->adj_gkey = key;
+      }
+      if ((e = hipGraphLaunch(ctx->adj_gexec, s)) != hipSuccess) return fail_hip(ctx, e);
+    } else if ((e = core(s)) != hipSuccess) {
+      return fail_hip(ctx, e);
     }
+    // results back to caller order
+    {
+      Dev dS = ctx->d;
+      dS.u[0] = st_u;
+      dS.v = st_v;
+      if ((xS || vS) && (e = launch_scatter_out(dS, 0, (float4*)xS, (float4*)vS, nullptr, s)) != hipSuccess)
+        return fail_hip(ctx, e);
+    }
+    const int cur = S & 1;   // one swap per frame s > 0
     if ((e = launch_scatter_vec(ctx->d, xb, (float4*)xbar0, s)) != hipSuccess) return fail_hip(ctx, e);
     if ((e = launch_scatter_vec(ctx->d, vb[cur], (float4*)vbar0, s)) != hipSuccess) return fail_hip(ctx, e);
     if ((e = hipMemcpyAsync(thbar, thb, sizeof(double) * 3 * ctx->R, hipMemcpyDeviceToDevice, s)) != hipSuccess)
+      return fail_hip(ctx, e);
+    if ((e = hipMemcpyAsync(loss, lossb, sizeof(double) * ctx->R, hipMemcpyDeviceToDevice, s)) != hipSuccess)
       return fail_hip(ctx, e);
     Flags fl;
     if ((e = read_flags(ctx, s, &fl)) != hipSuccess) return fail_hip(ctx, e);

@@ -201,3 +201,35 @@ def test_gauss_newton_recovers_the_paper_parameters():
     assert abs(th["lambda_"] - 23.15) < 1e-3 * 23.15, path
     assert abs(th["epsilon"] - 6.189) < 1e-3 * 6.189, path
     assert np.abs(res).max() < 1e-6 * abs(target[0])
+
+
+def test_captured_adjoint_replays_equal_plain_launches():
+    """With graph mode on, the adjoint's core is captured on the first call of
+    a configuration and replayed afterwards.  Every replay, with other GPU
+    work and fresh caller tensors in between, and after a different
+    configuration forced a new capture, gives the plain launches' results
+    bit for bit (terminal seeds included)."""
+    import torch
+    from paper_0809_2811_amd import sw
+    x, v, L = liquid(1, sigma=0.0)
+    x, v = f32(x), f32(v)
+    rng = np.random.default_rng(12)
+    xs, vs = f32(rng.normal(size=x.shape)), f32(rng.normal(size=x.shape))
+    plain = ctx_for(x, L)
+    graph = sw.Context([0, len(x)], [L], cutoff=RC, skin=0.8, nbr_capacity=48,
+                       tuning=dict(lanes_per_atom=8, graph_steps=50))
+    keys = ("loss", "thbar", "xbar0", "vbar0", "xS", "vS")
+
+    def run(ctx, S, K):
+        r = ctx.adjoint(to_dev(x), to_dev(v), S, ckpt_every=K, aU=1.0, a3=0.5,
+                        xbar_S=to_dev(xs), vbar_S=to_dev(vs))
+        return {k: r[k].cpu().numpy() for k in keys}
+
+    ref = {(S, K): run(plain, S, K) for S, K in ((10, 4), (7, 7))}
+    xw, vw = to_dev(x), to_dev(v)
+    for S, K in ((10, 4), (10, 4), (7, 7), (10, 4), (10, 4)):
+        got = run(graph, S, K)
+        for k in keys:
+            assert np.array_equal(got[k], ref[(S, K)][k]), (S, K, k)
+        graph.step(xw, vw, 3)          # other work on the same context between replays
+        torch.cuda.synchronize()
