@@ -72,10 +72,11 @@ __device__ __forceinline__ void cell_put(const Dev& d, int gp, int c, const uint
 
 // As cell_put for the wavefront's binned entries (lanes with c >= 0), with
 // one counter atomic per distinct cell of the wavefront.  Used where every
-// lane bins an atom (the thermostat kernel): atoms are in Morton order, so
-// consecutive lanes often share a cell (the replica table: 112.8 -> 109.3 us
-// per step).  In the force kernel (one binning lane per group) and the
-// isobaric kick the extra pass measured slower than one atomic per atom.
+// lane bins an atom (the thermostat kernel) in large contexts: atoms are in
+// Morton order, so consecutive lanes often share a cell (the replica table:
+// 112.8 -> 109.3 us per step).  In small contexts, in the force kernel (one
+// binning lane per group) and in the isobaric kick the extra pass measured
+// slower than one atomic per atom.
 // Every lane of the wavefront calls it (lanes with nothing to bin pass
 // c = -1).  The order of entries within a cell is not fixed; rows are sorted
 // when built.
@@ -857,7 +858,14 @@ __device__ __forceinline__ bool fused_sums(const RepInfo& R, int apb) {
 // The kinetic energy comes from the force launch's partials (summed here
 // for replicas of at most kFusedBlocks force blocks of apb atoms, else from
 // the reduction launch).  All 64 lanes of a wave call it together.
+// Contexts of at least this many (padded) atoms bin the thermostat kernel's
+// drifted positions with one atomic per distinct cell of a wavefront: the
+// replica table (~2.8e5 atoms, throughput bound) gains 3.5 us per step, a
+// 4096-atom box (latency bound) would lose ~3 us per launch to the extra pass.
+constexpr long long kAggAtoms = 65536;
+
 __device__ __forceinline__ void thermostat_atom(const Dev& d, const Phys& p, int par, int last, int i, int apb) {
+  const bool agg = d.npad >= kAggAtoms;
   if (i < d.npad) {
     // the atom's records before the replica lookup (padded arrays), pinned
     // so their round trip overlaps it
@@ -890,12 +898,18 @@ __device__ __forceinline__ void thermostat_atom(const Dev& d, const Phys& p, int
       if (!last) {
         v.x += p.hdt_cm * Fi.x; v.y += p.hdt_cm * Fi.y; v.z += p.hdt_cm * Fi.z;
         uint4 un = ui;
-        bc = drift(d, geo_of(R), rep, i, un, v, urefi, p.dt, p.half_skin, par ^ 1);
-        be = make_uint4(un.x, un.y, un.z, (unsigned)i);
+        const int c = drift(d, geo_of(R), rep, i, un, v, urefi, p.dt, p.half_skin, par ^ 1);
+        const uint4 e = make_uint4(un.x, un.y, un.z, (unsigned)i);
+        if (agg) {
+          bc = c;
+          be = e;
+        } else {
+          cell_put(d, par ^ 1, c, e);
+        }
       }
       d.v[i] = v;
     }
-    if (!last) cell_append(d, par ^ 1, bc, be);   // npad is a multiple of 64: whole wavefronts
+    if (!last && agg) cell_append(d, par ^ 1, bc, be);   // npad is a multiple of 64: whole wavefronts
   }
 }
 
