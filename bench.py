@@ -395,11 +395,30 @@ def bench_adjoint(plain_ms_per_step, steps=200, ckpt=20, skin=None):
     dt = (time.perf_counter() - t0) / reps
     ms = dt * 1e3 / steps
     th = res["thbar"].cpu().numpy()[0]
+    # The same call with every frame kept (one segment: the frame store holds
+    # all steps + 1 frames, ~90 MB here, so the reverse sweep recomputes
+    # nothing); its results are bitwise those of the checkpointed call.
+    ctx.adjoint(x, v, steps, ckpt_every=steps)
+    sync()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        res_all = ctx.adjoint(x, v, steps, ckpt_every=steps)
+    sync()
+    dt_all = (time.perf_counter() - t0) / reps
+    same = all(bool(torch_equal(res[k], res_all[k])) for k in ("loss", "thbar", "xbar0", "vbar0"))
     return {"workload": f"adjoint: {n}-atom 298 K liquid, {steps}-step NVE trajectory, checkpoints every {ckpt}, "
                         "loss = mean PE/atom + mean three-body energy/atom",
             "seconds_per_trajectory": dt, "ms_per_step": ms, "value": n * steps / dt, "unit": "atom-steps/s",
             "ratio_to_plain_step": ms / plain_ms_per_step, "loss": float(res["loss"].cpu()[0]),
-            "dL_dtheta": [float(t) for t in th]}
+            "dL_dtheta": [float(t) for t in th],
+            "all_frames_stored": {"ckpt_every": steps, "ms_per_step": dt_all * 1e3 / steps,
+                                  "value": n * steps / dt_all, "ratio_to_plain_step": dt_all * 1e3 / steps / plain_ms_per_step,
+                                  "bitwise_equal_to_checkpointed": same}}
+
+
+def torch_equal(a, b):
+    import torch
+    return torch.equal(a, b)
 
 
 def bench_observables(ctx, x, reps=20):
