@@ -171,9 +171,9 @@ hipError_t launch_moments(const Dev& d, const Phys& p, int lpa, int par, int for
                           int energy, hipStream_t s, const KTimer& tm = KTimer());
 hipError_t launch_forces(const Dev& d, const Phys& p, int lpa, int mode, int vir, int par,
                          double* ring_row, hipStream_t s, const KTimer& tm = KTimer());
-// Moments with energies at parity 0 and, in the same launch, their tangent
+// Moments with energies at parity par and, in the same launch, their tangent
 // along w (mdot [Npad][3]); rows rebuilt if forced or flagged.
-hipError_t launch_moments_tan(const Dev& d, const Phys& p, int lpa, int force_rebuild, const float4* w,
+hipError_t launch_moments_tan(const Dev& d, const Phys& p, int lpa, int par, int force_rebuild, const float4* w,
                               float4* mdot, hipStream_t s);
 hipError_t launch_thermostat(const Dev& d, const Phys& p, int lpa, int par, int last, hipStream_t s);
 hipError_t launch_scatter_out(const Dev& d, int par, float4* x_user, float4* v_user,
@@ -219,6 +219,9 @@ struct Adj {
   double coef_d;     // the frame weight coef_cm in double, applied to the w.F sums below
   double* tacc;      // [kTQ][nblocks] per-block sums over the sweep's frames (w.F terms
                      // weighted by coef_d); one reduction after the sweep
+  const uint4* unext;  // positions of the frame the sweep visits next, or null: an atom
+                       // more than half the skin from its row-build position raises the
+                       // replica's flag of the other parity (that frame rebuilds its rows)
 };
 hipError_t launch_gather_vec(const Dev& d, const float4* user, float4* internal, hipStream_t s);
 hipError_t launch_scatter_vec(const Dev& d, const float4* internal, float4* user, hipStream_t s);

@@ -566,15 +566,14 @@ __global__ __launch_bounds__(kBlock) void k_moments(Dev d, Phys p, int par, int 
   clear_next(d, par, blockIdx.x, gridDim.x);
 }
 
-// Moments with energies and their tangent along w (positions of parity 0):
-// the primal moments of k_moments and the tangent moments of the tangent
-// pass in one launch.
+// Moments with energies and their tangent along w: the primal moments of
+// k_moments and the tangent moments of the tangent pass in one launch.
 template <int LPA>
-__global__ __launch_bounds__(kBlock) void k_moments_tan(Dev d, Phys p, int force_rebuild, const float4* __restrict__ w,
-                                                        float4* __restrict__ mdot) {
+__global__ __launch_bounds__(kBlock) void k_moments_tan(Dev d, Phys p, int par, int force_rebuild,
+                                                        const float4* __restrict__ w, float4* __restrict__ mdot) {
   extern __shared__ int lds[];
-  moments_tile<LPA, true, true>(d, p, 0, force_rebuild, xcd_remap(blockIdx.x, gridDim.x), lds, w, mdot);
-  clear_next(d, 0, blockIdx.x, gridDim.x);
+  moments_tile<LPA, true, true>(d, p, par, force_rebuild, xcd_remap(blockIdx.x, gridDim.x), lds, w, mdot);
+  clear_next(d, par, blockIdx.x, gridDim.x);
 }
 
 // ----------------------------------------------------------------- forces
@@ -1381,16 +1380,16 @@ hipError_t launch_moments(const Dev& d, const Phys& p, int lpa, int par, int for
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_moments_tan(const Dev& d, const Phys& p, int lpa, int force_rebuild, const float4* w, float4* mdot,
-                              hipStream_t s) {
+hipError_t launch_moments_tan(const Dev& d, const Phys& p, int lpa, int par, int force_rebuild, const float4* w,
+                              float4* mdot, hipStream_t s) {
   const unsigned grid = (unsigned)(d.npad / (kBlock / lpa));
   const uint32_t lds = (uint32_t)moments_lds_bytes(kBlock / lpa, d.cap);
   switch (lpa) {
-    case 4: hipLaunchKernelGGL(k_moments_tan<4>, dim3(grid), dim3(kBlock), lds, s, d, p, force_rebuild, w, mdot); break;
-    case 8: hipLaunchKernelGGL(k_moments_tan<8>, dim3(grid), dim3(kBlock), lds, s, d, p, force_rebuild, w, mdot); break;
-    case 16: hipLaunchKernelGGL(k_moments_tan<16>, dim3(grid), dim3(kBlock), lds, s, d, p, force_rebuild, w, mdot); break;
-    case 32: hipLaunchKernelGGL(k_moments_tan<32>, dim3(grid), dim3(kBlock), lds, s, d, p, force_rebuild, w, mdot); break;
-    case 64: hipLaunchKernelGGL(k_moments_tan<64>, dim3(grid), dim3(kBlock), lds, s, d, p, force_rebuild, w, mdot); break;
+    case 4: hipLaunchKernelGGL(k_moments_tan<4>, dim3(grid), dim3(kBlock), lds, s, d, p, par, force_rebuild, w, mdot); break;
+    case 8: hipLaunchKernelGGL(k_moments_tan<8>, dim3(grid), dim3(kBlock), lds, s, d, p, par, force_rebuild, w, mdot); break;
+    case 16: hipLaunchKernelGGL(k_moments_tan<16>, dim3(grid), dim3(kBlock), lds, s, d, p, par, force_rebuild, w, mdot); break;
+    case 32: hipLaunchKernelGGL(k_moments_tan<32>, dim3(grid), dim3(kBlock), lds, s, d, p, par, force_rebuild, w, mdot); break;
+    case 64: hipLaunchKernelGGL(k_moments_tan<64>, dim3(grid), dim3(kBlock), lds, s, d, p, par, force_rebuild, w, mdot); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -22,9 +22,11 @@
 // full-step velocities and the row state, so the recompute repeats the
 // forward kernels exactly.  While a segment is recomputed (or, for the last
 // segment, while it first runs) every launch writes the frame's positions and
-// cell binning straight into per-frame stores; a frame of the reverse sweep
-// then builds its rows from the stored cells and runs the tangent pass with
-// no copies.  The loss terms are summed during the reverse sweep.
+// cell binning straight into per-frame stores; the reverse sweep runs the
+// tangent pass on each stored frame with no copies, carrying its rows from
+// frame to frame and rebuilding them from a frame's stored cells when that
+// frame's displacement check fails.  The loss terms are summed during the
+// reverse sweep.
 #include "sw_ctx.h"
 #include "sw_device.h"
 
@@ -54,6 +56,10 @@ __global__ __launch_bounds__(kBlock) void k_tan_forces(Dev d, Tan t, Phys p, con
   const float4* m = d.mom + 3 * (size_t)i;
   const float4* md = t.mdot + 3 * (size_t)i;
   const float4 a0 = m[0], a1 = m[1], a2 = m[2], b0 = md[0], b1 = md[1], b2 = md[2];
+  // the next frame's row check (adjoint sweep): its position and the row-build position
+  const bool chk = ADJ && a.unext != nullptr;
+  const uint4 unx = chk ? a.unext[i] : ui;
+  const uint4 urf = chk ? d.uref[i] : ui;
   const int nn_row = d.nn[i];
   const int* row = d.nl + (size_t)i * d.cap;
   int jn = row[min(lane, d.cap - 1)];
@@ -157,6 +163,11 @@ __global__ __launch_bounds__(kBlock) void k_tan_forces(Dev d, Tan t, Phys p, con
         a.xb[i] = xb;
         if (!a.last)
           a.vb_next[i] = make_float4(wi.x + a.dt * xb.x, wi.y + a.dt * xb.y, wi.z + a.dt * xb.z, 0.f);
+        if (chk) {
+          const float3 dd = disp(urf, unx, R.scale[0], R.scale[1], R.scale[2]);
+          if (dd.x * dd.x + dd.y * dd.y + dd.z * dd.z > p.half_skin * p.half_skin)
+            d.dflag[(par ^ 1) * d.R + rep] = 1;
+        }
       }
     }
 #pragma unroll
@@ -443,14 +454,32 @@ hipError_t load_ckpt(sw_ctx* c, const Ckpt& k, uint4* u_dst, bool rows, hipStrea
   return hipMemcpyAsync(c->d.nl, k.nl, sizeof(int) * np * c->cap, hipMemcpyDeviceToDevice, s);
 }
 
-// Tangent pass along w at the positions of dv.u[0], whose cells are binned
-// in dv.gcnt[0] / dv.gmem[0]: rows built fresh there, moments with energies,
-// tangent moments, tangent forces and the per-replica terms of pt.
-hipError_t tangent_frame(sw_ctx* c, const Dev& dv, const Phys& ph, int lpa, const float4* w, const Adj* adj,
-                         const PTerm& pt, hipStream_t s) {
+// Row state only (rows, lengths, build positions) to and from k.
+hipError_t save_rows(sw_ctx* c, const Ckpt& k, hipStream_t s) {
+  const size_t np = c->npad;
   hipError_t e;
-  if ((e = launch_moments_tan(dv, ph, lpa, 1, w, c->t.mdot, s)) != hipSuccess) return e;
-  return launch_tan_forces(dv, c->t, ph, lpa, w, 0, adj, pt, s);
+  if ((e = launch_copy_u(c->d, c->d.uref, k.uref, s)) != hipSuccess) return e;
+  if ((e = hipMemcpyAsync(k.nn, c->d.nn, sizeof(int) * np, hipMemcpyDeviceToDevice, s)) != hipSuccess) return e;
+  return hipMemcpyAsync(k.nl, c->d.nl, sizeof(int) * np * c->cap, hipMemcpyDeviceToDevice, s);
+}
+
+hipError_t load_rows(sw_ctx* c, const Ckpt& k, hipStream_t s) {
+  const size_t np = c->npad;
+  hipError_t e;
+  if ((e = launch_copy_u(c->d, k.uref, c->d.uref, s)) != hipSuccess) return e;
+  if ((e = hipMemcpyAsync(c->d.nn, k.nn, sizeof(int) * np, hipMemcpyDeviceToDevice, s)) != hipSuccess) return e;
+  return hipMemcpyAsync(c->d.nl, k.nl, sizeof(int) * np * c->cap, hipMemcpyDeviceToDevice, s);
+}
+
+// Tangent pass along w at the positions of dv.u[par], whose cells are binned
+// in dv.gcnt[par] / dv.gmem[par]: moments with energies and their tangent
+// (rows rebuilt there when forced or flagged in dv.dflag[par]), then tangent
+// forces with the adjoint update of *adj and the per-replica terms of pt.
+hipError_t tangent_frame(sw_ctx* c, const Dev& dv, const Phys& ph, int lpa, int par, int force_rebuild,
+                         const float4* w, const Adj* adj, const PTerm& pt, hipStream_t s) {
+  hipError_t e;
+  if ((e = launch_moments_tan(dv, ph, lpa, par, force_rebuild, w, c->t.mdot, s)) != hipSuccess) return e;
+  return launch_tan_forces(dv, c->t, ph, lpa, w, par, adj, pt, s);
 }
 
 // Tangent pass at positions u[0] along w; rows rebuilt first, or kept when
@@ -462,7 +491,7 @@ hipError_t tangent_pass(sw_ctx* c, const Phys& ph, int lpa, const float4* w, con
   if ((e = launch_fill_i32(d.gcnt[0], 0, c->ctot, s)) != hipSuccess) return e;
   if ((e = launch_fill_i32(d.dflag, 0, 2 * c->R, s)) != hipSuccess) return e;
   if ((e = launch_bin(d, 0, rebuild ? 0 : 1, ph.half_skin, s)) != hipSuccess) return e;
-  if ((e = launch_moments_tan(d, ph, lpa, rebuild ? 1 : 0, w, c->t.mdot, s)) != hipSuccess) return e;
+  if ((e = launch_moments_tan(d, ph, lpa, 0, rebuild ? 1 : 0, w, c->t.mdot, s)) != hipSuccess) return e;
   return launch_tan_forces(d, c->t, ph, lpa, w, 0, nullptr, pt, s);
 }
 
@@ -522,8 +551,9 @@ int sw_adjoint(sw_ctx* ctx, const float* x0, const float* v0, const sw_params* p
   for (int attempt = 0; attempt < 6; ++attempt) {
     AdjBuffers B{ctx};
     uint4 *ck_u = nullptr, *ck_uref = nullptr, *fs_u = nullptr, *fs_cells = nullptr, *st_u = nullptr;
+    uint4* rs_uref = nullptr;
     float4 *ck_v = nullptr, *xb = nullptr, *vb[2] = {nullptr, nullptr}, *st_v = nullptr;
-    int *ck_nl = nullptr, *ck_nn = nullptr, *fs_cnt = nullptr;
+    int *ck_nl = nullptr, *ck_nn = nullptr, *fs_cnt = nullptr, *rs_nl = nullptr, *rs_nn = nullptr, *rfl = nullptr;
     double *thb = nullptr, *tacc = nullptr, *lossb = nullptr;
     hipError_t e;
     const size_t nf = (size_t)K + 1;
@@ -535,7 +565,9 @@ int sw_adjoint(sw_ctx* ctx, const float* x0, const float* v0, const sw_params* p
         (e = B.get(&xb, np)) != hipSuccess || (e = B.get(&vb[0], np)) != hipSuccess ||
         (e = B.get(&vb[1], np)) != hipSuccess || (e = B.get(&thb, (size_t)ctx->R * 3)) != hipSuccess ||
         (e = B.get(&tacc, (np / kMinAPB + 1) * kTQ)) != hipSuccess || (e = B.get(&lossb, (size_t)ctx->R)) != hipSuccess ||
-        (e = B.get(&st_u, np)) != hipSuccess || (e = B.get(&st_v, np)) != hipSuccess)
+        (e = B.get(&st_u, np)) != hipSuccess || (e = B.get(&st_v, np)) != hipSuccess ||
+        (e = B.get(&rs_nl, np * ctx->cap)) != hipSuccess || (e = B.get(&rs_nn, np)) != hipSuccess ||
+        (e = B.get(&rs_uref, np)) != hipSuccess || (e = B.get(&rfl, 2 * (size_t)ctx->R)) != hipSuccess)
       return e == hipErrorOutOfMemory ? SW_ENOMEM : fail_hip(ctx, e);
     const FrameStore fs{fs_u, fs_cnt, fs_cells};
     // caller inputs into internal order (eager: the core below touches only
@@ -570,28 +602,40 @@ int sw_adjoint(sw_ctx* ctx, const float* x0, const float* v0, const sw_params* p
       const int len_last = S - (nseg - 1) * K;
       if ((r = launch_copy_u(ctx->d, fs.u + (size_t)len_last * np, st_u, q)) != hipSuccess) return r;
       if ((r = launch_copy_v(ctx->d, ctx->d.v, st_v, q)) != hipSuccess) return r;
-      // reverse sweep
+      // Reverse sweep.  Its rows start as the forward run's final rows (valid
+      // at x_S) and go from frame to frame like the forward's: a frame
+      // rebuilds them (from its stored cells) only when some atom of it lies
+      // more than half the skin from the rows' build position, which the
+      // previous frame's tangent-force launch checks.  They are set aside
+      // while a segment is recomputed, so the rebuilds, and every sum, depend
+      // on the frames alone and not on where segments start.
       int cur = 0;
       if ((r = launch_fill_f64(thb, 0.0, 3 * (long long)ctx->R, q)) != hipSuccess) return r;
       if ((r = launch_fill_f64(lossb, 0.0, ctx->R, q)) != hipSuccess) return r;
       if ((r = launch_fill_f64(tacc, 0.0, (long long)(np / kMinAPB + 1) * kTQ, q)) != hipSuccess) return r;
+      if ((r = launch_fill_i32(rfl, 0, 2 * ctx->R, q)) != hipSuccess) return r;
       for (int j = nseg - 1; j >= 0; --j) {
         const int c = j * K, len = std::min(K, S - c);
         if (j < nseg - 1) {   // recompute the segment into the frame store
+          const Ckpt rows{nullptr, nullptr, rs_nl, rs_nn, rs_uref};
+          if ((r = save_rows(ctx, rows, q)) != hipSuccess) return r;
           if ((r = load_ckpt(ctx, ckpt(j), fs.u, j > 0, q)) != hipSuccess) return r;
           if ((r = run_segment(ctx, ph, lpa, len, j == 0, &fs, q)) != hipSuccess) return r;
+          if ((r = load_rows(ctx, rows, q)) != hipSuccess) return r;
         }
         const int s_lo = j == 0 ? 0 : c + 1;
         for (int sf = c + len; sf >= s_lo; --sf) {
-          const int k = sf - c;
-          Dev dv = ctx->d;   // frame sf: its positions and cells in parity slot 0
-          dv.u[0] = fs.u + (size_t)k * np;
-          dv.gcnt[0] = fs.cnt + (size_t)k * ctx->ctot;
-          dv.gmem[0] = fs.cells + (size_t)k * ctx->ctot * ctx->cc;
+          const int k = sf - c, par = sf & 1;
+          Dev dv = ctx->d;   // frame sf: its positions and cells in parity slot sf & 1
+          dv.u[par] = fs.u + (size_t)k * np;
+          dv.gcnt[par] = fs.cnt + (size_t)k * ctx->ctot;
+          dv.gmem[par] = fs.cells + (size_t)k * ctx->ctot * ctx->cc;
+          dv.dflag = rfl;
           const double coef = (sf == S || sf == 0) ? 0.5 * dt : dt;
+          // frame sf - 1 is frame k - 1 of this store (a store holds its segment's start)
           const Adj a{xb, vb[cur ^ 1], (float)(coef * c_m), (float)dt, (float)aU, (float)a3, S, sf == 0,
-                      coef * c_m, tacc};
-          if ((r = tangent_frame(ctx, dv, ph, lpa, vb[cur], &a, PTerm{}, q)) != hipSuccess) return r;
+                      coef * c_m, tacc, sf > 0 ? fs.u + (size_t)(k - 1) * np : nullptr};
+          if ((r = tangent_frame(ctx, dv, ph, lpa, par, 0, vb[cur], &a, PTerm{}, q)) != hipSuccess) return r;
           if (sf > 0) cur ^= 1;
         }
       }
