@@ -200,6 +200,38 @@ def test_step_is_deterministic():
         assert np.array_equal(a[k], b[k])
 
 
+def test_large_context_thermostat_binning_keeps_replicas_exact():
+    """16 replicas of the 4096-atom liquid in one context (65536 atoms: the
+    thermostat kernel appends a wavefront's cell entries with one counter
+    atomic per distinct cell) through Berendsen steps with row rebuilds:
+    replica 0 follows the oracle over the first 8 steps, and after 40 every
+    replica checked equals the same replica run alone (4096 atoms: one atomic
+    per atom) bit for bit."""
+    from paper_0809_2811_amd import sw
+    x, v, L = liquid(2)
+    x, v = f32(x), f32(v)
+    n, R = len(x), 16
+    T0 = [230.0 + 10.0 * r for r in range(R)]
+    ctx = make_ctx(np.tile(x, (R, 1)), None, offsets=np.arange(R + 1) * n, boxes=[L] * R)
+    xd, vd = to_dev(np.tile(x, (R, 1))), to_dev(np.tile(v, (R, 1)))
+    r0 = ctx.query(sw.SW_Q_REBUILDS)
+    ctx.step(xd, vd, 8, thermostat=sw.SW_BERENDSEN, T0=T0, tau_fs=100.0)
+    xo, vo, _, _ = oracle.vv(x, v, L, 8, dt=10.0, thermostat=2, T0=T0[0], tau=100.0)
+    xb, vb = from_dev(xd), from_dev(vd)
+    assert np.abs(min_image(xb[:n] - xo, L)).max() < 1e-4
+    assert np.abs(vb[:n] - vo).max() < 1e-4 * np.abs(vo).max()
+    ctx.step(xd, vd, 32, thermostat=sw.SW_BERENDSEN, T0=T0, tau_fs=100.0)
+    assert ctx.query(sw.SW_Q_REBUILDS) - r0 >= 5 * R
+    xb, vb = from_dev(xd), from_dev(vd)
+    for r in (0, 9, 15):
+        c1 = make_ctx(x, L)
+        x1, v1 = to_dev(x), to_dev(v)
+        c1.step(x1, v1, 8, thermostat=sw.SW_BERENDSEN, T0=[T0[r]], tau_fs=100.0)
+        c1.step(x1, v1, 32, thermostat=sw.SW_BERENDSEN, T0=[T0[r]], tau_fs=100.0)
+        assert np.array_equal(from_dev(x1), xb[r * n:(r + 1) * n]), r
+        assert np.array_equal(from_dev(v1), vb[r * n:(r + 1) * n]), r
+
+
 def test_replicas_evolve_independently():
     """Each replica of a batched context equals the same replica run alone."""
     from paper_0809_2811_amd import sw
