@@ -98,6 +98,7 @@ hipError_t alloc_capacity(sw_ctx* c) {
   free_list(c, c->grow_allocs);
   hipError_t e;
   if ((e = dalloc(c, &c->d.nl, (size_t)c->npad * c->cap, c->grow_allocs)) != hipSuccess) return e;
+  if ((e = dalloc(c, &c->d.act, (size_t)c->npad * c->cap, c->grow_allocs)) != hipSuccess) return e;
   for (int k = 0; k < 2; ++k)
     if ((e = dalloc(c, &c->d.gmem[k], (size_t)c->ctot * c->cc, c->grow_allocs)) != hipSuccess) return e;
   c->d.cap = c->cap;
@@ -113,7 +114,7 @@ hipError_t alloc_all(sw_ctx* c) {
 #define SWA(ptr, n) \
   if ((e = dalloc(c, &(ptr), (n), L)) != hipSuccess) return e
   SWA(c->d.u[0], np); SWA(c->d.u[1], np); SWA(c->d.v, np); SWA(c->d.f, np); SWA(c->d.uref, np);
-  SWA(c->d.ids, np); SWA(c->d.nn, np); SWA(c->d.mom, 3 * np);
+  SWA(c->d.ids, np); SWA(c->d.nn, np); SWA(c->d.nact, np); SWA(c->d.mom, 3 * np);
   SWA(c->d.gcnt[0], (size_t)c->ctot); SWA(c->d.gcnt[1], (size_t)c->ctot);
   SWA(c->d.partial, (np / kMinAPB + 1) * kNQ);   // one slot per block and quantity
   SWA(c->d.thermo_cur, (size_t)c->R * kNQ);

@@ -11,6 +11,9 @@
 //   ids[Npad]         int     caller index of internal atom i (-1 for padding)
 //   nl[Npad][cap]     int     neighbour rows (internal indices, ascending)
 //   nn[Npad]          int     row lengths
+//   act[Npad][cap]    int     with 8 or fewer lanes per atom: the row's entries within the
+//                             cutoff at the last moments launch, in row order
+//   nact[Npad]        int     their number
 //   mom[Npad][3]      float4  per-centre three-body moments and energies
 //   gcnt[2][Ctot], gmem[2][Ctot][cc]   binning cells (ping-pong), positions with
 //                                      the internal index in .w
@@ -89,6 +92,9 @@ struct Dev {
   double* lref;        // [R] box edge 0 at the replica's last row build
   int npad, cap, cc, ctot, R;
   int max_rep_pad;     // largest padded replica size (atoms)
+  // last, so the fields every kernel reads keep their argument offsets
+  int* act;            // [Npad][cap] entries within the cutoff (8 or fewer lanes per atom)
+  int* nact;           // [Npad]
 };
 
 // Per-call physical constants, pre-folded for the kernels.

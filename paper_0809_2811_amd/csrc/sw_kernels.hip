@@ -478,6 +478,17 @@ __device__ void moments_tile(const Dev& d, const Phys& p, int par, int force_reb
   float dT0 = 0.f, dT1 = 0.f, dT2 = 0.f, dT3 = 0.f, dT4 = 0.f, dT5 = 0.f, dV0 = 0.f, dV1 = 0.f, dV2 = 0.f, dS = 0.f;
   const float4 wi = TAN ? tw[i] : make_float4(0.f, 0.f, 0.f, 0.f);
   const uint4* upm = pick(d.u, par);
+  // With 8 or fewer lanes per atom the entries within the cutoff are also
+  // written out, in row order, as the force kernel's row: a row holds ~40 %
+  // more entries than the cutoff sphere, and the force loop then runs one
+  // batch of slots instead of two.  The order follows from a group ballot per
+  // slot batch (a lane that leaves the loop early has no entry left).
+  constexpr bool kAct = LPA <= 8;
+  int* act_row = d.act + (size_t)i * cap;
+  const int wla = threadIdx.x & 63;
+  const unsigned long long amask = LPA == 64 ? ~0ull : ((1ull << (LPA & 63)) - 1) << (wla & ~(LPA - 1));
+  const unsigned long long abelow = (1ull << wla) - 1;
+  int nact = 0;
   // pipelined like the force loop: a batch of slots' positions, then the
   // arithmetic, with the next batch's slots read in between
   for (int s0 = lane; s0 < nn; s0 += kMU * LPA) {
@@ -502,6 +513,12 @@ __device__ void moments_tile(const Dev& d, const Phys& p, int par, int force_reb
     for (int u = 0; u < kMU; ++u) {
       const float3 dd = disp(ui, uu[u], sc0, sc1, sc2);
       const float r2 = dd.x * dd.x + dd.y * dd.y + dd.z * dd.z;
+      if (kAct) {
+        const bool in = jj[u] >= 0 && r2 < p.rc2;
+        const unsigned long long m = __ballot(in) & amask;
+        if (in) act_row[nact + __popcll(m & abelow)] = jj[u];
+        nact += __popcll(m);
+      }
       if (jj[u] >= 0 && r2 < p.rc2) {
         const float ir = rsq(r2);
         const float ux = dd.x * ir, uy = dd.y * ir, uz = dd.z * ir;
@@ -544,6 +561,7 @@ __device__ void moments_tile(const Dev& d, const Phys& p, int par, int force_reb
     m[0] = make_float4(T0, T1, T2, T3);
     m[1] = make_float4(T4, T5, V0, V1);
     m[2] = make_float4(V2, S, E2, E3);
+    if (kAct) d.nact[i] = nact;
   }
   if (TAN) {
     dT0 = group_sum<LPA>(dT0); dT1 = group_sum<LPA>(dT1); dT2 = group_sum<LPA>(dT2);
@@ -620,13 +638,14 @@ __device__ void forces_tile(const Dev& d, const Phys& p, int par, int bid) {
   // of independent loads before any arithmetic.  The per-lane order of
   // neighbours is the plain stride order.
   constexpr int kFU = LPA >= 32 ? 1 : 2;   // a batch spans at most 32 slots (one row line)
+  constexpr bool kAct = LPA <= 8;          // the moments launch's rows of entries within the cutoff
   const int cap = d.cap;
-  const int* row = d.nl + (size_t)i * cap;
+  const int* row = (kAct ? d.act : d.nl) + (size_t)i * cap;
   const uint4* up = pick(d.u, par);
   const uint4 ui = up[i];
   const float4* m = d.mom + 3 * (size_t)i;
   const float4 ma = m[0], mb = m[1], mc = m[2];
-  const int nn_row = d.nn[i];
+  const int nn_row = kAct ? d.nact[i] : d.nn[i];
   int jn[kFU];
 #pragma unroll
   for (int u = 0; u < kFU; ++u) jn[u] = row[min(lane + u * LPA, cap - 1)];
