@@ -36,7 +36,10 @@ PEAK_HBM = 8.0e12
 # including 4 transcendentals; per row entry beyond a sigma 14 flop (distance
 # test); per atom 30 flop (group reduction, two half-kicks, drift).  Bytes per
 # atom: own position, own moments, row length and row, force, velocity in and
-# out, new position, binning slot: 16+48+4+4*row+16+32+16+8.
+# out, new position, binning slot: 16+48+4+4*row+16+32+16+8.  With 8 or fewer
+# lanes per atom the kernel reads the moments launch's list of the entries
+# within the cutoff instead of the row (4 + 4*active bytes, no inactive
+# entries), and the moments launch writes that list (4 + 4*active more).
 FLOP_PER_ACTIVE = 120.0
 FLOP_PER_INACTIVE = 14.0
 FLOP_PER_ATOM = 30.0
@@ -61,21 +64,23 @@ def expected_counts(rho_gcc, skin):
     return act, row
 
 
-def force_kernel_work(n_atoms, rho_gcc, skin):
+def force_kernel_work(n_atoms, rho_gcc, skin, lpa=32):
     act, row = expected_counts(rho_gcc, skin)
-    flop = n_atoms * (act * FLOP_PER_ACTIVE + (row - act) * FLOP_PER_INACTIVE + FLOP_PER_ATOM)
-    bytes_ = n_atoms * (16 + 48 + 4 + 4 * row + 16 + 32 + 16 + 8)
+    listed = act if lpa <= 8 else row
+    flop = n_atoms * (act * FLOP_PER_ACTIVE + (listed - act) * FLOP_PER_INACTIVE + FLOP_PER_ATOM)
+    bytes_ = n_atoms * (16 + 48 + 4 + 4 * listed + 16 + 32 + 16 + 8)
     return flop, bytes_
 
 
-def moments_kernel_work(n_atoms, rho_gcc, skin, box, rebuild_frac):
+def moments_kernel_work(n_atoms, rho_gcc, skin, box, rebuild_frac, lpa=32):
     """Average over launches; rebuild_frac of them rebuild the rows."""
     act, row = expected_counts(rho_gcc, skin)
     ncell = [max(3, int(np.floor(b / (RC + skin)))) for b in np.atleast_1d(box) * np.ones(3)]
     cand = 27.0 * number_density(rho_gcc) * np.prod([b / c for b, c in zip(np.atleast_1d(box) * np.ones(3), ncell)])
     flop = n_atoms * (act * MOM_FLOP_PER_ACTIVE + (row - act) * FLOP_PER_INACTIVE + MOM_FLOP_PER_ATOM
                       + rebuild_frac * cand * REBUILD_FLOP_PER_CAND)
-    bytes_ = n_atoms * (16 + 4 + 4 * row + 48 + rebuild_frac * (16 + 4 * row + 4 + 16))
+    bytes_ = n_atoms * (16 + 4 + 4 * row + 48 + rebuild_frac * (16 + 4 * row + 4 + 16)
+                        + (4 + 4 * act if lpa <= 8 else 0))
     return flop, bytes_
 
 
@@ -161,8 +166,8 @@ def kernel_roofline(kernel, flop, bytes_, kernel_us, workload):
 def step_rooflines(n_atoms, rho, skin, box, res, steps, lpa, workload):
     """Both kernels of the step; the dominant one (longest average launch)
     becomes the line's roofline, the other is kept under "other"."""
-    ff, fb = force_kernel_work(n_atoms, rho, skin)
-    mf, mb = moments_kernel_work(n_atoms, rho, skin, box, min(1.0, res["rebuilds"] / max(steps, 1)))
+    ff, fb = force_kernel_work(n_atoms, rho, skin, lpa)
+    mf, mb = moments_kernel_work(n_atoms, rho, skin, box, min(1.0, res["rebuilds"] / max(steps, 1)), lpa)
     kf = kernel_roofline(f"k_forces<{lpa}, 2, false>", ff, fb, res["forces_us"], workload)
     km = kernel_roofline(f"k_moments<{lpa}, false>", mf, mb, res["moments_us"], workload)
     dom, other = (kf, km) if res["forces_us"] >= res["moments_us"] else (km, kf)
