@@ -49,7 +49,7 @@ def best(n_atoms: int, rho: float = 1.0, skin: float | None = None, arch: str | 
     """Tuning for a box of n_atoms at rho.  With skin=None the entry also
     carries the best skin ("skin" key); with a fixed skin, the whole winning
     form (lanes per atom and launch form) if it is the winner's skin, else the
-    best lanes per atom for that skin."""
+    best lanes per atom for that skin with the winner's launch form."""
     key = f"{arch or 'gfx950'}/{'replicas' if replicas else bucket(n_atoms, rho)}"
     out = dict(DEFAULT)
     ent = load_cache().get(key)
@@ -60,10 +60,9 @@ def best(n_atoms: int, rho: float = 1.0, skin: float | None = None, arch: str | 
                 out.pop("skin", None)
         else:
             by = ent.get("by_skin", {}).get(f"{skin:.2f}")
-            if by:
-                out["lanes_per_atom"] = by["lanes_per_atom"]
-            else:
-                out["lanes_per_atom"] = ent["best"]["lanes_per_atom"]
+            out["lanes_per_atom"] = (by or ent["best"])["lanes_per_atom"]
+            for k in ("persistent", "graph_steps"):
+                out[k] = ent["best"].get(k, out[k])
     return out
 
 
