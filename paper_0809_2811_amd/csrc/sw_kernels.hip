@@ -486,8 +486,9 @@ __device__ void moments_tile(const Dev& d, const Phys& p, int par, int force_reb
   constexpr bool kAct = LPA <= 8;
   int* act_row = d.act + (size_t)i * cap;
   const int wla = threadIdx.x & 63;
-  const unsigned long long amask = LPA == 64 ? ~0ull : ((1ull << (LPA & 63)) - 1) << (wla & ~(LPA - 1));
-  const unsigned long long abelow = (1ull << wla) - 1;
+  const int ash = wla & ~(LPA - 1);                          // the group's first lane
+  const unsigned amask = (1u << (kAct ? LPA : 1)) - 1u;      // its bits, shifted down
+  const unsigned abelow = (1u << (wla - ash)) - 1u;          // lanes of the group below this one
   int nact = 0;
   // pipelined like the force loop: a batch of slots' positions, then the
   // arithmetic, with the next batch's slots read in between
@@ -515,9 +516,9 @@ __device__ void moments_tile(const Dev& d, const Phys& p, int par, int force_reb
       const float r2 = dd.x * dd.x + dd.y * dd.y + dd.z * dd.z;
       if (kAct) {
         const bool in = jj[u] >= 0 && r2 < p.rc2;
-        const unsigned long long m = __ballot(in) & amask;
-        if (in) act_row[nact + __popcll(m & abelow)] = jj[u];
-        nact += __popcll(m);
+        const unsigned m = (unsigned)(__ballot(in) >> ash) & amask;
+        if (in) act_row[nact + __builtin_popcount(m & abelow)] = jj[u];
+        nact += __builtin_popcount(m);
       }
       if (jj[u] >= 0 && r2 < p.rc2) {
         const float ir = rsq(r2);
