@@ -345,7 +345,8 @@ def bench_batched(steps=5000, melt_steps=1000, skin=1.0, sequential_steps=500):
     ctx.step(x0, v0, melt_steps, thermostat=sw.SW_RESCALE, T0=[400.0] * len(boxes))
     out = {"workload": f"batched: {len(boxes)} replicas, {n} atoms total (512-8192 each, 0.92-1.05 g/cm^3), "
                        f"melted {melt_steps} steps at 400 K, then Berendsen (tau 1 ps) at 200-320 K, dt=10 fs",
-           "n_atoms": n, "n_replicas": len(boxes), "steps": steps, "unit": "atom-steps/s", "skin_A": skin}
+           "n_atoms": n, "n_replicas": len(boxes), "steps": steps, "unit": "atom-steps/s", "skin_A": skin,
+           "tuning": dict(base)}
     for name, persistent in (("per_phase", 0), ("persistent", 1)):
         ctx.set_tuning(persistent=persistent)
         x, v = x0.clone(), v0.clone()
@@ -458,16 +459,18 @@ def bench_npt(plain_ms_per_step, steps=5000, warm=1000):
     from paper_0809_2811_amd import scan, sw, synth, tune
     x0, v0, L0 = scan.start_liquid(2)
     n = len(x0)
-    out = {"workload": f"npt: {n}-atom liquid at 298 K and p = 0; and 9 replicas of it at 220-320 K",
+    out = {"workload": f"npt: {n}-atom liquid at 298 K and p = 0; and 9 replicas of it at 220-320 K "
+                       "(rows of all replicas rebuilt together when any replica's check fires)",
            "unit": "atom-steps/s"}
     for name, temps in (("single", [298.0]), ("batched", [220, 230, 240, 250, 260, 270, 280, 300, 320])):
         R = len(temps)
         x = torch.from_numpy(synth.to_float4(np.concatenate([x0] * R))).cuda()
         v = torch.from_numpy(synth.to_float4(np.concatenate([v0] * R))).cuda()
         lpa = tune.best(R * n, 1.0, 1.0)["lanes_per_atom"]
-        # captured 50-step blocks: faster for isobaric steps at both sizes (16.9 vs 17.8 us, 37.4 vs 37.9 us)
+        # captured 50-step blocks: faster for isobaric steps at both sizes (16.9 vs 17.8 us, 37.4 vs 37.9 us);
+        # replicas rebuilding together: 36.3 -> 27.7 us per step for the nine
         ctx = sw.Context(np.arange(R + 1) * n, [L0] * R, cutoff=RC, skin=1.0, nbr_capacity=48,
-                         tuning=dict(lanes_per_atom=lpa, graph_steps=50))
+                         tuning=dict(lanes_per_atom=lpa, graph_steps=50, sync_rebuild=int(R > 1)))
         ctx.npt(x, v, warm, T0=temps, reset=True)
         sync()
         t0 = time.perf_counter()
@@ -475,7 +478,7 @@ def bench_npt(plain_ms_per_step, steps=5000, warm=1000):
         sync()
         dt = time.perf_counter() - t0
         out[name] = {"value": R * n * steps / dt, "ms_per_step": dt * 1e3 / steps, "n_atoms": R * n,
-                     "lanes_per_atom": lpa}
+                     "lanes_per_atom": lpa, "sync_rebuild": int(R > 1)}
     out["value"] = out["batched"]["value"]
     out["single_ratio_to_nve_step"] = out["single"]["ms_per_step"] / plain_ms_per_step
     return out

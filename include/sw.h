@@ -281,6 +281,12 @@ typedef struct sw_tuning {
                            their durations to the SW_Q_TIME_* counters (an odd
                            period samples steps of both parities, so rebuild
                            steps are sampled at their own rate)                 */
+  int sync_rebuild;     /* 1: when any replica's displacement check fires, every
+                           replica rebuilds its rows (fewer launches pay for a
+                           rebuild when many replicas share a context; a
+                           replica then no longer equals the same replica run
+                           alone bit for bit, only within rounding); 0: each
+                           replica rebuilds on its own check                   */
 } sw_tuning;
 int sw_set_tuning(sw_ctx* ctx, const sw_tuning* t);
 int sw_get_tuning(const sw_ctx* ctx, sw_tuning* t);

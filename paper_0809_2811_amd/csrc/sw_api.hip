@@ -314,8 +314,8 @@ long long lcm_ll(long long a, long long b) {
 // Captures steps base+1 .. base+K (base a multiple of the pattern period) of
 // the per-phase path into a graph, unless the cached one matches.
 hipError_t ensure_graph(sw_ctx* c, const Phys& ph, int lpa, int K, int thermostat, int every) {
-  std::vector<unsigned char> key(sizeof(Phys) + 6 * sizeof(int));
-  int meta[6] = {K, lpa, thermostat, every, c->tune.rebuild_every, c->alloc_gen};
+  std::vector<unsigned char> key(sizeof(Phys) + 7 * sizeof(int));
+  int meta[7] = {K, lpa, thermostat, every, c->tune.rebuild_every, c->alloc_gen, c->d.sync_rb};
   std::memcpy(key.data(), &ph, sizeof(Phys));
   std::memcpy(key.data() + sizeof(Phys), meta, sizeof meta);
   if (c->gexec && key == c->gkey) return hipSuccess;
@@ -484,7 +484,9 @@ int sw_set_tuning(sw_ctx* ctx, const sw_tuning* t) {
       t->lanes_per_atom != 64)
     return SW_EUNSUPPORTED;
   if (t->graph_steps < 0 || t->rebuild_every < 0 || t->timing < 0 || t->persistent < 0) return SW_EINVAL;
+  if (t->sync_rebuild != 0 && t->sync_rebuild != 1) return SW_EINVAL;
   ctx->tune = *t;
+  ctx->d.sync_rb = t->sync_rebuild;
   ctx->t_mom_ms = ctx->t_for_ms = 0.0;
   ctx->t_samples = 0;
   return SW_OK;

@@ -95,6 +95,7 @@ struct Dev {
   // last, so the fields every kernel reads keep their argument offsets
   int* act;            // [Npad][cap] entries within the cutoff (8 or fewer lanes per atom)
   int* nact;           // [Npad]
+  int sync_rb;         // every replica rebuilds when any replica's flag is set
 };
 
 // Per-call physical constants, pre-folded for the kernels.

@@ -283,8 +283,17 @@ __device__ void moments_tile(const Dev& d, const Phys& p, int par, int force_reb
   const float sc0 = G.sc0, sc1 = G.sc1, sc2 = G.sc2;
   const bool real = i < iend;
   const int nn_row = real ? nn_all : 0;
-  // each replica rebuilds on its own displacement record
-  const bool rebuild = force_rebuild || d.dflag[par * d.R + rep] != 0;
+  // each replica rebuilds on its own displacement record, or (sync_rb) all
+  // replicas when any record is set: one lane per replica, then a ballot
+  bool flagged;
+  if (d.sync_rb) {
+    int f = 0;
+    for (int r = (int)(threadIdx.x & 63); r < d.R; r += 64) f |= d.dflag[par * d.R + r];
+    flagged = __ballot(f != 0) != 0ull;
+  } else {
+    flagged = d.dflag[par * d.R + rep] != 0;
+  }
+  const bool rebuild = force_rebuild || flagged;
   int nn = nn_row;
   bool from_lds = false;                   // row slots name candidate positions in LDS
   const uint4* lds_u = nullptr;

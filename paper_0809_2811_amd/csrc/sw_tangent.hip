@@ -631,6 +631,7 @@ int sw_adjoint(sw_ctx* ctx, const float* x0, const float* v0, const sw_params* p
           dv.gcnt[par] = fs.cnt + (size_t)k * ctx->ctot;
           dv.gmem[par] = fs.cells + (size_t)k * ctx->ctot * ctx->cc;
           dv.dflag = rfl;
+          dv.sync_rb = 0;   // the sweep's own per-replica flags
           const double coef = (sf == S || sf == 0) ? 0.5 * dt : dt;
           // frame sf - 1 is frame k - 1 of this store (a store holds its segment's start)
           const Adj a{xb, vb[cur ^ 1], (float)(coef * c_m), (float)dt, (float)aU, (float)a3, S, sf == 0,

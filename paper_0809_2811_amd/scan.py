@@ -44,7 +44,8 @@ def density_scan(temperatures, reps: int = 2, p_bar: float = 0.0, equil_steps: i
     x = torch.from_numpy(synth.to_float4(np.concatenate(xs))).cuda()
     v = torch.from_numpy(synth.to_float4(np.concatenate(vs))).cuda()
     ctx = sw.Context(np.arange(R + 1) * n, [L0] * R, cutoff=RC, skin=skin, nbr_capacity=48,
-                     tuning=dict(lanes_per_atom=tune.best(R * n, 1.0, skin)["lanes_per_atom"], graph_steps=50))
+                     tuning=dict(lanes_per_atom=tune.best(R * n, 1.0, skin)["lanes_per_atom"], graph_steps=50,
+                                 sync_rebuild=1))   # all replicas rebuild their rows together
     T0 = [float(t) for t in temperatures]
     kw = dict(T0=T0, p_bar=p_bar, tau_T=tau_T, tau_P=tau_P, dt=dt)
     done = 0

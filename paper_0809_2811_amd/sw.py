@@ -52,7 +52,8 @@ class sw_params(ctypes.Structure):
 
 class sw_tuning(ctypes.Structure):
     _fields_ = [("lanes_per_atom", ctypes.c_int), ("graph_steps", ctypes.c_int),
-                ("persistent", ctypes.c_int), ("rebuild_every", ctypes.c_int), ("timing", ctypes.c_int)]
+                ("persistent", ctypes.c_int), ("rebuild_every", ctypes.c_int), ("timing", ctypes.c_int),
+                ("sync_rebuild", ctypes.c_int)]
 
 
 class SWError(RuntimeError):
@@ -308,8 +309,10 @@ def sw_npt_state(ctx: int, R: int = 1, state=None):
     return st
 
 
-def sw_set_tuning(ctx: int, lanes_per_atom=8, graph_steps=0, persistent=0, rebuild_every=0, timing=0):
-    t = sw_tuning(int(lanes_per_atom), int(graph_steps), int(persistent), int(rebuild_every), int(timing))
+def sw_set_tuning(ctx: int, lanes_per_atom=8, graph_steps=0, persistent=0, rebuild_every=0, timing=0,
+                  sync_rebuild=0):
+    t = sw_tuning(int(lanes_per_atom), int(graph_steps), int(persistent), int(rebuild_every), int(timing),
+                  int(sync_rebuild))
     _check(lib().sw_set_tuning(ctypes.c_void_p(ctx), ctypes.byref(t)), "sw_set_tuning")
 
 
@@ -317,7 +320,7 @@ def sw_get_tuning(ctx: int) -> dict:
     t = sw_tuning()
     _check(lib().sw_get_tuning(ctypes.c_void_p(ctx), ctypes.byref(t)), "sw_get_tuning")
     return dict(lanes_per_atom=t.lanes_per_atom, graph_steps=t.graph_steps, persistent=t.persistent,
-                rebuild_every=t.rebuild_every, timing=t.timing)
+                rebuild_every=t.rebuild_every, timing=t.timing, sync_rebuild=t.sync_rebuild)
 
 
 def sw_query(ctx: int, what: int) -> int:

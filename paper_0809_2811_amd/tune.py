@@ -2,8 +2,9 @@
 
 Search space: lanes of a wavefront per atom (4, 8, 16, 32, 64; the sw_tuning block of
 include/sw.h), the Verlet skin (a context parameter: longer rows against
-fewer rebuilds) and the launch form (one launch per phase or the persistent
-cooperative kernel).  `search()` times short NVE runs of a synthetic 298 K
+fewer rebuilds), the launch form (one launch per phase, the persistent
+cooperative kernel or captured blocks) and, for the replica table, whether
+all replicas rebuild their rows together.  `search()` times short NVE runs of a synthetic 298 K
 liquid for every candidate on the current GPU, `search_replicas()` times
 Berendsen runs of the uneven replica table; the winners are written to
 tuning_cache.json next to this file, keyed by (arch, atom-count bucket,
@@ -20,7 +21,7 @@ import pathlib
 import time
 
 CACHE = pathlib.Path(__file__).resolve().parent / "tuning_cache.json"
-DEFAULT = dict(lanes_per_atom=8, graph_steps=0, persistent=0, rebuild_every=0, timing=0)
+DEFAULT = dict(lanes_per_atom=8, graph_steps=0, persistent=0, rebuild_every=0, timing=0, sync_rebuild=0)
 RC = 1.8 * 2.3925
 
 
@@ -61,7 +62,7 @@ def best(n_atoms: int, rho: float = 1.0, skin: float | None = None, arch: str | 
         else:
             by = ent.get("by_skin", {}).get(f"{skin:.2f}")
             out["lanes_per_atom"] = (by or ent["best"])["lanes_per_atom"]
-            for k in ("persistent", "graph_steps"):
+            for k in ("persistent", "graph_steps", "sync_rebuild"):
                 out[k] = ent["best"].get(k, out[k])
     return out
 
@@ -150,8 +151,15 @@ def search_replicas(steps: int = 300, skin: float = 1.0, write: bool = True):
             results.append(dict(skin=skin, lanes_per_atom=lpa, persistent=persistent, graph_steps=graph_steps,
                                 s_per_step=dt))
     win = min(results, key=lambda r: r["s_per_step"])
+    # all replicas rebuilding together whenever one needs it, at the winning point
+    ctx = sw.Context(off, boxes, cutoff=RC, skin=skin, nbr_capacity=48,
+                     tuning=dict(DEFAULT, lanes_per_atom=win["lanes_per_atom"], persistent=win["persistent"],
+                                 graph_steps=win["graph_steps"], sync_rebuild=1))
+    dt = _timed(ctx, x0.clone(), v0.clone(), steps, thermostat=sw.SW_BERENDSEN, T0=T, tau_fs=1000.0)
+    results.append(dict(win, sync_rebuild=1, s_per_step=dt))
+    win = min(results, key=lambda r: r["s_per_step"])
     entry = dict(best=dict(lanes_per_atom=win["lanes_per_atom"], skin=skin, persistent=win["persistent"],
-                           graph_steps=win["graph_steps"]),
+                           graph_steps=win["graph_steps"], sync_rebuild=win.get("sync_rebuild", 0)),
                  s_per_step=win["s_per_step"], by_skin={f"{skin:.2f}": dict(lanes_per_atom=win["lanes_per_atom"],
                                                                          s_per_step=win["s_per_step"])},
                  n_atoms=int(off[-1]), candidates=results)

@@ -232,6 +232,38 @@ def test_large_context_thermostat_binning_keeps_replicas_exact():
         assert np.array_equal(from_dev(v1), vb[r * n:(r + 1) * n]), r
 
 
+def test_synchronised_rebuilds_keep_every_replica_on_the_oracle():
+    """sync_rebuild: every replica rebuilds its rows whenever any replica's
+    check fires (rows are still supersets of the cutoff sphere, so only the
+    summation order can change): each replica follows the oracle over 8
+    Berendsen steps, and every row rebuild counted is a rebuild of all
+    replicas."""
+    from paper_0809_2811_amd import sw
+    specs = [((4, 4, 4), 1.0, 300.0), ((3, 4, 5), 0.93, 250.0), ((4, 5, 5), 1.05, 220.0)]
+    xs, vs, boxes = [], [], []
+    for k, (cells, rho, T) in enumerate(specs):
+        d = synth.lattice_at_density(cells, rho, sigma=0.2, temperature=T, seed=40 + k)
+        xs.append(f32(d["x"])); vs.append(f32(d["v"])); boxes.append(d["box"])
+    offsets = np.cumsum([0] + [len(x) for x in xs])
+    ctx = make_ctx(np.concatenate(xs), None, offsets=offsets, boxes=boxes, sync_rebuild=1)
+    assert ctx.tuning()["sync_rebuild"] == 1
+    xd, vd = to_dev(np.concatenate(xs)), to_dev(np.concatenate(vs))
+    T0 = [s[2] for s in specs]
+    ctx.step(xd, vd, 8, thermostat=sw.SW_BERENDSEN, T0=T0, tau_fs=100.0)
+    xb, vb = from_dev(xd), from_dev(vd)
+    for r in range(len(specs)):
+        a, b = offsets[r], offsets[r + 1]
+        xo, vo, _, _ = oracle.vv(xs[r], vs[r], boxes[r], 8, dt=10.0, thermostat=2, T0=T0[r], tau=100.0)
+        assert np.abs(min_image(xb[a:b] - xo, boxes[r])).max() < 1e-4, r
+        assert np.abs(vb[a:b] - vo).max() < 1e-4 * np.abs(vo).max(), r
+    # 30 more steps: the call's opening build plus at least one fired check,
+    # each a rebuild of every replica
+    r0 = ctx.query(sw.SW_Q_REBUILDS)
+    ctx.step(xd, vd, 30, thermostat=sw.SW_BERENDSEN, T0=T0, tau_fs=100.0)
+    nrb = ctx.query(sw.SW_Q_REBUILDS) - r0
+    assert nrb >= 2 * len(specs) and nrb % len(specs) == 0, nrb
+
+
 def test_replicas_evolve_independently():
     """Each replica of a batched context equals the same replica run alone."""
     from paper_0809_2811_amd import sw
