@@ -75,3 +75,29 @@ def test_null_arguments_rejected():
     assert L.sw_step(None, None, None, None, None, 18.0, 10.0, 1, 0, None, 1.0, None, 1, None) == sw.SW_EINVAL
     assert L.sw_query(None, 0, None) == sw.SW_EINVAL
     L.sw_destroy(None)
+
+
+def _struct_fields(name):
+    """(type, field) pairs of `typedef struct name { ... } name;` in include/sw.h."""
+    text = (ROOT / "include" / "sw.h").read_text()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    body = re.search(r"typedef struct %s\s*\{(.*?)\}\s*%s;" % (name, name), text, flags=re.S).group(1)
+    out = []
+    for ct, names in re.findall(r"\b(int|double|float|long long)\s+([\w\s,]+);", body):
+        out += [(ct, n.strip()) for n in names.split(",")]
+    return out
+
+
+@pytest.mark.parametrize("name", ["sw_params", "sw_tuning"])
+def test_binding_structs_match_the_header(name):
+    """The ctypes mirrors of the ABI's structs have the header's fields, in
+    order, with the same C types and size."""
+    ctype = {"int": ctypes.c_int, "double": ctypes.c_double, "float": ctypes.c_float,
+             "long long": ctypes.c_longlong}
+    header = _struct_fields(name)
+    py = getattr(sw, name)._fields_
+    assert len(header) == len(py) and len(header) > 0
+    for (ct, fname), (pname, ptype) in zip(header, py):
+        assert ptype is ctype[ct], (fname, ct, ptype)
+        assert pname.rstrip("_") == fname, (fname, pname)
+    assert ctypes.sizeof(getattr(sw, name)) == sum(ctypes.sizeof(ctype[t]) for t, _ in header)
