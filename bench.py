@@ -178,6 +178,32 @@ def step_rooflines(n_atoms, rho, skin, box, res, steps, lpa, workload):
     return line
 
 
+def launch_floor_us(n=200, reps=5):
+    """What one launch costs on this GPU with almost no work in it: a plain
+    elementwise add over 131072 floats, n launches captured in a graph and
+    replayed (the step kernels are replayed the same way); microseconds per
+    launch.  Context for the step kernels' durations, which sit close to a
+    few of these."""
+    import torch
+    t = torch.zeros(1 << 17, device="cuda")
+    st = torch.cuda.Stream()
+    with torch.cuda.stream(st):
+        for _ in range(3):
+            t.add_(1.0)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=st):
+        for _ in range(n):
+            t.add_(1.0)
+    g.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        g.replay()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / (reps * n) * 1e6
+
+
 def cpu_baseline(target_s=15.0):
     """The FP64 oracle (single thread) on a 4096-atom 298 K liquid: the
     oracle-made 512-atom liquid tiled 2x2x2 and perturbed by 0.02 A."""
@@ -257,6 +283,7 @@ def main():
     if "forces_us" in res:
         line["roofline"] = step_rooflines(n, 1.0, args.skin, cfg["box"], res, args.steps,
                                           tuning["lanes_per_atom"], "liquid4096")
+        line["roofline"]["launch_floor_us"] = launch_floor_us()
     forms = [f for f in args.forms.split(",") if f and f != "none"]
     line["forms"] = {}
     if "large" in forms:
