@@ -60,6 +60,31 @@ def test_npt_large_replica_sums_match_oracle():
         assert np.allclose(r[:, k], o["rows"][:, k], rtol=tol, atol=0), (k, r[:, k], o["rows"][:, k])
 
 
+def test_npt_synchronised_rebuilds_match_oracle_per_replica():
+    """Three replicas with sync_rebuild (every replica rebuilds its rows when
+    any check fires, as the isobaric bench form and the density scan run):
+    each follows the NPT oracle over 10 steps at its own temperature and
+    pressure, and every counted rebuild is a rebuild of all three."""
+    from paper_0809_2811_amd import sw
+    x, v, L = liquid(1, sigma=0.0)
+    x, v = f32(x), f32(v)
+    n, R = len(x), 3
+    T0, P = [250.0, 298.0, 330.0], [0.0, 500.0, 1000.0]
+    ctx = sw.Context(np.arange(R + 1) * n, [L] * R, cutoff=RC, skin=0.5, nbr_capacity=64,
+                     tuning=dict(lanes_per_atom=8, sync_rebuild=1))
+    xd, vd = to_dev(np.tile(x, (R, 1))), to_dev(np.tile(v, (R, 1)))
+    r0 = ctx.query(sw.SW_Q_REBUILDS)
+    ctx.npt(xd, vd, 10, T0=T0, p_bar=P, tau_T=200.0, tau_P=500.0, chain=3, reset=True)
+    nrb = ctx.query(sw.SW_Q_REBUILDS) - r0
+    assert nrb >= 2 * R and nrb % R == 0, nrb
+    xg, vg = from_dev(xd), from_dev(vd)
+    for r in range(R):
+        o = oracle.npt(x, v, L, 10, T0=T0[r], p_bar=P[r], tau_T=200.0, tau_P=500.0, chain=3)
+        assert np.allclose(ctx.box[r], o["box"], rtol=2e-6, atol=0), r
+        assert np.abs(min_image(xg[r * n:(r + 1) * n] - o["x"], o["box"])).max() < 1e-4, r
+        assert np.abs(vg[r * n:(r + 1) * n] - o["v"]).max() < 1e-4 * np.abs(o["v"]).max(), r
+
+
 def test_npt_mixed_replica_sizes_are_independent():
     """A 512-atom replica (kick-summed) beside a 4096-atom one (1024 force
     blocks at 64 lanes per atom: reduction launch) gives the same bits as the
