@@ -233,3 +233,32 @@ def test_captured_adjoint_replays_equal_plain_launches():
             assert np.array_equal(got[k], ref[(S, K)][k]), (S, K, k)
         graph.step(xw, vw, 3)          # other work on the same context between replays
         torch.cuda.synchronize()
+
+
+def test_adjoint_with_synchronised_rebuilds_per_replica():
+    """Three replicas in one context with sync_rebuild (the forward run and
+    its recomputes rebuild every replica's rows together; the reverse sweep
+    keeps its own per-replica flags): each replica's loss and gradients follow
+    the oracle's adjoint, and the results stay bitwise independent of the
+    checkpoint interval."""
+    from paper_0809_2811_amd import sw
+    x, v, L = liquid(1, sigma=0.0)
+    x, v = f32(x), f32(v)
+    n, R, S = len(x), 3, 8
+    scale = np.array([1.0, 0.97, 1.03], dtype=np.float32)
+    vs = [f32(v * s) for s in scale]          # three replicas at different temperatures
+    ctx = sw.Context(np.arange(R + 1) * n, [L] * R, cutoff=RC, skin=0.5, nbr_capacity=48,
+                     tuning=dict(lanes_per_atom=8, sync_rebuild=1))
+    res = {}
+    for K in (4, 8):
+        r = ctx.adjoint(to_dev(np.tile(x, (R, 1))), to_dev(np.concatenate(vs)), S, ckpt_every=K)
+        res[K] = {k: r[k].cpu().numpy() for k in ("loss", "thbar", "xbar0", "vbar0", "xS", "vS")}
+    for k in res[4]:
+        assert np.array_equal(res[4][k], res[8][k]), k
+    g = res[4]
+    for r in range(R):
+        o = oracle.adjoint(x, vs[r], L, S)
+        assert abs(g["loss"][r] - o["loss"]) <= 1e-5 * abs(o["loss"]), r
+        assert np.allclose(g["thbar"][r], o["thbar"], rtol=1e-4, atol=0), (r, g["thbar"][r], o["thbar"])
+        assert rel_err(g["xbar0"][r * n:(r + 1) * n, :3].astype(np.float64), o["xbar0"]) <= 1e-3, r
+        assert rel_err(g["vbar0"][r * n:(r + 1) * n, :3].astype(np.float64), o["vbar0"]) <= 1e-3, r
