@@ -8,8 +8,11 @@ present, the calls raise.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import pathlib
+import sys
+import weakref
 from typing import Optional, Sequence
 
 import numpy as np
@@ -330,8 +333,29 @@ def sw_query(ctx: int, what: int) -> int:
 
 
 # ------------------------------------------------------------------ convenience
+# Contexts still open, destroyed by close_all() when the interpreter exits.
+_live: "weakref.WeakSet[Context]" = weakref.WeakSet()
+
+
+def close_all():
+    """Destroy every open context now, newest first.  Registered with atexit,
+    so that sw_destroy (graph, stream and device-memory release) runs while
+    the HIP runtime is still up, before interpreter shutdown collects the
+    remaining objects in no fixed order."""
+    for c in sorted(list(_live), key=lambda c: -c._serial):
+        c.close()
+
+
+atexit.register(close_all)
+_serial = [0]
+
+
 class Context:
-    """Owns one sw_ctx.  offsets: int[R+1]; boxes: [R,3] (A)."""
+    """Owns one sw_ctx.  offsets: int[R+1]; boxes: [R,3] (A).
+
+    Use it as a context manager (`with Context(...) as c:`) or call close();
+    contexts left open are destroyed at interpreter exit by close_all(), and
+    never from a finaliser during interpreter shutdown."""
 
     def __init__(self, offsets, boxes, cutoff: Optional[float] = None, skin: float = 1.0,
                  nbr_capacity: int = 48, tuning: Optional[dict] = None):
@@ -344,15 +368,31 @@ class Context:
         self.n = int(self.offsets[-1])
         self.cutoff, self.skin = float(cutoff), float(skin)
         self.handle = sw_create(self.offsets, self.boxes, cutoff, skin, nbr_capacity)
+        _serial[0] += 1
+        self._serial = _serial[0]
+        _live.add(self)
         if tuning:
             self.set_tuning(**tuning)
 
     def close(self):
+        """Release the device context (idempotent)."""
         if getattr(self, "handle", None):
-            sw_destroy(self.handle)
-            self.handle = None
+            h, self.handle = self.handle, None
+            _live.discard(self)
+            sw_destroy(h)
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+        return False
 
     def __del__(self):
+        # A context dropped during interpreter shutdown is left to the
+        # process exit: the HIP runtime may already be finalising.
+        if sys is None or sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:

@@ -178,3 +178,26 @@ def test_parameters_other_than_mw():
         g = gpu_forces(x, L, P=sw.params_from_array(P))
         o = oracle.forces(x, L, P)
         assert force_error(g["F"], o["F"]) <= TOL
+
+
+@pytest.mark.parametrize("lpa", [8, 32])
+def test_clusters_against_closed_forms(lpa):
+    """Three-atom clusters (Sec. II.A, Eq. phi3): the equilateral and linear
+    clusters at r = 3.0 A against the stored closed-form energies, and an
+    unequal-leg cluster (legs 2.7 and 3.6 A at 140 deg, one vertex) against the
+    oracle, through sw_forces in a 16 A box (three cells of cutoff + skin)."""
+    from tests.test_oracle_cluster_pins import equilateral, golden, linear, vee
+    g = golden()
+    L = np.array([16.0, 16.0, 16.0])
+    for name, x in (("equilateral", equilateral(3.0)), ("linear", linear(3.0)), ("vee", vee(2.7, 3.6, 140.0))):
+        x = f32(x)
+        out = gpu_forces(x, L, lpa=lpa, skin=0.5)
+        o = oracle.forces(x, L)
+        if name != "vee":
+            for k, col in (("E2", 0), ("E3", 1)):
+                want = g[f"{name}_{k}"][1]
+                assert abs(out["E"][0, col] - want) <= TOL * abs(want), (name, k, out["E"][0, col], want)
+        assert abs(out["E"][0, 0] - o["E2"]) <= TOL * abs(o["E2"])
+        assert abs(out["E"][0, 1] - o["E3"]) <= TOL * abs(o["E3"])
+        assert force_error(out["F"], o["F"]) <= TOL, name
+        out["ctx"].close()
