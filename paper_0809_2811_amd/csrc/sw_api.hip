@@ -281,7 +281,7 @@ hipError_t sort_in(sw_ctx* c, const float* x, const float* v, hipStream_t s) {
                              c->d_uq, c->d_key, c->d_scnt, c->d_sstart, c->d_scur, c->d_order, s);
   if (e != hipSuccess) return e;
   if ((e = launch_fill_i32(c->d.gcnt[0], 0, c->ctot, s)) != hipSuccess) return e;
-  if ((e = launch_bin(c->d, 0, 0, 0.f, s)) != hipSuccess) return e;
+  if ((e = launch_bin(c->d, 0, 0, 0.f, 0.f, s)) != hipSuccess) return e;
   c->have_order = true;
   return hipSuccess;
 }
@@ -560,7 +560,7 @@ int sw_forces(sw_ctx* ctx, const float* x, const sw_params* params, float* f, do
     } else {
       if ((e = launch_gather_ids(ctx->d, (const float4*)x, 0, s)) != hipSuccess) return fail_hip(ctx, e);
       if ((e = launch_fill_i32(ctx->d.gcnt[0], 0, ctx->ctot, s)) != hipSuccess) return fail_hip(ctx, e);
-      if ((e = launch_bin(ctx->d, 0, 1, ph.half_skin, s)) != hipSuccess) return fail_hip(ctx, e);
+      if ((e = launch_bin(ctx->d, 0, 1, (float)(ctx->cutoff + ctx->skin), ph.rc, s)) != hipSuccess) return fail_hip(ctx, e);
     }
     const int lpa = lpa_for(ctx);
     if ((e = launch_moments(ctx->d, ph, lpa, 0, force_rebuild, 1, s)) != hipSuccess) return fail_hip(ctx, e);

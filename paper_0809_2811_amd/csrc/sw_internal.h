@@ -173,7 +173,9 @@ hipError_t launch_sort(const Dev& d, const float4* x_user, const float4* v_user,
                        const long long* uoff, int R, const int* cell_rank, uint4* uq, int* key,
                        int* cnt, int* start, int* cursor, int* order, hipStream_t s);
 hipError_t launch_gather_ids(const Dev& d, const float4* x_user, int par, hipStream_t s);
-hipError_t launch_bin(const Dev& d, int par, int check_disp, float half_skin, hipStream_t s);
+// Bins u[par] into grid par; with check_disp, flags replicas with an atom too far from its
+// row-build position for rows of radius rl (in the box of the build) to cover rc.
+hipError_t launch_bin(const Dev& d, int par, int check_disp, float rl, float rc, hipStream_t s);
 hipError_t launch_moments(const Dev& d, const Phys& p, int lpa, int par, int force_rebuild,
                           int energy, hipStream_t s, const KTimer& tm = KTimer());
 hipError_t launch_forces(const Dev& d, const Phys& p, int lpa, int mode, int vir, int par,

@@ -215,9 +215,12 @@ __global__ __launch_bounds__(kBlock) void k_gather_ids(Dev d, const float4* __re
 }
 
 // Bin positions u[par] into grid `par` (counts must be zero) and, if asked,
-// raise the replica's rebuild flag for atoms beyond half_skin of their
-// row-build position.
-__global__ __launch_bounds__(kBlock) void k_bin(Dev d, int par, int check, float half_skin) {
+// raise the replica's rebuild flag for atoms that moved too far from their
+// row-build position.  Rows hold every atom within rl of the build position
+// in the box of that build (edge lref); a box scaled since then (isobaric
+// steps) scales those distances by s = L / lref, so an atom may move
+// (s rl - rc) / 2 in the current box before a pair inside rc can be missing.
+__global__ __launch_bounds__(kBlock) void k_bin(Dev d, int par, int check, float rl, float rc) {
   const int i = blockIdx.x * kBlock + threadIdx.x;
   if (i < d.npad) {
     const int rep = d.tile_rep[i >> 6];
@@ -229,8 +232,9 @@ __global__ __launch_bounds__(kBlock) void k_bin(Dev d, int par, int check, float
       if (slot < d.cc) d.gmem[par][(size_t)c * d.cc + slot] = make_uint4(u.x, u.y, u.z, (unsigned)i);
       else atomicOr(&d.flags[F_CELL_OVER], 1);
       if (check) {
+        const float hs = (float)(0.5 * (R.L[0] / d.lref[rep] * rl - rc) - 1e-4);
         const float3 dd = disp(d.uref[i], u, R.scale[0], R.scale[1], R.scale[2]);
-        if (dd.x * dd.x + dd.y * dd.y + dd.z * dd.z > half_skin * half_skin) d.dflag[par * d.R + rep] = 1;
+        if (!(hs > 0.f) || dd.x * dd.x + dd.y * dd.y + dd.z * dd.z > hs * hs) d.dflag[par * d.R + rep] = 1;
       }
     }
   }
@@ -1392,8 +1396,8 @@ hipError_t launch_gather_ids(const Dev& d, const float4* x_user, int par, hipStr
   return hipGetLastError();
 }
 
-hipError_t launch_bin(const Dev& d, int par, int check_disp, float half_skin, hipStream_t s) {
-  hipLaunchKernelGGL(k_bin, dim3(nblk(d.npad, kBlock)), dim3(kBlock), 0, s, d, par, check_disp, half_skin);
+hipError_t launch_bin(const Dev& d, int par, int check_disp, float rl, float rc, hipStream_t s) {
+  hipLaunchKernelGGL(k_bin, dim3(nblk(d.npad, kBlock)), dim3(kBlock), 0, s, d, par, check_disp, rl, rc);
   return hipGetLastError();
 }
 

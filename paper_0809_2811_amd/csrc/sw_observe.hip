@@ -268,6 +268,7 @@ int bin_positions(sw_ctx* c, const float* x, hipStream_t s) {
     hipError_t e;
     if ((e = reset_flags(c, s)) != hipSuccess) return fail_hip(c, e);
     if ((e = sort_in(c, x, nullptr, s)) != hipSuccess) return fail_hip(c, e);
+    c->have_order = false;   // the new internal order no longer matches the rows
     Flags fl;
     if ((e = read_flags(c, s, &fl)) != hipSuccess) return fail_hip(c, e);
     if (!fl.cell_over) return SW_OK;

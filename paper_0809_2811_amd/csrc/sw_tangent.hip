@@ -406,7 +406,7 @@ hipError_t run_segment(sw_ctx* c, const Phys& ph, int lpa, int len, bool first, 
   const Dev d0 = frame_dev(c, fs, 0, len);
   if ((e = launch_fill_i32(d0.gcnt[0], 0, c->ctot, s)) != hipSuccess) return e;
   if ((e = launch_fill_i32(d0.dflag, 0, 2 * c->R, s)) != hipSuccess) return e;
-  if ((e = launch_bin(d0, 0, 0, 0.f, s)) != hipSuccess) return e;
+  if ((e = launch_bin(d0, 0, 0, 0.f, 0.f, s)) != hipSuccess) return e;
   if ((e = launch_moments(d0, ph, lpa, 0, first ? 1 : 0, 0, s)) != hipSuccess) return e;
   if (len == 0) return launch_forces(d0, ph, lpa, MODE_FORCES, 0, 0, nullptr, s);
   if ((e = launch_forces(d0, ph, lpa, MODE_START, 0, 0, nullptr, s)) != hipSuccess) return e;
@@ -483,14 +483,15 @@ hipError_t tangent_frame(sw_ctx* c, const Dev& dv, const Phys& ph, int lpa, int 
 }
 
 // Tangent pass at positions u[0] along w; rows rebuilt first, or kept when
-// no atom has moved half the skin since they were built.
+// no atom has moved half the skin since they were built (the skin scaled by
+// any change of the box since the build).
 hipError_t tangent_pass(sw_ctx* c, const Phys& ph, int lpa, const float4* w, const PTerm& pt, hipStream_t s,
                         bool rebuild) {
   const Dev& d = c->d;
   hipError_t e;
   if ((e = launch_fill_i32(d.gcnt[0], 0, c->ctot, s)) != hipSuccess) return e;
   if ((e = launch_fill_i32(d.dflag, 0, 2 * c->R, s)) != hipSuccess) return e;
-  if ((e = launch_bin(d, 0, rebuild ? 0 : 1, ph.half_skin, s)) != hipSuccess) return e;
+  if ((e = launch_bin(d, 0, rebuild ? 0 : 1, (float)(c->cutoff + c->skin), ph.rc, s)) != hipSuccess) return e;
   if ((e = launch_moments_tan(d, ph, lpa, 0, rebuild ? 1 : 0, w, c->t.mdot, s)) != hipSuccess) return e;
   return launch_tan_forces(d, c->t, ph, lpa, w, 0, nullptr, pt, s);
 }

@@ -248,3 +248,55 @@ def test_slab_surface_tension_300K():
     g = observables.surface_tension(r[:, 8], r[:, 9], r[:, 10], s["slab_box"][2])
     assert 54.0 < g < 78.0, g
     assert abs(r[:, 2].mean() - 300.0) < 3.0
+
+
+def test_forces_after_box_compression_rebuild_rows():
+    """Rows built in a larger box cover less in a compressed one.  One
+    isobaric step with the barostat rate set to shrink the box by 3 %
+    (rows built at the start box, none rebuilt during the step), then the
+    caller moves the two atoms of a pair that sits just beyond the scaled
+    row radius 0.97 (cutoff + skin) toward each other by 0.45 A each (less
+    than half the nominal skin, more than half the scaled one), bringing
+    the pair inside a*sigma.  sw_forces must rebuild the rows and agree
+    with the oracle in the compressed box."""
+    from paper_0809_2811_amd import sw
+    x, v, L = liquid(1, sigma=0.0)
+    x, v = f32(x), f32(v)
+    skin = 1.0
+    ctx = ctx_for([0, len(x)], [L], skin=skin)
+    xd, vd = to_dev(x), to_dev(v)
+    ctx.npt(xd, vd, 0, T0=298.0, reset=True)
+    st = ctx.npt_state()
+    st[0, 0] = np.log(0.97) / 10.0            # barostat rate v_e (1/fs): one 10 fs step scales L by ~0.97
+    ctx.npt_state(st)
+    r0 = ctx.query(sw.SW_Q_REBUILDS)
+    ctx.npt(xd, vd, 1, T0=298.0, tau_P=2500.0)
+    assert ctx.query(sw.SW_Q_REBUILDS) - r0 == 1    # the call's initial build only
+    Lc = ctx.box[0]
+    s = Lc[0] / L[0]
+    assert 0.965 < s < 0.975
+    rl = RC + skin
+    xc = from_dev(xd)
+    d = xc[None, :, :] - xc[:, None, :]
+    d = min_image(d, Lc)
+    r = np.sqrt((d ** 2).sum(-1))
+    lo, hi = s * rl + 0.01, RC + 2 * 0.45 - 0.01
+    cand = np.argwhere(np.triu((r > lo) & (r < hi), 1))
+    assert len(cand) > 0
+    i, j = cand[0]
+    u = d[i, j] / r[i, j]                         # from i toward j
+    xm = xc.copy()
+    xm[i] += 0.45 * u
+    xm[j] -= 0.45 * u
+    xm = f32(xm)
+    f, e, w = ctx.forces(to_dev(xm))
+    o = oracle.forces(xm, Lc)
+    rij = np.linalg.norm(min_image(xm[j] - xm[i], Lc))
+    assert rij < RC                               # the pair now interacts
+    F = from_dev(f)
+    rms = np.sqrt((o["F"] ** 2).sum(1).mean())
+    assert np.abs(F - o["F"]).max() / rms <= 1e-5
+    etot = o["E2"] + o["E3"]
+    assert abs(float(e[0, 0]) - o["E2"]) <= 1e-5 * abs(etot)
+    assert abs(float(e[0, 1]) - o["E3"]) <= 1e-5 * abs(etot)
+    ctx.close()
