@@ -129,14 +129,25 @@ __global__ __launch_bounds__(kBlock) void k_sort_count(const float4* __restrict_
   atomicAdd(&cnt[rank], 1);
 }
 
-// Exclusive scan of n counts with one block of 1024 threads.
+// Exclusive scan of n counts with one block of 1024 threads.  Each thread
+// owns a contiguous range, read 16 counts per batch of independent loads
+// (a thread's one-at-a-time loop waited on every load: 121 us for the
+// 68921 cells of the 262144-atom box).
+constexpr int kScanBatch = 16;
+
 __global__ __launch_bounds__(1024) void k_scan(const int* __restrict__ cnt, int* __restrict__ start, int n) {
   __shared__ int part[1024];
   const int t = threadIdx.x;
   const int per = (n + 1023) / 1024;
   const int b = min(n, t * per), e = min(n, b + per);
   int s = 0;
-  for (int k = b; k < e; ++k) s += cnt[k];
+  for (int k0 = b; k0 < e; k0 += kScanBatch) {
+    int v[kScanBatch];
+#pragma unroll
+    for (int u = 0; u < kScanBatch; ++u) v[u] = k0 + u < e ? cnt[k0 + u] : 0;
+#pragma unroll
+    for (int u = 0; u < kScanBatch; ++u) s += v[u];
+  }
   part[t] = s;
   __syncthreads();
   for (int off = 1; off < 1024; off <<= 1) {
@@ -146,9 +157,16 @@ __global__ __launch_bounds__(1024) void k_scan(const int* __restrict__ cnt, int*
     __syncthreads();
   }
   int run = part[t] - s;
-  for (int k = b; k < e; ++k) {
-    start[k] = run;
-    run += cnt[k];
+  for (int k0 = b; k0 < e; k0 += kScanBatch) {
+    int v[kScanBatch];
+#pragma unroll
+    for (int u = 0; u < kScanBatch; ++u) v[u] = k0 + u < e ? cnt[k0 + u] : 0;
+#pragma unroll
+    for (int u = 0; u < kScanBatch; ++u)
+      if (k0 + u < e) {
+        start[k0 + u] = run;
+        run += v[u];
+      }
   }
 }
 
@@ -415,12 +433,17 @@ __device__ void moments_tile(const Dev& d, const Phys& p, int par, int force_reb
       }
       if (lane == 0) cnt[g] = run;
     } else if (real) {
-      // Few lanes per atom (large boxes, the CU full of waves: throughput
-      // bound).  Each slot searches its cell on its own and skips the search
-      // and the load past the end; appends take an LDS counter.
+      // Few lanes per atom (large boxes, the CU full of waves: bound by
+      // instruction issue).  Each slot searches its cell on its own and skips
+      // the search and the load past the end; entry indices are 32-bit, and
+      // accepted entries are compacted with a group ballot (no LDS atomics).
       const int ncand = pre[27];
       const float rl2 = p.rl2;
       constexpr int kCL = 8;
+      const int wl = threadIdx.x & 63;
+      const int gsh = wl & ~(LPA - 1);                           // the group's first lane
+      const unsigned gmk = (1u << LPA) - 1u, gbl = (1u << (wl - gsh)) - 1u;
+      int run = 0;                                               // entries appended so far (group-uniform)
       for (int k0 = lane; k0 < ncand; k0 += kCL * LPA) {
         uint4 e[kCL];
 #pragma unroll
@@ -432,19 +455,23 @@ __device__ void moments_tile(const Dev& d, const Phys& p, int par, int force_reb
 #pragma unroll
             for (int step = 16; step >= 1; step >>= 1)
               if (c + step < 27 && pre[c + step] <= k) c += step;
-            e[t] = gm[(size_t)cid[c] * ccap + (k - pre[c])];
+            e[t] = gm[(unsigned)cid[c] * (unsigned)ccap + (unsigned)(k - pre[c])];
           }
         }
 #pragma unroll
         for (int t = 0; t < kCL; ++t) {
           const int j = (int)e[t].w;
           const float3 dd = disp(ui, e[t], sc0, sc1, sc2);
-          if (j != i && dd.x * dd.x + dd.y * dd.y + dd.z * dd.z < rl2) {
-            const int sl = atomicAdd(&cnt[g], 1);
+          const bool acc = j != i && dd.x * dd.x + dd.y * dd.y + dd.z * dd.z < rl2;
+          const unsigned m = (unsigned)(__ballot(acc) >> gsh) & gmk;
+          if (acc) {
+            const int sl = run + __builtin_popcount(m & gbl);
             if (sl < cap) cand[sl] = j;
           }
+          run += __builtin_popcount(m);
         }
       }
+      if (lane == 0) cnt[g] = run;
     }
     __syncthreads();
     int total = cnt[g];
@@ -457,10 +484,18 @@ __device__ void moments_tile(const Dev& d, const Phys& p, int par, int force_reb
       // Ascending neighbour index: the row and every later sum over it are
       // independent of the order the cells were filled in.  With candidate
       // positions in LDS the sorted list holds candidate slots, else indices.
+      // The list is read four entries at a time (16-byte aligned; entries
+      // past the count are masked).
+      const int4* cand4 = reinterpret_cast<const int4*>(cand);
       for (int k = lane; k < total; k += LPA) {
         const int vj = cand[k];
         int rank = 0;
-        for (int q = 0; q < total; ++q) rank += cand[q] < vj;
+#pragma unroll 1
+        for (int q = 0; q < total; q += 4) {
+          const int4 w = cand4[q >> 2];
+          rank += (w.x < vj) + (q + 1 < total && w.y < vj) + (q + 2 < total && w.z < vj) +
+                  (q + 3 < total && w.w < vj);
+        }
         srt[rank] = (LPA >= 16 && !TAN) ? k : vj;
         d.nl[(size_t)i * cap + rank] = vj;
       }
