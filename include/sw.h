@@ -146,15 +146,23 @@ int sw_step(sw_ctx* ctx, float* x, float* v, float* f, const sw_params* params, 
             double dt, int nsteps, int thermostat, const double* h_T0, double tau_fs,
             double* thermo, int thermo_every, void* stream);
 
+/* Terms of Eq. E (Sec. II.A) selected by sw_grad's term_mask. */
+enum { SW_TERM_TWO_BODY = 1, SW_TERM_THREE_BODY = 2 };
+
 /* Tangent of the force field along w at positions x (forward mode):
- *  hvp     device float[N][4] out: (dF/dx) w = -H w (H is symmetric, so this
- *          is also (dF/dx)^T w).
- *  wdF     device double[R][3] out (may be NULL): w . dF/d(lambda, epsilon, sigma).
- *  dU      device double[R][3] out (may be NULL): dU/d(lambda, epsilon, sigma).
- * Uses the reduced form of Sec. II.A: dF/deps = F/eps, dF/dlambda = F3/lambda,
- * dF/dsigma = -(1/sigma) dW/dx with W the virial trace. Synchronises. */
-int sw_grad(sw_ctx* ctx, const float* x, const float* w, const sw_params* params, float* hvp,
-            double* wdF, double* dU, void* stream);
+ *  w         device float[N][4] direction (A).
+ *  term_mask SW_TERM_TWO_BODY, SW_TERM_THREE_BODY or both (3): the terms of
+ *            Eq. E whose forces, energies and virial enter every output
+ *            (other values: SW_EINVAL).
+ *  hvp       device float[N][4] out: (dF/dx) w = -H w of the selected terms (H
+ *            is symmetric, so this is also (dF/dx)^T w).
+ *  wdF       device double[R][3] out (may be NULL): w . dF/d(lambda, epsilon, sigma).
+ *  dU        device double[R][3] out (may be NULL): dU/d(lambda, epsilon, sigma).
+ * Uses the reduced form of Sec. II.A, which holds for each term on its own:
+ * dF/deps = F/eps, dF/dlambda = F3/lambda, dF/dsigma = -(1/sigma) dW/dx with W
+ * the virial trace (dU/dsigma = W/sigma). Synchronises. */
+int sw_grad(sw_ctx* ctx, const float* x, const float* w, const sw_params* params, int term_mask,
+            float* hvp, double* wdF, double* dU, void* stream);
 
 /* Gradient of a trajectory observable by the discrete adjoint of NVE velocity
  * Verlet, with checkpoints every ckpt_every steps and recomputation:
@@ -287,6 +295,14 @@ typedef struct sw_tuning {
                            replica then no longer equals the same replica run
                            alone bit for bit, only within rounding); 0: each
                            replica rebuilds on its own check                   */
+  int audit_every;      /* > 0: after the moments launch of every audit_every-th
+                           step of sw_step (per-phase or captured launches; the
+                           persistent launch is not audited), check the rows in
+                           use against a fresh search of the binning cells:
+                           every pair closer than a*sigma is counted, and so is
+                           every such pair missing from its row
+                           (SW_Q_AUDIT_PAIRS, SW_Q_MISSED_PAIRS; results are
+                           unchanged); 0 = off                                  */
 } sw_tuning;
 int sw_set_tuning(sw_ctx* ctx, const sw_tuning* t);
 int sw_get_tuning(const sw_ctx* ctx, sw_tuning* t);
@@ -304,7 +320,11 @@ enum {
                               observables' search-radius limit)            */
   SW_Q_TIME_MOMENTS_NS = 8, /* summed event time of sampled moments launches */
   SW_Q_TIME_FORCES_NS = 9,  /* summed event time of sampled force launches   */
-  SW_Q_TIMED_STEPS = 10     /* number of sampled steps (reset by sw_set_tuning) */
+  SW_Q_TIMED_STEPS = 10,    /* number of sampled steps (reset by sw_set_tuning) */
+  SW_Q_AUDIT_PAIRS = 12,    /* pairs closer than a*sigma seen by audits (sw_tuning.audit_every),
+                               since creation                                    */
+  SW_Q_MISSED_PAIRS = 13    /* of those, pairs absent from the rows in use (0 unless the
+                               rebuild criterion failed)                         */
 };
 int sw_query(sw_ctx* ctx, int what, long long* out);
 

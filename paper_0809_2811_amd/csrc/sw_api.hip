@@ -122,6 +122,7 @@ hipError_t alloc_all(sw_ctx* c) {
   SWA(c->d.dflag, 2 * (size_t)c->R);
   SWA(c->d.flags, F_NFLAGS);
   SWA(c->d_bar, 1);
+  SWA(c->d_audit, 2);
   SWA(c->d_reps, (size_t)c->R);
   SWA(c->d_tile_rep, c->tile_rep.size());
   SWA(c->d_uoff, (size_t)c->R + 1);
@@ -151,6 +152,7 @@ hipError_t alloc_all(sw_ctx* c) {
   if ((e = hipMemcpy(c->d_cell_rank, c->cell_rank.data(), sizeof(int) * c->ctot, hipMemcpyHostToDevice)) != hipSuccess) return e;
   if ((e = hipMemset(c->d.arrive, 0, sizeof(int) * c->R)) != hipSuccess) return e;
   if ((e = hipMemset(c->d.flags, 0, sizeof(int) * F_NFLAGS)) != hipSuccess) return e;
+  if ((e = hipMemset(c->d_audit, 0, sizeof(unsigned long long) * 2)) != hipSuccess) return e;
   if ((e = hipMemset(c->d.dflag, 0, sizeof(int) * 2 * c->R)) != hipSuccess) return e;
   if ((e = hipMemset(c->d.thermo_cur, 0, sizeof(double) * kNQ * c->R)) != hipSuccess) return e;
   return hipSuccess;
@@ -186,6 +188,8 @@ int make_phys(const sw_ctx* c, const sw_params* P, double mass, double dt, Phys*
   o->dt_d = dt;
   o->tau_d = 1.0;
   o->thermostat = 0;
+  o->term2 = 1.f;
+  o->term3 = 1.f;
   return SW_OK;
 }
 
@@ -295,6 +299,9 @@ hipError_t enqueue_step(sw_ctx* c, const Phys& ph, int lpa, int t, int nsteps, i
   const int force_rb = c->tune.rebuild_every > 0 && (t % c->tune.rebuild_every == 0);
   hipError_t e;
   if ((e = launch_moments(c->d, ph, lpa, par, force_rb, rec, s, tm_m)) != hipSuccess) return e;
+  if (c->tune.audit_every > 0 && t % c->tune.audit_every == 0 &&
+      (e = launch_audit(c->d, ph, par, c->d_audit, s)) != hipSuccess)
+    return e;
   if (thermostat == SW_NVE) {
     const int mode = t == nsteps ? MODE_NVE_LAST : MODE_NVE;
     if ((e = launch_forces(c->d, ph, lpa, mode, rec, par, row, s, tm_f)) != hipSuccess) return e;
@@ -314,8 +321,8 @@ long long lcm_ll(long long a, long long b) {
 // Captures steps base+1 .. base+K (base a multiple of the pattern period) of
 // the per-phase path into a graph, unless the cached one matches.
 hipError_t ensure_graph(sw_ctx* c, const Phys& ph, int lpa, int K, int thermostat, int every) {
-  std::vector<unsigned char> key(sizeof(Phys) + 7 * sizeof(int));
-  int meta[7] = {K, lpa, thermostat, every, c->tune.rebuild_every, c->alloc_gen, c->d.sync_rb};
+  std::vector<unsigned char> key(sizeof(Phys) + 8 * sizeof(int));
+  int meta[8] = {K, lpa, thermostat, every, c->tune.rebuild_every, c->alloc_gen, c->d.sync_rb, c->tune.audit_every};
   std::memcpy(key.data(), &ph, sizeof(Phys));
   std::memcpy(key.data() + sizeof(Phys), meta, sizeof meta);
   if (c->gexec && key == c->gkey) return hipSuccess;
@@ -483,7 +490,8 @@ int sw_set_tuning(sw_ctx* ctx, const sw_tuning* t) {
   if (t->lanes_per_atom != 4 && t->lanes_per_atom != 8 && t->lanes_per_atom != 16 && t->lanes_per_atom != 32 &&
       t->lanes_per_atom != 64)
     return SW_EUNSUPPORTED;
-  if (t->graph_steps < 0 || t->rebuild_every < 0 || t->timing < 0 || t->persistent < 0) return SW_EINVAL;
+  if (t->graph_steps < 0 || t->rebuild_every < 0 || t->timing < 0 || t->persistent < 0 || t->audit_every < 0)
+    return SW_EINVAL;
   if (t->sync_rebuild != 0 && t->sync_rebuild != 1) return SW_EINVAL;
   ctx->tune = *t;
   ctx->d.sync_rb = t->sync_rebuild;
@@ -635,6 +643,7 @@ int sw_step(sw_ctx* ctx, float* x, float* v, float* f, const sw_params* params, 
         const int every = thermo ? thermo_every : 0;
         if (every > 0) period = lcm_ll(period, every);
         if (ctx->tune.rebuild_every > 0) period = lcm_ll(period, ctx->tune.rebuild_every);
+        if (ctx->tune.audit_every > 0) period = lcm_ll(period, ctx->tune.audit_every);
         const long long K = ((ctx->tune.graph_steps + period - 1) / period) * period;
         const long long nblk = (nsteps - 1) / K;
         if (nblk > 0 && K <= 1 << 20) {
@@ -707,6 +716,15 @@ int sw_query(sw_ctx* ctx, int what, long long* out) {
       for (const RepInfo& R : ctx->reps)
         for (int k = 0; k < 3; ++k) m = std::min(m, R.L[k] / R.nc[k]);
       *out = (long long)std::floor(m * 1e6);
+      return SW_OK;
+    }
+    case SW_Q_AUDIT_PAIRS:
+    case SW_Q_MISSED_PAIRS: {
+      unsigned long long h[2];
+      hipError_t e = hipDeviceSynchronize();
+      if (e == hipSuccess) e = hipMemcpy(h, ctx->d_audit, sizeof h, hipMemcpyDeviceToHost);
+      if (e != hipSuccess) return fail_hip(ctx, e);
+      *out = (long long)h[what == SW_Q_AUDIT_PAIRS ? 0 : 1];
       return SW_OK;
     }
     case SW_Q_REBUILDS: {

@@ -21,7 +21,7 @@ struct sw_ctx {
   std::vector<RepInfo> reps;
   int ctot = 0;
   std::vector<int> tile_rep, cell_rank;
-  sw_tuning tune{8, 0, 0, 0, 0};
+  sw_tuning tune{8, 0, 0, 0, 0, 0, 0};
   std::vector<hipEvent_t> tev;     // sampled launch timing: 4 events per sample
   double t_mom_ms = 0.0, t_for_ms = 0.0;
   long long t_samples = 0;
@@ -35,6 +35,7 @@ struct sw_ctx {
   int *d_key = nullptr, *d_scnt = nullptr, *d_sstart = nullptr, *d_scur = nullptr, *d_order = nullptr;
   Tan t{};
   unsigned* d_bar = nullptr;       // grid barrier counter of the persistent launch
+  unsigned long long* d_audit = nullptr;   // [2] pairs within the cut-off audited, pairs missing from rows
   // captured block of steps (graph_steps > 0)
   hipStream_t cap_stream = nullptr;
   hipGraph_t graph = nullptr;

@@ -113,6 +113,8 @@ struct Phys {
   float m_acc;          // mass / 4.184e-4
   double dt_d, tau_d;   // thermostat
   int thermostat;       // SW_NVE / SW_RESCALE / SW_BERENDSEN
+  float term2, term3;   // weights of the two- and three-body terms in a tangent pass (sw_grad's
+                        // term mask; 1 elsewhere)
 };
 
 // Kernel modes of the force kernel.
@@ -185,6 +187,10 @@ hipError_t launch_forces(const Dev& d, const Phys& p, int lpa, int mode, int vir
 hipError_t launch_moments_tan(const Dev& d, const Phys& p, int lpa, int par, int force_rebuild, const float4* w,
                               float4* mdot, hipStream_t s);
 hipError_t launch_thermostat(const Dev& d, const Phys& p, int lpa, int par, int last, hipStream_t s);
+// Audit of the rows in use at parity par against a fresh search of grid par:
+// counts[0] += pairs closer than the cut-off, counts[1] += those missing from
+// their row.
+hipError_t launch_audit(const Dev& d, const Phys& p, int par, unsigned long long* counts, hipStream_t s);
 hipError_t launch_scatter_out(const Dev& d, int par, float4* x_user, float4* v_user,
                               float4* f_user, hipStream_t s);
 hipError_t launch_copy_thermo(const Dev& d, double* energy, double* virial, hipStream_t s);

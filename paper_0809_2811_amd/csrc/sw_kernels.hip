@@ -643,6 +643,61 @@ __global__ __launch_bounds__(kBlock) void k_moments_tan(Dev d, Phys p, int par, 
   clear_next(d, par, blockIdx.x, gridDim.x);
 }
 
+// ----------------------------------------------------------------- audit
+// Missed-pair audit: one lane per atom walks the 27 cells of grid par (the
+// binning of the positions this step reads), and for every j within the
+// cut-off (the same float test as the moments kernel) looks j up in the
+// atom's row by bisection (rows are ascending).  Counts go to two 64-bit
+// counters, one atomic per wavefront each.
+__global__ __launch_bounds__(kBlock) void k_audit(Dev d, Phys p, int par, unsigned long long* __restrict__ counts) {
+  const int i = blockIdx.x * kBlock + (int)threadIdx.x;
+  if (i >= d.npad) return;                             // whole wavefronts
+  const int rep = d.tile_rep[i >> 6];
+  const RepInfo& R = d.reps[rep];
+  unsigned long long seen = 0, missed = 0;
+  if (i < R.iend) {
+    const uint4 ui = pick(d.u, par)[i];
+    const int n0 = R.nc[0], n1 = R.nc[1], n2 = R.nc[2];
+    const int cx = (int)__umulhi(ui.x, (unsigned)n0);
+    const int cy = (int)__umulhi(ui.y, (unsigned)n1);
+    const int cz = (int)__umulhi(ui.z, (unsigned)n2);
+    const int* gc = pick(d.gcnt, par);
+    const uint4* gm = pick(d.gmem, par);
+    const int* row = d.nl + (size_t)i * d.cap;
+    const int nn = d.nn[i];
+    for (int c = 0; c < 27; ++c) {
+      int xx = cx + c / 9 - 1, yy = cy + (c / 3) % 3 - 1, zz = cz + c % 3 - 1;
+      xx = xx < 0 ? xx + n0 : (xx >= n0 ? xx - n0 : xx);
+      yy = yy < 0 ? yy + n1 : (yy >= n1 ? yy - n1 : yy);
+      zz = zz < 0 ? zz + n2 : (zz >= n2 ? zz - n2 : zz);
+      const int cell = R.cell_off + (xx * n1 + yy) * n2 + zz;
+      const int m = min(gc[cell], d.cc);
+      for (int r = 0; r < m; ++r) {
+        const uint4 e = gm[(size_t)cell * d.cc + r];
+        const int j = (int)e.w;
+        const float3 dd = disp(ui, e, R.scale[0], R.scale[1], R.scale[2]);
+        if (j == i || !(dd.x * dd.x + dd.y * dd.y + dd.z * dd.z < p.rc2)) continue;
+        ++seen;
+        int lo = 0, hi = nn;                           // first slot with row[slot] >= j
+        while (lo < hi) {
+          const int mid = (lo + hi) >> 1;
+          if (row[mid] < j) lo = mid + 1;
+          else hi = mid;
+        }
+        if (lo == nn || row[lo] != j) ++missed;
+      }
+    }
+  }
+  for (int o = 32; o >= 1; o >>= 1) {
+    seen += __shfl_xor(seen, o, 64);
+    missed += __shfl_xor(missed, o, 64);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    atomicAdd(&counts[0], seen);
+    if (missed) atomicAdd(&counts[1], missed);
+  }
+}
+
 // ----------------------------------------------------------------- forces
 // Block partial sums of the thermo quantities (fixed order within the block).
 // The per-replica sums are taken by k_reduce_thermo after the kernel ends.
@@ -1477,6 +1532,11 @@ hipError_t launch_forces(const Dev& d, const Phys& p, int lpa, int mode, int vir
 
 hipError_t launch_thermostat(const Dev& d, const Phys& p, int lpa, int par, int last, hipStream_t s) {
   hipLaunchKernelGGL(k_thermostat, dim3(nblk(d.npad, kBlock)), dim3(kBlock), 0, s, d, p, par, last, kBlock / lpa);
+  return hipGetLastError();
+}
+
+hipError_t launch_audit(const Dev& d, const Phys& p, int par, unsigned long long* counts, hipStream_t s) {
+  hipLaunchKernelGGL(k_audit, dim3(nblk(d.npad, kBlock)), dim3(kBlock), 0, s, d, p, par, counts);
   return hipGetLastError();
 }
 

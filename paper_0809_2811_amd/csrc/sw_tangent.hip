@@ -67,6 +67,10 @@ __global__ __launch_bounds__(kBlock) void k_tan_forces(Dev d, Tan t, Phys p, con
   const RepInfo& R = d.reps[rep];
   const bool real = i < R.iend;
   const float c0 = p.c0, c02 = p.c0 * p.c0;
+  // term weights (sw_grad's term mask; an adjoint frame always takes both):
+  // the pair derivative scales the two-body force and virial, the leg factor
+  // lambda eps e_j every three-body contribution
+  const float m2 = ADJ ? 1.f : p.term2, m3 = ADJ ? 1.f : p.term3;
   D Tm[6], Vm[3], Sm{0.f, 0.f};
   float E2i = 0.f, E3i = 0.f;
   for (int k = 0; k < 6; ++k) Tm[k] = D{0.f, 0.f};
@@ -99,7 +103,7 @@ __global__ __launch_bounds__(kBlock) void k_tan_forces(Dev d, Tan t, Phys p, con
       const D e1 = ex2D(p.sig_l2e * G.idr);
       const D sr = p.sig * G.ir, s2 = sr * sr, s4 = s2 * s2;
       const D poly = (p.B * s4) - 1.f;
-      const D dphi = p.Aeps * (e1 * ((-4.f * p.B) * (s4 * G.ir) - p.sig * (poly * idr2)));
+      const D dphi = m2 * (p.Aeps * (e1 * ((-4.f * p.B) * (s4 * G.ir) - p.sig * (poly * idr2))));
       const D gg = (-p.gsig) * idr2;
       const D Ts0 = Tm[0] + D{na.x, da.x}, Ts1 = Tm[1] + D{na.y, da.y}, Ts2 = Tm[2] + D{na.z, da.z};
       const D Ts3 = Tm[3] + D{na.w, da.w}, Ts4 = Tm[4] + D{nb.x, db.x}, Ts5 = Tm[5] + D{nb.y, db.y};
@@ -115,7 +119,7 @@ __global__ __launch_bounds__(kBlock) void k_tan_forces(Dev d, Tan t, Phys p, con
       const D px = (y0x - c0 * Dv0) - uy_ * G.ux;
       const D py = (y0y - c0 * Dv1) - uy_ * G.uy;
       const D pz = (y0z - c0 * Dv2) - uy_ * G.uz;
-      const D le = p.lameps * G.eg;
+      const D le = m3 * (p.lameps * G.eg);
       const D b3 = le * gg * q;
       const D a2 = 2.f * (le * G.ir);
       const D a1 = dphi + b3;
@@ -192,6 +196,7 @@ __global__ __launch_bounds__(kBlock) void k_tan_forces(Dev d, Tan t, Phys p, con
 // coef_cm, loss weights aU, a3 with the 1/(n (S+1)) normalisation).
 struct PTerm {
   double lam, eps, sig;
+  double m2, m3;          // term weights of the energies in dU (the tangent pass weights the rest)
   double* wdF;
   double* dU;
   double* thbar;
@@ -232,7 +237,7 @@ __global__ __launch_bounds__(kBlock) void k_reduce_tan(Dev d, Tan t, int apb, PT
       }
       const double E2 = q[0], E3 = q[1], W2 = q[2], W3 = q[3], wF = q[4], wF3 = q[5], Wd = q[6];
       const double g[3] = {wF3 / pt.lam, wF / pt.eps, -Wd / pt.sig};   // w . dF/d(lambda, eps, sigma)
-      const double u[3] = {E3 / pt.lam, (E2 + E3) / pt.eps, (W2 + W3) / pt.sig};
+      const double u[3] = {pt.m3 * E3 / pt.lam, (pt.m2 * E2 + pt.m3 * E3) / pt.eps, (W2 + W3) / pt.sig};
       const double u3[3] = {E3 / pt.lam, E3 / pt.eps, W3 / pt.sig};
       if (pt.wdF) for (int k = 0; k < 3; ++k) pt.wdF[3 * rep + k] = g[k];
       if (pt.dU) for (int k = 0; k < 3; ++k) pt.dU[3 * rep + k] = u[k];
@@ -500,15 +505,19 @@ hipError_t tangent_pass(sw_ctx* c, const Phys& ph, int lpa, const float4* w, con
 
 extern "C" {
 
-int sw_grad(sw_ctx* ctx, const float* x, const float* w, const sw_params* params, float* hvp, double* wdF,
-            double* dU, void* stream) {
+int sw_grad(sw_ctx* ctx, const float* x, const float* w, const sw_params* params, int term_mask, float* hvp,
+            double* wdF, double* dU, void* stream) {
   if (!ctx || !x || !w || !hvp) return SW_EINVAL;
+  if (term_mask < 1 || term_mask > (SW_TERM_TWO_BODY | SW_TERM_THREE_BODY)) return SW_EINVAL;
   hipStream_t s = (hipStream_t)stream;
   Phys ph{};
   int st = make_phys(ctx, params, 1.0, 1.0, &ph);
   if (st != SW_OK) return st;
+  ph.term2 = (term_mask & SW_TERM_TWO_BODY) ? 1.f : 0.f;
+  ph.term3 = (term_mask & SW_TERM_THREE_BODY) ? 1.f : 0.f;
   const int lpa = lpa_for(ctx);
-  const PTerm pt{params->lambda, params->epsilon, params->sigma, wdF, dU, nullptr, nullptr, 0.0, 0.0, 0.0, 0};
+  const PTerm pt{params->lambda, params->epsilon, params->sigma, (double)ph.term2, (double)ph.term3,
+                 wdF, dU, nullptr, nullptr, 0.0, 0.0, 0.0, 0};
   for (int attempt = 0; attempt < 6; ++attempt) {
     hipError_t e;
     if ((e = reset_flags(ctx, s)) != hipSuccess) return fail_hip(ctx, e);
@@ -644,7 +653,7 @@ int sw_adjoint(sw_ctx* ctx, const float* x0, const float* v0, const sw_params* p
       // parameter adjoint and loss from the sums of all frames (weights already applied)
       Tan tr = ctx->t;
       tr.tpartial = tacc;
-      const PTerm pt{params->lambda, params->epsilon, params->sigma, nullptr, nullptr, thb, lossb, 1.0, aU, a3, S};
+      const PTerm pt{params->lambda, params->epsilon, params->sigma, 1.0, 1.0, nullptr, nullptr, thb, lossb, 1.0, aU, a3, S};
       return launch_tan_reduce(ctx->d, tr, lpa, pt, q);
     };
     if (ctx->tune.graph_steps > 0) {

@@ -33,10 +33,12 @@ SW_ESTATE = -9
 SW_ETIMEOUT = -10
 
 SW_NVE, SW_RESCALE, SW_BERENDSEN = 0, 1, 2
+SW_TERM_TWO_BODY, SW_TERM_THREE_BODY = 1, 2
 SW_THERMO_WIDTH = 12
 SW_Q_NATOMS, SW_Q_NREPLICAS, SW_Q_NBR_CAPACITY, SW_Q_REBUILDS = 0, 1, 2, 3
 SW_Q_CELL_CAPACITY, SW_Q_DEVICE_BYTES, SW_Q_STEPS = 5, 6, 7
 SW_Q_TIME_MOMENTS_NS, SW_Q_TIME_FORCES_NS, SW_Q_TIMED_STEPS = 8, 9, 10
+SW_Q_AUDIT_PAIRS, SW_Q_MISSED_PAIRS = 12, 13
 
 # symbols declared in include/sw.h
 EXPORTS = ("sw_params_mw", "sw_create", "sw_destroy", "sw_build_neighbors", "sw_get_neighbors",
@@ -56,7 +58,7 @@ class sw_params(ctypes.Structure):
 class sw_tuning(ctypes.Structure):
     _fields_ = [("lanes_per_atom", ctypes.c_int), ("graph_steps", ctypes.c_int),
                 ("persistent", ctypes.c_int), ("rebuild_every", ctypes.c_int), ("timing", ctypes.c_int),
-                ("sync_rebuild", ctypes.c_int)]
+                ("sync_rebuild", ctypes.c_int), ("audit_every", ctypes.c_int)]
 
 
 class SWError(RuntimeError):
@@ -88,7 +90,7 @@ def lib():
         L.sw_get_neighbors.argtypes = [vp, P(ctypes.c_int), P(ctypes.c_int), ip]
         L.sw_forces.argtypes = [vp, fp, P(sw_params), fp, vp, vp, vp]
         L.sw_step.argtypes = [vp, fp, fp, fp, P(sw_params), dp, dp, ip, ip, P(ctypes.c_double), dp, vp, ip, vp]
-        L.sw_grad.argtypes = [vp, fp, fp, P(sw_params), fp, vp, vp, vp]
+        L.sw_grad.argtypes = [vp, fp, fp, P(sw_params), ip, fp, vp, vp, vp]
         L.sw_adjoint.argtypes = [vp, fp, fp, P(sw_params), dp, dp, ip, ip, dp, dp, fp, fp, vp, fp, fp, vp,
                                  fp, fp, vp]
         L.sw_set_tuning.argtypes = [vp, P(sw_tuning)]
@@ -217,11 +219,12 @@ def sw_step(ctx: int, x, v, f, params: sw_params, mass: float, dt: float, nsteps
                          _stream()), "sw_step")
 
 
-def sw_grad(ctx: int, x, w, params: sw_params, hvp, wdF=None, dU=None, R: int = 1):
+def sw_grad(ctx: int, x, w, params: sw_params, hvp, wdF=None, dU=None, R: int = 1,
+            term_mask: int = SW_TERM_TWO_BODY | SW_TERM_THREE_BODY):
     n = x.shape[0]
     _check(lib().sw_grad(ctypes.c_void_p(ctx), _atoms(x, n, "x"), _atoms(w, n, "w"), ctypes.byref(params),
-                         _atoms(hvp, n, "hvp"), _doubles(wdF, (R, 3), "wdF"), _doubles(dU, (R, 3), "dU"),
-                         _stream()), "sw_grad")
+                         int(term_mask), _atoms(hvp, n, "hvp"), _doubles(wdF, (R, 3), "wdF"),
+                         _doubles(dU, (R, 3), "dU"), _stream()), "sw_grad")
 
 
 def sw_adjoint(ctx: int, x0, v0, params: sw_params, mass: float, dt: float, nsteps: int, ckpt_every: int,
@@ -313,9 +316,9 @@ def sw_npt_state(ctx: int, R: int = 1, state=None):
 
 
 def sw_set_tuning(ctx: int, lanes_per_atom=8, graph_steps=0, persistent=0, rebuild_every=0, timing=0,
-                  sync_rebuild=0):
+                  sync_rebuild=0, audit_every=0):
     t = sw_tuning(int(lanes_per_atom), int(graph_steps), int(persistent), int(rebuild_every), int(timing),
-                  int(sync_rebuild))
+                  int(sync_rebuild), int(audit_every))
     _check(lib().sw_set_tuning(ctypes.c_void_p(ctx), ctypes.byref(t)), "sw_set_tuning")
 
 
@@ -323,7 +326,8 @@ def sw_get_tuning(ctx: int) -> dict:
     t = sw_tuning()
     _check(lib().sw_get_tuning(ctypes.c_void_p(ctx), ctypes.byref(t)), "sw_get_tuning")
     return dict(lanes_per_atom=t.lanes_per_atom, graph_steps=t.graph_steps, persistent=t.persistent,
-                rebuild_every=t.rebuild_every, timing=t.timing, sync_rebuild=t.sync_rebuild)
+                rebuild_every=t.rebuild_every, timing=t.timing, sync_rebuild=t.sync_rebuild,
+                audit_every=t.audit_every)
 
 
 def sw_query(ctx: int, what: int) -> int:
@@ -435,13 +439,15 @@ class Context:
                 max(thermo_every, 1), R=self.R)
         return f, thermo
 
-    def grad(self, x, w, params: Optional[sw_params] = None):
+    def grad(self, x, w, params: Optional[sw_params] = None, term_mask: int = SW_TERM_TWO_BODY | SW_TERM_THREE_BODY):
+        """(dF/dx) w, w . dF/d(lambda, eps, sigma) and dU/d(lambda, eps, sigma)
+        of the terms selected by term_mask (see sw_grad in include/sw.h)."""
         torch = _torch()
         params = params_mw() if params is None else params
         hvp = torch.empty_like(x)
         wdF = torch.empty((self.R, 3), dtype=torch.float64, device=x.device)
         dU = torch.empty((self.R, 3), dtype=torch.float64, device=x.device)
-        sw_grad(self.handle, x, w, params, hvp, wdF, dU, R=self.R)
+        sw_grad(self.handle, x, w, params, hvp, wdF, dU, R=self.R, term_mask=term_mask)
         return hvp, wdF, dU
 
     def adjoint(self, x0, v0, nsteps: int, dt: float = 10.0, mass: float = 18.015, ckpt_every: int = 20,

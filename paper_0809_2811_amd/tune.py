@@ -21,7 +21,8 @@ import pathlib
 import time
 
 CACHE = pathlib.Path(__file__).resolve().parent / "tuning_cache.json"
-DEFAULT = dict(lanes_per_atom=8, graph_steps=0, persistent=0, rebuild_every=0, timing=0, sync_rebuild=0)
+DEFAULT = dict(lanes_per_atom=8, graph_steps=0, persistent=0, rebuild_every=0, timing=0, sync_rebuild=0,
+               audit_every=0)
 RC = 1.8 * 2.3925
 
 

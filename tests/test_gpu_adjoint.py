@@ -47,6 +47,37 @@ def test_hessian_vector_product(lpa):
         assert abs(float(dU[0, k]) - refU) <= 1e-5 * abs(refU), (k, float(dU[0, k]), refU)
 
 
+@pytest.mark.parametrize("mask", [1, 2])
+def test_term_mask_selects_two_or_three_body_terms(mask):
+    """sw_grad with one term of Eq. E: the HVP against the oracle's tangent of
+    that term's forces (two-body = all minus three-body), and the parameter
+    terms against the oracle's parameter tangents of the same term."""
+    from paper_0809_2811_amd import sw
+    x, _, L = liquid(1, sigma=0.0)
+    x = f32(x)
+    w = f32(np.random.default_rng(8).normal(size=x.shape))
+    ctx = ctx_for(x, L)
+    hvp, wdF, dU = ctx.grad(to_dev(x), to_dev(w), term_mask=mask)
+    part = (lambda t: t["F3dot"]) if mask == sw.SW_TERM_THREE_BODY else (lambda t: t["Fdot"] - t["F3dot"])
+    t = oracle.tangent(x, L, xdot=w)
+    assert rel_err(from_dev(hvp), part(t)) <= 1e-4
+    for k in range(3):
+        Pd = np.zeros(10); Pd[k] = 1.0
+        tp = oracle.tangent(x, L, Pdot=Pd)
+        ref = float((w * part(tp)).sum())
+        assert abs(float(wdF[0, k]) - ref) <= 1e-4 * abs(ref) + 1e-12, (mask, k, float(wdF[0, k]), ref)
+        refU = float(tp["Edot"][1] if mask == sw.SW_TERM_THREE_BODY else tp["Edot"][0])
+        assert abs(float(dU[0, k]) - refU) <= 1e-5 * abs(refU) + 1e-12, (mask, k, float(dU[0, k]), refU)
+    # both masks together give the full tangent
+    h1 = from_dev(ctx.grad(to_dev(x), to_dev(w), term_mask=1)[0])
+    h2 = from_dev(ctx.grad(to_dev(x), to_dev(w), term_mask=2)[0])
+    h3 = from_dev(ctx.grad(to_dev(x), to_dev(w))[0])
+    assert rel_err(h1 + h2, h3) <= 1e-5
+    with pytest.raises(sw.SWError):
+        ctx.grad(to_dev(x), to_dev(w), term_mask=0)
+    ctx.close()
+
+
 def test_hvp_is_symmetric_and_kills_translations():
     x, _, L = liquid(1, sigma=0.0)
     x = f32(x)
@@ -162,6 +193,43 @@ def test_parameter_gradient_vs_oracle_central_differences():
         Pm = P0.copy(); Pm[k] -= h
         fd = (oracle.traj_loss(x, v, L, S, P=Pp)[0] - oracle.traj_loss(x, v, L, S, P=Pm)[0]) / (2 * h)
         assert abs(g["thbar"][k] - fd) <= 1e-4 * abs(fd), (k, g["thbar"][k], fd)
+
+
+@pytest.mark.slow
+def test_initial_state_gradient_vs_oracle_central_differences():
+    """The same workload shape and horizon for the initial state: GPU
+    xbar0 . u and vbar0 . u against central differences of the FP64 oracle's
+    trajectory loss along u, for 4 seeded unit directions over all 3N
+    coordinates and 8 single coordinates (the atoms with the largest oracle
+    adjoint xbar0, one axis each, so no compared component is near zero).
+    Steps: h = 1e-4 sigma for positions, h / dt for velocities (the same
+    drift over one step).  Bar 1e-4 relative."""
+    x, v, L = liquid(2)
+    x, v = f32(x), f32(v)
+    S, dt = 20, 10.0
+    g = gpu_adjoint(x, v, L, S, 20)
+    o = oracle.adjoint(x, v, L, S)
+    rng = np.random.default_rng(21)
+    dirs = []
+    for _ in range(4):
+        u = rng.normal(size=x.shape)
+        dirs.append(u / np.linalg.norm(u))
+    mag = np.abs(o["xbar0"]).max(axis=1)
+    for a in np.argsort(-mag)[:8]:
+        u = np.zeros_like(x)
+        u[a, int(np.argmax(np.abs(o["xbar0"][a])))] = 1.0
+        dirs.append(u)
+    hx = 1e-4 * 2.3925
+    hv = hx / dt
+    worst = 0.0
+    for u in dirs:
+        fdx = (oracle.traj_loss(x + hx * u, v, L, S)[0] - oracle.traj_loss(x - hx * u, v, L, S)[0]) / (2 * hx)
+        fdv = (oracle.traj_loss(x, v + hv * u, L, S)[0] - oracle.traj_loss(x, v - hv * u, L, S)[0]) / (2 * hv)
+        for got, fd in ((float((g["xbar0"] * u).sum()), fdx), (float((g["vbar0"] * u).sum()), fdv)):
+            err = abs(got - fd) / abs(fd)
+            worst = max(worst, err)
+            assert err <= 1e-4, (got, fd, err)
+    print(f"initial-state gradient: worst relative error {worst:.2e} over {2 * len(dirs)} directional derivatives")
 
 
 @pytest.mark.slow

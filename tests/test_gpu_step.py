@@ -350,3 +350,30 @@ def test_graph_replays_equal_plain_launches(thermostat):
     for call in range(3):
         for k in range(4):
             assert np.array_equal(runs[0][call][k], runs[10][call][k]), (call, k)
+
+
+@pytest.mark.parametrize("lpa,graph", [(8, 0), (32, 0), (8, 20)])
+def test_missed_pair_audit(lpa, graph):
+    """The rows in use are audited against a fresh search of the cells after
+    every step's moments launch: 120 NVE steps of the 4096-atom liquid with a
+    0.5 A skin (rows rebuilt on the displacement check only) miss no pair
+    inside a*sigma, and the audited pair count of a single step equals the
+    oracle's count of ordered pairs within a*sigma at the returned
+    positions (up to pairs within float rounding of the cut-off)."""
+    from paper_0809_2811_amd import sw
+    x, v, L = liquid(2)
+    x, v = f32(x), f32(v)
+    ctx = sw.Context([0, len(x)], [L], cutoff=RC, skin=0.5, nbr_capacity=48,
+                     tuning=dict(lanes_per_atom=lpa, graph_steps=graph, audit_every=1))
+    xd, vd = to_dev(x), to_dev(v)
+    ctx.step(xd, vd, 1)
+    pairs1 = ctx.query(sw.SW_Q_AUDIT_PAIRS)
+    ref = int(oracle.neighbour_counts(from_dev(xd), L, RC).sum())
+    assert abs(pairs1 - ref) <= 2, (pairs1, ref)
+    r0 = ctx.query(sw.SW_Q_REBUILDS)
+    ctx.step(xd, vd, 120)
+    assert ctx.query(sw.SW_Q_REBUILDS) - r0 >= 10          # the check fired many times
+    pairs = ctx.query(sw.SW_Q_AUDIT_PAIRS) - pairs1
+    assert 0.9 * 120 * pairs1 < pairs < 1.1 * 120 * pairs1
+    assert ctx.query(sw.SW_Q_MISSED_PAIRS) == 0
+    ctx.close()
