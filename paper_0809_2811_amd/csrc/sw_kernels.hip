@@ -442,7 +442,10 @@ __device__ void moments_tile(const Dev& d, const Phys& p, int par, int force_reb
       constexpr int kCL = 8;
       const int wl = threadIdx.x & 63;
       const int gsh = wl & ~(LPA - 1);                           // the group's first lane
-      const unsigned gmk = (1u << LPA) - 1u, gbl = (1u << (wl - gsh)) - 1u;
+      // (this branch runs with fewer than 16 lanes per atom; the mask is
+      // spelled so that every instantiation compiles)
+      constexpr unsigned gmk = LPA < 32 ? (1u << (LPA % 32)) - 1u : ~0u;
+      const unsigned gbl = (1u << (wl - gsh)) - 1u;
       int run = 0;                                               // entries appended so far (group-uniform)
       for (int k0 = lane; k0 < ncand; k0 += kCL * LPA) {
         uint4 e[kCL];
