@@ -66,7 +66,8 @@ typedef enum sw_status {
   SW_ENOMEM = -7,          /* device allocation failed                                 */
   SW_EUNSUPPORTED = -8,    /* parameter or option outside what the kernels implement  */
   SW_ESTATE = -9,          /* call needs state the context does not have              */
-  SW_ETIMEOUT = -10        /* a grid barrier of the persistent launch waited too long  */
+  SW_ETIMEOUT = -10,       /* a grid barrier of the persistent launch waited too long  */
+  SW_ESCRATCH = -11        /* input too large for sw_forces_noalloc's static scratch   */
 } sw_status;
 
 /* Opaque context: replica layout, cell grids, neighbour rows, workspaces. */
@@ -118,6 +119,31 @@ int sw_get_neighbors(sw_ctx* ctx, int* h_counts, int* h_rows, int max_per_row);
  * Synchronises. */
 int sw_forces(sw_ctx* ctx, const float* x, const sw_params* params, float* f, double* energy,
               double* virial, void* stream);
+
+/* Allocation-free variant of sw_forces, for callers that cannot allocate
+ * device memory: code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc.  It needs no context: one periodic box of n atoms is
+ * sorted, binned, given rows (cutoff a*sigma + SW_NOALLOC_SKIN) and evaluated
+ * with the same kernels as sw_forces, and every device buffer of that work
+ * lies in one static device array of SW_SCRATCH_BYTES that each GPU the
+ * library runs on holds until the process ends.  Calls allocate and free
+ * nothing (host or device side of HIP); they share the array of their GPU,
+ * which keeps the last call's contents (each call clears what must start at
+ * zero), so calls that overlap on one GPU race.
+ *  x       device float[n][4] positions (A), caller order.
+ *  n       atoms, 2 <= n <= SW_NOALLOC_MAX_ATOMS (else SW_ESCRATCH).
+ *  h_box   host double[3] box edges (A), each at least 3 (a*sigma + skin).
+ *  params  host; as for sw_forces (p = 4, q = 0).
+ *  f, energy, virial  device outputs as for sw_forces (R = 1).
+ * Errors: SW_EINVAL, SW_EBOX_TOO_SMALL, SW_ESCRATCH (the box needs more
+ * working memory than the array holds), SW_ENBR_OVERFLOW / SW_ECELL_OVERFLOW
+ * (rows hold 64 slots and never grow here), SW_EOVERLAP, SW_EHIP.
+ * Synchronises. */
+#define SW_SCRATCH_BYTES (32u << 20)
+#define SW_NOALLOC_MAX_ATOMS 16384
+#define SW_NOALLOC_SKIN 0.5
+int sw_forces_noalloc(const float* x, long long n, const double* h_box, const sw_params* params,
+                      float* f, double* energy, double* virial, void* stream);
 
 /* Thermostat kinds for sw_step. */
 enum { SW_NVE = 0, SW_RESCALE = 1, SW_BERENDSEN = 2 };

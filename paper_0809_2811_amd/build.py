@@ -10,7 +10,7 @@ PKG = pathlib.Path(__file__).resolve().parent
 ROOT = PKG.parent
 CSRC = PKG / "csrc"
 LIB = PKG / "libsw.so"
-SOURCES = ["sw_kernels.hip", "sw_tangent.hip", "sw_api.hip", "sw_observe.hip", "sw_npt.hip"]
+SOURCES = ["sw_kernels.hip", "sw_tangent.hip", "sw_api.hip", "sw_observe.hip", "sw_npt.hip", "sw_noalloc.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

@@ -96,56 +96,17 @@ int lpa_for(const sw_ctx* c) {
 // Buffers whose size depends on the row and cell capacities.
 hipError_t alloc_capacity(sw_ctx* c) {
   free_list(c, c->grow_allocs);
-  hipError_t e;
-  if ((e = dalloc(c, &c->d.nl, (size_t)c->npad * c->cap, c->grow_allocs)) != hipSuccess) return e;
-  if ((e = dalloc(c, &c->d.act, (size_t)c->npad * c->cap, c->grow_allocs)) != hipSuccess) return e;
-  for (int k = 0; k < 2; ++k)
-    if ((e = dalloc(c, &c->d.gmem[k], (size_t)c->ctot * c->cc, c->grow_allocs)) != hipSuccess) return e;
-  c->d.cap = c->cap;
-  c->d.cc = c->cc;
+  hipError_t e = place_capacity_buffers(c, [c](void** p, size_t bytes) { return dalloc_raw(c, p, bytes, c->grow_allocs); });
+  if (e != hipSuccess) return e;
   ++c->alloc_gen;
   return hipSuccess;
 }
 
 hipError_t alloc_all(sw_ctx* c) {
   hipError_t e;
-  auto& L = c->allocs;
-  const size_t np = (size_t)c->npad;
-#define SWA(ptr, n) \
-  if ((e = dalloc(c, &(ptr), (n), L)) != hipSuccess) return e
-  SWA(c->d.u[0], np); SWA(c->d.u[1], np); SWA(c->d.v, np); SWA(c->d.f, np); SWA(c->d.uref, np);
-  SWA(c->d.ids, np); SWA(c->d.nn, np); SWA(c->d.nact, np); SWA(c->d.mom, 3 * np);
-  SWA(c->d.gcnt[0], (size_t)c->ctot); SWA(c->d.gcnt[1], (size_t)c->ctot);
-  SWA(c->d.partial, (np / kMinAPB + 1) * kNQ);   // one slot per block and quantity
-  SWA(c->d.thermo_cur, (size_t)c->R * kNQ);
-  SWA(c->d.arrive, (size_t)c->R);
-  SWA(c->d.dflag, 2 * (size_t)c->R);
-  SWA(c->d.flags, F_NFLAGS);
-  SWA(c->d_bar, 1);
-  SWA(c->d_audit, 2);
-  SWA(c->d_reps, (size_t)c->R);
-  SWA(c->d_tile_rep, c->tile_rep.size());
-  SWA(c->d_uoff, (size_t)c->R + 1);
-  SWA(c->d_cell_rank, (size_t)c->ctot);
-  SWA(c->d_T0, (size_t)c->R);
-  SWA(c->d.lref, (size_t)c->R);
-  SWA(c->d_kick, (size_t)c->R);
-  SWA(c->d_uq, (size_t)c->N); SWA(c->d_key, (size_t)c->N); SWA(c->d_order, (size_t)c->N);
-  SWA(c->d_scnt, (size_t)c->ctot); SWA(c->d_sstart, (size_t)c->ctot); SWA(c->d_scur, (size_t)c->ctot);
-  SWA(c->t.w, np); SWA(c->t.mdot, 3 * np); SWA(c->t.fdot, np); SWA(c->t.f3, np);
-  SWA(c->t.tpartial, (np / kMinAPB + 1) * kTQ);
-  SWA(c->t.tsum, (size_t)c->R * kTQ);
-#undef SWA
+  if ((e = place_buffers(c, [c](void** p, size_t bytes) { return dalloc_raw(c, p, bytes, c->allocs); })) != hipSuccess)
+    return e;
   if ((e = alloc_capacity(c)) != hipSuccess) return e;
-  c->d.reps = c->d_reps;
-  c->d.tile_rep = c->d_tile_rep;
-  c->d.T0 = c->d_T0;
-  c->d.npt_kick = c->d_kick;
-  c->d.npad = c->npad;
-  c->d.ctot = c->ctot;
-  c->d.R = c->R;
-  c->d.max_rep_pad = 0;
-  for (const RepInfo& R : c->reps) c->d.max_rep_pad = std::max(c->d.max_rep_pad, R.ipad_end - R.ioff);
   if ((e = hipMemcpy(c->d_reps, c->reps.data(), sizeof(RepInfo) * c->R, hipMemcpyHostToDevice)) != hipSuccess) return e;
   if ((e = hipMemcpy(c->d_tile_rep, c->tile_rep.data(), sizeof(int) * c->tile_rep.size(), hipMemcpyHostToDevice)) != hipSuccess) return e;
   if ((e = hipMemcpy(c->d_uoff, c->uoff.data(), sizeof(long long) * (c->R + 1), hipMemcpyHostToDevice)) != hipSuccess) return e;
@@ -156,6 +117,68 @@ hipError_t alloc_all(sw_ctx* c) {
   if ((e = hipMemset(c->d.dflag, 0, sizeof(int) * 2 * c->R)) != hipSuccess) return e;
   if ((e = hipMemset(c->d.thermo_cur, 0, sizeof(double) * kNQ * c->R)) != hipSuccess) return e;
   return hipSuccess;
+}
+
+// Replica layout of a context (no device work): boxes, binning grids,
+// Morton ranks of the cells, 64-atom tiles, padded atom ranges, initial row
+// and cell capacities.  Returns SW_OK, SW_EINVAL or SW_EBOX_TOO_SMALL.
+int setup_layout(sw_ctx* c, int n_replicas, const long long* h_offsets, const double* h_box, double cutoff,
+                 double skin, int nbr_capacity) {
+  if (n_replicas <= 0 || !h_offsets || !h_box || !(cutoff > 0.0) || !(skin >= 0.0) || nbr_capacity <= 0 ||
+      nbr_capacity > kMaxCap || !std::isfinite(cutoff) || !std::isfinite(skin))
+    return SW_EINVAL;
+  if (h_offsets[0] != 0) return SW_EINVAL;
+  for (int r = 0; r < n_replicas; ++r) {
+    if (h_offsets[r + 1] - h_offsets[r] < 2) return SW_EINVAL;
+    for (int k = 0; k < 3; ++k)
+      if (!(h_box[3 * r + k] > 0.0) || !std::isfinite(h_box[3 * r + k])) return SW_EINVAL;
+  }
+  if (h_offsets[n_replicas] >= (1LL << 30)) return SW_EINVAL;
+  c->R = n_replicas;
+  c->N = h_offsets[n_replicas];
+  c->uoff.assign(h_offsets, h_offsets + n_replicas + 1);
+  c->box.assign(h_box, h_box + 3 * n_replicas);
+  c->cutoff = cutoff;
+  c->skin = skin;
+  c->cap = (nbr_capacity + 3) & ~3;
+  const double rl = cutoff + skin;
+  int ioff = 0, coff = 0;
+  c->reps.clear();
+  c->tile_rep.clear();
+  c->cell_rank.clear();
+  for (int r = 0; r < n_replicas; ++r) {
+    RepInfo R{};
+    const int n = (int)(h_offsets[r + 1] - h_offsets[r]);
+    for (int k = 0; k < 3; ++k) {
+      const double L = h_box[3 * r + k];
+      R.L[k] = L;
+      R.scale[k] = (float)(L / kTwo32);
+      R.inv_scale[k] = (float)(kTwo32 / L);
+      const int nc = (int)std::floor(L / rl);
+      if (nc < 3) return SW_EBOX_TOO_SMALL;
+      R.nc[k] = std::min(nc, 1024);
+    }
+    R.ncell = R.nc[0] * R.nc[1] * R.nc[2];
+    R.cell_off = coff;
+    R.ioff = ioff;
+    R.n = n;
+    R.iend = ioff + n;
+    R.ipad_end = ioff + ((n + kTile - 1) / kTile) * kTile;
+    R.uoff = h_offsets[r];
+    R.ndof_kb = (3.0 * n - 3.0) * kBoltz;
+    cell_ranks(R, coff, c->cell_rank);
+    for (int t = ioff / kTile; t < R.ipad_end / kTile; ++t) c->tile_rep.push_back(r);
+    ioff = R.ipad_end;
+    coff += R.ncell;
+    c->reps.push_back(R);
+  }
+  c->npad = ioff;
+  c->ctot = coff;
+  // binning cells hold ~ n * rl^3 atoms on average; start at 4x that, min 32
+  double mean = 0.0;
+  for (const auto& R : c->reps) mean = std::max(mean, (double)R.n / R.ncell);
+  c->cc = std::max(32, (int)std::ceil(4.0 * mean / 8.0) * 8);
+  return SW_OK;
 }
 
 int make_phys(const sw_ctx* c, const sw_params* P, double mass, double dt, Phys* o) {
@@ -389,6 +412,7 @@ const char* sw_status_string(int s) {
     case SW_EUNSUPPORTED: return "unsupported parameter or option";
     case SW_ESTATE: return "context has no neighbour rows yet";
     case SW_ETIMEOUT: return "a grid barrier of the persistent launch waited too long";
+    case SW_ESCRATCH: return "input too large for the allocation-free entry point's static scratch";
   }
   return "unknown status";
 }
@@ -399,62 +423,13 @@ int sw_create(sw_ctx** out, int n_replicas, const long long* h_offsets, const do
               double skin, int nbr_capacity) {
   if (!out) return SW_EINVAL;
   *out = nullptr;
-  if (n_replicas <= 0 || !h_offsets || !h_box || !(cutoff > 0.0) || !(skin >= 0.0) || nbr_capacity <= 0 ||
-      nbr_capacity > kMaxCap || !std::isfinite(cutoff) || !std::isfinite(skin))
-    return SW_EINVAL;
-  if (h_offsets[0] != 0) return SW_EINVAL;
-  for (int r = 0; r < n_replicas; ++r) {
-    if (h_offsets[r + 1] - h_offsets[r] < 2) return SW_EINVAL;
-    for (int k = 0; k < 3; ++k)
-      if (!(h_box[3 * r + k] > 0.0) || !std::isfinite(h_box[3 * r + k])) return SW_EINVAL;
-  }
-  if (h_offsets[n_replicas] >= (1LL << 30)) return SW_EINVAL;
   sw_ctx* c = new (std::nothrow) sw_ctx;
   if (!c) return SW_ENOMEM;
-  c->R = n_replicas;
-  c->N = h_offsets[n_replicas];
-  c->uoff.assign(h_offsets, h_offsets + n_replicas + 1);
-  c->box.assign(h_box, h_box + 3 * n_replicas);
-  c->cutoff = cutoff;
-  c->skin = skin;
-  c->cap = (nbr_capacity + 3) & ~3;
-  const double rl = cutoff + skin;
-  int ioff = 0, coff = 0;
-  for (int r = 0; r < n_replicas; ++r) {
-    RepInfo R{};
-    const int n = (int)(h_offsets[r + 1] - h_offsets[r]);
-    for (int k = 0; k < 3; ++k) {
-      const double L = h_box[3 * r + k];
-      R.L[k] = L;
-      R.scale[k] = (float)(L / kTwo32);
-      R.inv_scale[k] = (float)(kTwo32 / L);
-      const int nc = (int)std::floor(L / rl);
-      if (nc < 3) {
-        delete c;
-        return SW_EBOX_TOO_SMALL;
-      }
-      R.nc[k] = std::min(nc, 1024);
-    }
-    R.ncell = R.nc[0] * R.nc[1] * R.nc[2];
-    R.cell_off = coff;
-    R.ioff = ioff;
-    R.n = n;
-    R.iend = ioff + n;
-    R.ipad_end = ioff + ((n + kTile - 1) / kTile) * kTile;
-    R.uoff = h_offsets[r];
-    R.ndof_kb = (3.0 * n - 3.0) * kBoltz;
-    cell_ranks(R, coff, c->cell_rank);
-    for (int t = ioff / kTile; t < R.ipad_end / kTile; ++t) c->tile_rep.push_back(r);
-    ioff = R.ipad_end;
-    coff += R.ncell;
-    c->reps.push_back(R);
+  const int st = setup_layout(c, n_replicas, h_offsets, h_box, cutoff, skin, nbr_capacity);
+  if (st != SW_OK) {
+    delete c;
+    return st;
   }
-  c->npad = ioff;
-  c->ctot = coff;
-  // binning cells hold ~ n * rl^3 atoms on average; start at 4x that, min 32
-  double mean = 0.0;
-  for (const auto& R : c->reps) mean = std::max(mean, (double)R.n / R.ncell);
-  c->cc = std::max(32, (int)std::ceil(4.0 * mean / 8.0) * 8);
   hipError_t e = alloc_all(c);
   if (e != hipSuccess) {
     free_list(c, c->grow_allocs);

@@ -3,6 +3,7 @@
 #include "sw.h"
 #include "sw_internal.h"
 
+#include <algorithm>
 #include <unordered_map>
 #include <vector>
 
@@ -82,6 +83,69 @@ struct sw_ctx {
 
 namespace swh {
 using namespace swk;
+
+// Every device buffer of a context, in one place: `alloc(void** p, size_t
+// bytes)` supplies the memory (hipMalloc in sw_create, a static scratch
+// array in the allocation-free entry point).  place_buffers places the
+// fixed-size ones, place_capacity_buffers the ones sized by the row and
+// cell capacities (and records those capacities in the device view).
+template <class A>
+hipError_t place_buffers(sw_ctx* c, A&& alloc) {
+  const size_t np = (size_t)c->npad;
+  hipError_t e = hipSuccess;
+  auto put = [&](auto*& ptr, size_t n) {
+    if (e == hipSuccess) e = alloc((void**)&ptr, std::max<size_t>(n, 1) * sizeof(*ptr));
+  };
+  put(c->d.u[0], np); put(c->d.u[1], np); put(c->d.v, np); put(c->d.f, np); put(c->d.uref, np);
+  put(c->d.ids, np); put(c->d.nn, np); put(c->d.nact, np); put(c->d.mom, 3 * np);
+  put(c->d.gcnt[0], (size_t)c->ctot); put(c->d.gcnt[1], (size_t)c->ctot);
+  put(c->d.partial, (np / kMinAPB + 1) * kNQ);   // one slot per block and quantity
+  put(c->d.thermo_cur, (size_t)c->R * kNQ);
+  put(c->d.arrive, (size_t)c->R);
+  put(c->d.dflag, 2 * (size_t)c->R);
+  put(c->d.flags, F_NFLAGS);
+  put(c->d_bar, 1);
+  put(c->d_audit, 2);
+  put(c->d_reps, (size_t)c->R);
+  put(c->d_tile_rep, c->tile_rep.size());
+  put(c->d_uoff, (size_t)c->R + 1);
+  put(c->d_cell_rank, (size_t)c->ctot);
+  put(c->d_T0, (size_t)c->R);
+  put(c->d.lref, (size_t)c->R);
+  put(c->d_kick, (size_t)c->R);
+  put(c->d_uq, (size_t)c->N); put(c->d_key, (size_t)c->N); put(c->d_order, (size_t)c->N);
+  put(c->d_scnt, (size_t)c->ctot); put(c->d_sstart, (size_t)c->ctot); put(c->d_scur, (size_t)c->ctot);
+  put(c->t.w, np); put(c->t.mdot, 3 * np); put(c->t.fdot, np); put(c->t.f3, np);
+  put(c->t.tpartial, (np / kMinAPB + 1) * kTQ);
+  put(c->t.tsum, (size_t)c->R * kTQ);
+  if (e != hipSuccess) return e;
+  c->d.reps = c->d_reps;
+  c->d.tile_rep = c->d_tile_rep;
+  c->d.T0 = c->d_T0;
+  c->d.npt_kick = c->d_kick;
+  c->d.npad = c->npad;
+  c->d.ctot = c->ctot;
+  c->d.R = c->R;
+  c->d.max_rep_pad = 0;
+  for (const RepInfo& R : c->reps) c->d.max_rep_pad = std::max(c->d.max_rep_pad, R.ipad_end - R.ioff);
+  return hipSuccess;
+}
+
+template <class A>
+hipError_t place_capacity_buffers(sw_ctx* c, A&& alloc) {
+  hipError_t e;
+  if ((e = alloc((void**)&c->d.nl, sizeof(int) * (size_t)c->npad * c->cap)) != hipSuccess) return e;
+  if ((e = alloc((void**)&c->d.act, sizeof(int) * (size_t)c->npad * c->cap)) != hipSuccess) return e;
+  for (int k = 0; k < 2; ++k)
+    if ((e = alloc((void**)&c->d.gmem[k], sizeof(uint4) * std::max<size_t>((size_t)c->ctot * c->cc, 1))) != hipSuccess)
+      return e;
+  c->d.cap = c->cap;
+  c->d.cc = c->cc;
+  return hipSuccess;
+}
+
+int setup_layout(sw_ctx* c, int n_replicas, const long long* h_offsets, const double* h_box, double cutoff,
+                 double skin, int nbr_capacity);
 int fail_hip(sw_ctx* c, hipError_t e);
 int lpa_for(const sw_ctx* c);
 int make_phys(const sw_ctx* c, const sw_params* P, double mass, double dt, Phys* o);

@@ -31,6 +31,8 @@ SW_ENOMEM = -7
 SW_EUNSUPPORTED = -8
 SW_ESTATE = -9
 SW_ETIMEOUT = -10
+SW_ESCRATCH = -11
+SW_NOALLOC_MAX_ATOMS = 16384
 
 SW_NVE, SW_RESCALE, SW_BERENDSEN = 0, 1, 2
 SW_TERM_TWO_BODY, SW_TERM_THREE_BODY = 1, 2
@@ -44,7 +46,7 @@ SW_Q_AUDIT_PAIRS, SW_Q_MISSED_PAIRS = 12, 13
 EXPORTS = ("sw_params_mw", "sw_create", "sw_destroy", "sw_build_neighbors", "sw_get_neighbors",
            "sw_forces", "sw_step", "sw_grad", "sw_adjoint", "sw_set_tuning", "sw_get_tuning",
            "sw_query", "sw_status_string", "sw_last_hip_error", "sw_rdf", "sw_adf", "sw_msd",
-           "sw_npt", "sw_get_box", "sw_npt_state")
+           "sw_npt", "sw_get_box", "sw_npt_state", "sw_forces_noalloc")
 SW_NPT_WIDTH = 11
 SW_Q_MIN_CELL_EDGE = 11
 SW_NPT_STATE = 17
@@ -105,6 +107,7 @@ def lib():
                              dp, dp, ip, ip, vp, ip, vp]
         L.sw_get_box.argtypes = [vp, P(ctypes.c_double)]
         L.sw_npt_state.argtypes = [vp, P(ctypes.c_double), ip]
+        L.sw_forces_noalloc.argtypes = [fp, ctypes.c_longlong, P(ctypes.c_double), P(sw_params), fp, vp, vp, vp]
         _lib = L
     return _lib
 
@@ -203,6 +206,15 @@ def sw_forces(ctx: int, x, params: sw_params, f, energy=None, virial=None, n: Op
     _check(lib().sw_forces(ctypes.c_void_p(ctx), _atoms(x, n, "x"), ctypes.byref(params), _atoms(f, n, "f"),
                            _doubles(energy, (R, 2), "energy"), _doubles(virial, (R, 6), "virial"), _stream()),
            "sw_forces")
+
+
+def sw_forces_noalloc(x, box, params: sw_params, f, energy=None, virial=None):
+    """Context-free, allocation-free sw_forces for one box (see include/sw.h)."""
+    n = x.shape[0]
+    b = np.ascontiguousarray(box, dtype=np.float64).reshape(3)
+    _check(lib().sw_forces_noalloc(_atoms(x, n, "x"), int(n), b.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                   ctypes.byref(params), _atoms(f, n, "f"), _doubles(energy, (1, 2), "energy"),
+                                   _doubles(virial, (1, 6), "virial"), _stream()), "sw_forces_noalloc")
 
 
 def sw_step(ctx: int, x, v, f, params: sw_params, mass: float, dt: float, nsteps: int, thermostat: int = SW_NVE,

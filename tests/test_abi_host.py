@@ -29,7 +29,7 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_status_strings():
-    for code in range(0, -11, -1):
+    for code in range(0, -12, -1):
         s = sw.status_string(code)
         assert s and s != "unknown status"
     assert sw.status_string(-99) == "unknown status"
