@@ -62,10 +62,10 @@ def lib():
         L.ora_vv.argtypes = [c_int, dp, dp, dp, dp, dp, c_double, c_double, c_int, c_int,
                              c_double, c_double, dp]
         L.ora_traj_loss.argtypes = [c_int, dp, dp, dp, dp, c_double, c_double, c_int, c_double,
-                                    c_double, dp, dp]
+                                    c_double, c_double, dp, dp]
         L.ora_traj_loss.restype = c_double
         L.ora_adjoint.argtypes = [c_int, dp, dp, dp, dp, c_double, c_double, c_int, c_double,
-                                  c_double, dp, dp, dp, dp, dp, dp]
+                                  c_double, c_double, dp, dp, dp, dp, dp, dp]
         L.ora_neighbour_counts.argtypes = [c_int, dp, dp, c_double, ip]
         L.ora_neighbour_lists.argtypes = [c_int, dp, dp, c_double, llp, ip]
         L.ora_npt.argtypes = [c_int, dp, dp, dp, dp, c_double, c_double, c_int, c_double, c_double, c_double,
@@ -153,17 +153,18 @@ def vv(x, v, box, nsteps, dt=10.0, mass=M_WATER, P=None, thermostat=0, T0=0.0, t
     return x, v, F, thermo[:nsteps]
 
 
-def traj_loss(x0, v0, box, nsteps, dt=10.0, mass=M_WATER, P=None, aU=1.0, a3=1.0):
+def traj_loss(x0, v0, box, nsteps, dt=10.0, mass=M_WATER, P=None, aU=1.0, a3=1.0, aW=0.0):
+    """1/(S+1) sum_s [aU U + a3 U3 + aW W](x_s) / N over an NVE trajectory; (loss, xS, vS)."""
     x0 = _d(x0); v0 = _d(v0); box = _d(box); P = params() if P is None else _d(P)
     n = len(x0)
     xS = np.zeros((n, 3)); vS = np.zeros((n, 3))
     loss = lib().ora_traj_loss(n, _ptr(x0), _ptr(v0), _ptr(box), _ptr(P), float(mass), float(dt),
-                               int(nsteps), float(aU), float(a3), _ptr(xS), _ptr(vS))
+                               int(nsteps), float(aU), float(a3), float(aW), _ptr(xS), _ptr(vS))
     return loss, xS, vS
 
 
 def adjoint(x0, v0, box, nsteps, dt=10.0, mass=M_WATER, P=None, aU=1.0, a3=1.0,
-            xbar_S=None, vbar_S=None):
+            xbar_S=None, vbar_S=None, aW=0.0):
     """Discrete adjoint of NVE velocity Verlet: dict(loss, xbar0, vbar0, thbar[3])."""
     x0 = _d(x0); v0 = _d(v0); box = _d(box); P = params() if P is None else _d(P)
     n = len(x0)
@@ -172,7 +173,7 @@ def adjoint(x0, v0, box, nsteps, dt=10.0, mass=M_WATER, P=None, aU=1.0, a3=1.0,
     loss = ctypes.c_double()
     xb = np.zeros((n, 3)); vb = np.zeros((n, 3)); th = np.zeros(3)
     _check(lib().ora_adjoint(n, _ptr(x0), _ptr(v0), _ptr(box), _ptr(P), float(mass), float(dt),
-                             int(nsteps), float(aU), float(a3), _ptr(xs), _ptr(vs),
+                             int(nsteps), float(aU), float(a3), float(aW), _ptr(xs), _ptr(vs),
                              ctypes.byref(loss), _ptr(xb), _ptr(vb), _ptr(th)))
     return dict(loss=loss.value, xbar0=xb, vbar0=vb, thbar=th)
 

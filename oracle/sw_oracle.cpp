@@ -434,25 +434,30 @@ int ora_vv(int n, double* x, double* v, double* f, const double* L, const double
   return 0;
 }
 
+// Virial trace W = sum over terms and legs of d . F (the configurational part
+// of the pressure, P V = (2 KE + W) / 3).
+double virial_trace(const Eval& ev) { return ev.w2[0] + ev.w2[4] + ev.w2[8] + ev.w3[0] + ev.w3[4] + ev.w3[8]; }
+
 // Trajectory loss of the differentiable workload:
-//   L = 1/(S+1) sum_{s=0..S} [aU U(x_s) + a3 U3(x_s)] / N,   U = E2 + E3, U3 = E3,
+//   L = 1/(S+1) sum_{s=0..S} [aU U(x_s) + a3 U3(x_s) + aW W(x_s)] / N,
+//   U = E2 + E3, U3 = E3, W the virial trace,
 // over an NVE velocity-Verlet trajectory of S = nsteps steps from (x0, v0).
 // x0 and v0 are left untouched; xS, vS (may be NULL) receive the final state.
 double ora_traj_loss(int n, const double* x0, const double* v0, const double* L, const double* P,
-                     double mass, double dt, int nsteps, double aU, double a3, double* xS, double* vS) {
+                     double mass, double dt, int nsteps, double aU, double a3, double aW, double* xS, double* vS) {
   Box b = make_box(L);
   std::vector<double> x(x0, x0 + 3 * n), v(v0, v0 + 3 * n);
   const double c_m = kAcc / mass;
   const double norm = 1.0 / ((double)n * (nsteps + 1));
   Eval ev = eval_value(n, x.data(), b, P);
-  double loss = (aU * (ev.e[0] + ev.e[1]) + a3 * ev.e[1]) * norm;
+  double loss = (aU * (ev.e[0] + ev.e[1]) + a3 * ev.e[1] + aW * virial_trace(ev)) * norm;
   for (int s = 0; s < nsteps; ++s) {
     for (int i = 0; i < 3 * n; ++i) v[i] += 0.5 * dt * c_m * ev.f[i];
     for (int i = 0; i < 3 * n; ++i) x[i] += dt * v[i];
     wrap_positions(n, x.data(), b);
     ev = eval_value(n, x.data(), b, P);
     for (int i = 0; i < 3 * n; ++i) v[i] += 0.5 * dt * c_m * ev.f[i];
-    loss += (aU * (ev.e[0] + ev.e[1]) + a3 * ev.e[1]) * norm;
+    loss += (aU * (ev.e[0] + ev.e[1]) + a3 * ev.e[1] + aW * virial_trace(ev)) * norm;
   }
   if (xS) std::memcpy(xS, x.data(), sizeof(double) * 3 * n);
   if (vS) std::memcpy(vS, v.data(), sizeof(double) * 3 * n);
@@ -469,10 +474,13 @@ double ora_traj_loss(int n, const double* x0, const double* v0, const double* L,
 //     xb += w_n J(x_n) vb + dl_n/dx_n,   w_n = h (n > 0), h/2 (n = 0)
 // and the parameter adjoint collects the same coefficients times vb . da/dtheta
 // plus dl_n/dtheta.  J vb is the forward-mode tangent of the forces along vb
-// (J is symmetric); da/dtheta comes from tangents in each parameter.
+// (J is symmetric); da/dtheta comes from tangents in each parameter.  The
+// virial term's gradient uses dU/dsigma = W/sigma (reduced form), hence
+// dW/dx = sigma d(dU/dx)/dsigma = -sigma dF/dsigma, from the sigma tangent;
+// its parameter derivatives are the tangents of the virial trace.
 // Outputs: loss, xbar0[n][3], vbar0[n][3], thbar[3] = dL/d(lambda, epsilon, sigma).
 int ora_adjoint(int n, const double* x0, const double* v0, const double* L, const double* P,
-                double mass, double dt, int nsteps, double aU, double a3,
+                double mass, double dt, int nsteps, double aU, double a3, double aW,
                 const double* xbar_S, const double* vbar_S,
                 double* loss_out, double* xbar0, double* vbar0, double* thbar) {
   Box b = make_box(L);
@@ -487,14 +495,14 @@ int ora_adjoint(int n, const double* x0, const double* v0, const double* L, cons
   std::vector<double> x(x0, x0 + n3), v(v0, v0 + n3);
   traj[0] = x;
   Eval ev = eval_value(n, x.data(), b, P);
-  double loss = (aU * (ev.e[0] + ev.e[1]) + a3 * ev.e[1]) * norm;
+  double loss = (aU * (ev.e[0] + ev.e[1]) + a3 * ev.e[1] + aW * virial_trace(ev)) * norm;
   for (int s = 0; s < S; ++s) {
     for (size_t i = 0; i < n3; ++i) v[i] += 0.5 * dt * c_m * ev.f[i];
     for (size_t i = 0; i < n3; ++i) x[i] += dt * v[i];
     wrap_positions(n, x.data(), b);
     ev = eval_value(n, x.data(), b, P);
     for (size_t i = 0; i < n3; ++i) v[i] += 0.5 * dt * c_m * ev.f[i];
-    loss += (aU * (ev.e[0] + ev.e[1]) + a3 * ev.e[1]) * norm;
+    loss += (aU * (ev.e[0] + ev.e[1]) + a3 * ev.e[1] + aW * virial_trace(ev)) * norm;
     traj[s + 1] = x;
   }
   *loss_out = loss;
@@ -507,17 +515,23 @@ int ora_adjoint(int n, const double* x0, const double* v0, const double* L, cons
   // dl/dx and dl/dtheta of frame s, plus coef * (J vb, vb . da/dtheta).
   auto frame = [&](int s, double coef) {
     const double* xs = traj[s].data();
-    Tangent hv = eval_tangent(n, xs, vb.data(), b, P, nullptr);   // (dF/dx) vb
-    for (size_t i = 0; i < n3; ++i)
-      xb[i] += coef * c_m * hv.fdot[i] - (aU * hv.f[i] + a3 * hv.f3[i]) * norm;
-    for (int k = 0; k < 3; ++k) {           // lambda, epsilon, sigma
+    Tangent tp[3];
+    for (int k = 0; k < 3; ++k) {           // tangents in lambda, epsilon, sigma
       double Pd[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
       Pd[k] = 1.0;
-      Tangent tp = eval_tangent(n, xs, nullptr, b, P, Pd);
-      double vdF = 0.0;
-      for (size_t i = 0; i < n3; ++i) vdF += vb[i] * tp.fdot[i];
-      th[k] += coef * c_m * vdF + (aU * (tp.edot[0] + tp.edot[1]) + a3 * tp.edot[1]) * norm;
+      tp[k] = eval_tangent(n, xs, nullptr, b, P, Pd);
     }
+    for (int k = 0; k < 3; ++k) {           // uses vb before this frame's update of xb
+      double vdF = 0.0;
+      for (size_t i = 0; i < n3; ++i) vdF += vb[i] * tp[k].fdot[i];
+      double wdot = 0.0;
+      for (int c = 0; c < 9; c += 4) wdot += tp[k].w2dot[c] + tp[k].w3dot[c];
+      th[k] += coef * c_m * vdF + (aU * (tp[k].edot[0] + tp[k].edot[1]) + a3 * tp[k].edot[1] + aW * wdot) * norm;
+    }
+    Tangent hv = eval_tangent(n, xs, vb.data(), b, P, nullptr);   // (dF/dx) vb
+    const double sig = P[2];
+    for (size_t i = 0; i < n3; ++i)
+      xb[i] += coef * c_m * hv.fdot[i] - (aU * hv.f[i] + a3 * hv.f3[i]) * norm - aW * sig * tp[2].fdot[i] * norm;
   };
   frame(S, 0.5 * dt);
   for (int s = S - 1; s >= 0; --s) {

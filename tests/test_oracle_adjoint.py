@@ -88,3 +88,60 @@ def test_terminal_seeds():
     assert abs(fd - float((res["xbar0"] * u).sum())) <= 1e-5 * abs(fd)
     fd = (obj(x, v + h * 1e-2 * u) - obj(x, v - h * 1e-2 * u)) / (2 * h * 1e-2)
     assert abs(fd - float((res["vbar0"] * u).sum())) <= 1e-5 * abs(fd)
+
+
+# --------------------------------------------------------------- virial term
+def virial(x, L, P=None):
+    o = oracle.forces(x, L, P)
+    return float(np.trace(o["W2"] + o["W3"]))
+
+
+def test_virial_term_zero_steps_against_differences_of_the_virial():
+    """aW W / N alone at S = 0: the loss is the virial trace per atom, and its
+    gradients in x0 and in (lambda, epsilon, sigma) equal central differences
+    of the virial trace itself (forces() in FP64), not of the loss routine."""
+    x, v, L = small_liquid_like(seed=14)
+    n = len(x)
+    res = oracle.adjoint(x, v, L, 0, aU=0.0, a3=0.0, aW=1.0)
+    assert abs(res["loss"] - virial(x, L) / n) <= 1e-12 * abs(res["loss"])
+    P0 = oracle.params()
+    for k in range(3):
+        h = 1e-5 * P0[k]
+        Pp = P0.copy(); Pp[k] += h
+        Pm = P0.copy(); Pm[k] -= h
+        fd = (virial(x, L, Pp) - virial(x, L, Pm)) / (2 * h) / n
+        assert abs(fd - res["thbar"][k]) <= 1e-6 * abs(fd), (k, fd, res["thbar"][k])
+    rng = np.random.default_rng(3)
+    for a in rng.choice(n, 5, replace=False):
+        for c in range(3):
+            h = 1e-5
+            xp = x.copy(); xp[a, c] += h
+            xm = x.copy(); xm[a, c] -= h
+            fd = (virial(xp, L) - virial(xm, L)) / (2 * h) / n
+            assert abs(fd - res["xbar0"][a, c]) <= 1e-6 * np.abs(res["xbar0"]).max(), (a, c)
+    assert np.all(res["vbar0"] == 0.0)
+
+
+@pytest.mark.parametrize("nsteps", [1, 10])
+def test_virial_term_gradients_match_central_differences(nsteps):
+    """The full loss with the virial term (aU U + aW W): parameter and
+    initial-state gradients against central differences of the forward loss."""
+    x, v, L = small_liquid_like(seed=15)
+    kw = dict(aU=0.5, a3=0.0, aW=1.0)
+    res = oracle.adjoint(x, v, L, nsteps, **kw)
+    P0 = oracle.params()
+    for k in range(3):
+        h = 1e-4 * P0[k]
+        Pp = P0.copy(); Pp[k] += h
+        Pm = P0.copy(); Pm[k] -= h
+        fd = (oracle.traj_loss(x, v, L, nsteps, P=Pp, **kw)[0] - oracle.traj_loss(x, v, L, nsteps, P=Pm, **kw)[0]) / (2 * h)
+        assert abs(fd - res["thbar"][k]) <= 1e-4 * abs(fd) + 1e-9, (k, fd, res["thbar"][k])
+    rng = np.random.default_rng(nsteps + 40)
+    h = 1e-4 * oracle.MW["sig"]
+    for _ in range(3):
+        u = rng.normal(size=x.shape); u /= np.linalg.norm(u)
+        fd = (oracle.traj_loss(x + h * u, v, L, nsteps, **kw)[0] - oracle.traj_loss(x - h * u, v, L, nsteps, **kw)[0]) / (2 * h)
+        assert abs(fd - float((res["xbar0"] * u).sum())) <= 1e-4 * abs(fd) + 1e-10
+        hv = h / 10.0
+        fd = (oracle.traj_loss(x, v + hv * u, L, nsteps, **kw)[0] - oracle.traj_loss(x, v - hv * u, L, nsteps, **kw)[0]) / (2 * hv)
+        assert abs(fd - float((res["vbar0"] * u).sum())) <= 1e-4 * abs(fd) + 1e-10
