@@ -192,9 +192,12 @@ int sw_grad(sw_ctx* ctx, const float* x, const float* w, const sw_params* params
 
 /* Gradient of a trajectory observable by the discrete adjoint of NVE velocity
  * Verlet, with checkpoints every ckpt_every steps and recomputation:
- *   L_r = 1/(S+1) sum_{s=0..S} [aU U_r(x_s) + a3 U3_r(x_s)] / N_r
+ *   L_r = 1/(S+1) sum_{s=0..S} [aU U_r(x_s) + a3 U3_r(x_s) + aW W_r(x_s)] / N_r
  *         + xbar_S . x_S + vbar_S . v_S
- * (U = E2 + E3, U3 = E3, S = nsteps).
+ * (U = E2 + E3, U3 = E3, W the virial trace (the configurational part of
+ * the pressure, P V = (2 KE + W)/3, used with the density of Sec. II.D to
+ * fix sigma), S = nsteps).  aW != 0 adds one scaling tangent pass per frame
+ * (dW/dx and dW/dsigma follow from the reduced form of Sec. II.A).
  *  x0, v0   device float[N][4] initial state (unchanged).
  *  xbar_S, vbar_S device float[N][4] terminal seeds, may be NULL (= 0).
  *  loss     device double[R] out.
@@ -208,7 +211,7 @@ int sw_grad(sw_ctx* ctx, const float* x, const float* w, const sw_params* params
  * found there and the call reruns itself with grown capacities). */
 int sw_adjoint(sw_ctx* ctx, const float* x0, const float* v0, const sw_params* params,
                double mass, double dt, int nsteps, int ckpt_every, double aU, double a3,
-               const float* xbar_S, const float* vbar_S, double* loss, float* xbar0,
+               double aW, const float* xbar_S, const float* vbar_S, double* loss, float* xbar0,
                float* vbar0, double* thbar, float* xS, float* vS, void* stream);
 
 /* Structural observables (Sec. II.C).  Positions x are the caller's device

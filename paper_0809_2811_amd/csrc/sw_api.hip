@@ -191,7 +191,13 @@ int make_phys(const sw_ctx* c, const sw_params* P, double mass, double dt, Phys*
   if (rc > c->cutoff * (1.0 + 1e-12)) return SW_EINVAL;
   const double rl = c->cutoff + c->skin;
   o->rc = (float)rc;
-  o->rc2 = (float)(rc * rc);
+  // Pairs are accepted on r^2 < rc2, but the radial factors then take
+  // r = r^2 rsq(r^2) with the hardware reciprocal square root (within 1 ulp):
+  // for an r^2 just below rc^2 that r can round to rc or past it, and
+  // exp(gamma sigma / (r - rc)) becomes exp(+inf).  rc2 sits 2^-20 (relative)
+  // below rc^2 so that every accepted pair has r < rc in float; over that
+  // sliver (about 2e-6 A) both exponential factors are exactly zero in float.
+  o->rc2 = (float)((double)o->rc * (double)o->rc * (1.0 - 0x1p-20));
   o->rl2 = (float)(rl * rl);
   o->half_skin = (float)(0.5 * (rl - rc) - 1e-4);
   o->sig = (float)P->sigma;

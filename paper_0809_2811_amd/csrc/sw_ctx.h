@@ -115,7 +115,7 @@ hipError_t place_buffers(sw_ctx* c, A&& alloc) {
   put(c->d_kick, (size_t)c->R);
   put(c->d_uq, (size_t)c->N); put(c->d_key, (size_t)c->N); put(c->d_order, (size_t)c->N);
   put(c->d_scnt, (size_t)c->ctot); put(c->d_sstart, (size_t)c->ctot); put(c->d_scur, (size_t)c->ctot);
-  put(c->t.w, np); put(c->t.mdot, 3 * np); put(c->t.fdot, np); put(c->t.f3, np);
+  put(c->t.w, np); put(c->t.mdot, 3 * np); put(c->t.fdot, np); put(c->t.f3, np); put(c->t.gw, np);
   put(c->t.tpartial, (np / kMinAPB + 1) * kTQ);
   put(c->t.tsum, (size_t)c->R * kTQ);
   if (e != hipSuccess) return e;

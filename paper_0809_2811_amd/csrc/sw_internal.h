@@ -213,12 +213,14 @@ hipError_t launch_persistent(const Dev& d, const Phys& p, int lpa, const PArgs& 
                              hipStream_t s, int* grid_out);
 
 // Tangent (forward-mode) kernels for sw_grad / sw_adjoint.
-constexpr int kTQ = 7;  // per replica: E2, E3, W2 trace, W3 trace, w.F, w.F3, d(W trace) along w
+constexpr int kTQ = 8;  // per replica: E2, E3, W2 trace, W3 trace, w.F, w.F3, d(W trace) along w,
+                        // d(W trace)/ds under a uniform scaling of every leg (adjoint virial term)
 struct Tan {
   float4* w;         // [Npad] tangent direction (A), internal order
   float4* mdot;      // [Npad][3] tangent of the moments
   float4* fdot;      // [Npad] tangent of the forces: (dF/dx) w
   float4* f3;        // [Npad] three-body part of the forces
+  float4* gw;        // [Npad] gradient of the virial trace, F + dF/ds (adjoint virial term)
   double* tpartial;  // [kTQ][nblocks]
   double* tsum;      // [R][kTQ]
 };
@@ -237,6 +239,8 @@ struct Adj {
   const uint4* unext;  // positions of the frame the sweep visits next, or null: an atom
                        // more than half the skin from its row-build position raises the
                        // replica's flag of the other parity (that frame rebuilds its rows)
+  float aW;            // weight of the virial trace in the loss
+  const float4* gw;    // [Npad] this frame's virial gradient (read when aW != 0)
 };
 hipError_t launch_gather_vec(const Dev& d, const float4* user, float4* internal, hipStream_t s);
 hipError_t launch_scatter_vec(const Dev& d, const float4* internal, float4* user, hipStream_t s);

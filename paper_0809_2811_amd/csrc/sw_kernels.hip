@@ -525,9 +525,11 @@ __device__ void moments_tile(const Dev& d, const Phys& p, int par, int force_reb
   float T0 = 0.f, T1 = 0.f, T2 = 0.f, T3 = 0.f, T4 = 0.f, T5 = 0.f;
   float V0 = 0.f, V1 = 0.f, V2 = 0.f, S = 0.f, P = 0.f, E2 = 0.f;
   // tangent mode: the moments' derivatives along the direction w as well
-  // (the dual-number arithmetic of the tangent kernels, same per-lane order)
+  // (the dual-number arithmetic of the tangent kernels, same per-lane order);
+  // with tw null, along a uniform scaling of every leg (each leg's tangent is
+  // the leg itself)
   float dT0 = 0.f, dT1 = 0.f, dT2 = 0.f, dT3 = 0.f, dT4 = 0.f, dT5 = 0.f, dV0 = 0.f, dV1 = 0.f, dV2 = 0.f, dS = 0.f;
-  const float4 wi = TAN ? tw[i] : make_float4(0.f, 0.f, 0.f, 0.f);
+  const float4 wi = TAN && tw ? tw[i] : make_float4(0.f, 0.f, 0.f, 0.f);
   const uint4* upm = pick(d.u, par);
   // With 8 or fewer lanes per atom the entries within the cutoff are also
   // written out, in row order, as the force kernel's row: a row holds ~40 %
@@ -558,7 +560,7 @@ __device__ void moments_tile(const Dev& d, const Phys& p, int par, int force_reb
       if (jj[u] >= 0) {
         if (from_lds) uu[u] = lds_u[jj[u]];
         else uu[u] = upm[jj[u]];
-        if (TAN) wu[u] = tw[jj[u]];
+        if (TAN && tw) wu[u] = tw[jj[u]];
       }
     }
 #pragma unroll
@@ -587,7 +589,7 @@ __device__ void moments_tile(const Dev& d, const Phys& p, int par, int force_reb
           E2 += 0.5f * p.Aeps * (p.B * s2 * s2 - 1.f) * e1;
         }
         if (TAN) {
-          const Leg L = leg_dual(dd, sub3(wu[u], wi), p);
+          const Leg L = leg_dual(dd, tw ? sub3(wu[u], wi) : dd, p);
           const D dx = L.eg * L.ux, dy = L.eg * L.uy, dz = L.eg * L.uz;
           dT0 += (dx * L.ux).d; dT1 += (dy * L.uy).d; dT2 += (dz * L.uz).d;
           dT3 += (dx * L.uy).d; dT4 += (dx * L.uz).d; dT5 += (dy * L.uz).d;

@@ -13,6 +13,12 @@
 //   dU/deps = U/eps,  dU/dlambda = U3/lambda,  dU/dsigma = W/sigma,
 // with W the virial trace.
 //
+// A loss term aW W(x_s) in the virial trace W needs dW/dx per atom: from the
+// reduced form, sigma dF/dsigma = -(F + dF/ds) with dF/ds the tangent of the
+// forces under a uniform scaling of every leg, and dW/dx = -sigma dF/dsigma,
+// so one scaling pass per frame gives dW/dx = F + dF/ds and dW/ds, whence
+// dW/dsigma = -(1/sigma) dW/ds (dW/deps = W/eps, dW/dlambda = W3/lambda).
+//
 // The adjoint of the velocity-Verlet map (a = 4.184e-4 F / m, J = da/dx):
 //   xb = xbar_S; vb = vbar_S; frame(S, dt/2)
 //   for s = S-1 .. 0:  vb += dt xb;  frame(s, s > 0 ? dt : dt/2)
@@ -38,11 +44,21 @@
 namespace swk {
 namespace {
 
-// Forces and their tangent along w, virial traces and their tangent; with
-// ADJ the per-atom adjoint update of one frame.
-template <int LPA, bool ADJ>
+// Kinds of tangent force pass: along w for sw_grad (TK_GRAD), along w with
+// the per-atom adjoint update of one frame (TK_ADJ), or along a uniform
+// scaling of every leg (TK_SCALE: each leg's tangent is the leg itself), which
+// gives the frame's virial gradient dW/dx = F + dF/ds (from the reduced form
+// of Sec. II.A, sigma dF/dsigma = -(F + dF/ds)) and dW/ds, so that
+// dW/dsigma = -(1/sigma) dW/ds.
+enum { TK_GRAD = 0, TK_ADJ = 1, TK_SCALE = 2 };
+
+// Forces and their tangent, virial traces and their tangent; by kind the
+// adjoint update of a frame or the virial gradient.
+template <int LPA, int KIND>
 __global__ __launch_bounds__(kBlock) void k_tan_forces(Dev d, Tan t, Phys p, const float4* __restrict__ w, int par,
                                                        Adj a) {
+  constexpr bool ADJ = KIND == TK_ADJ;
+  constexpr bool SCALE = KIND == TK_SCALE;
   constexpr int APB = kBlock / LPA;
   static_assert(APB >= kMinAPB, "tangent partials are sized for at least kMinAPB atoms per block");
   __shared__ double red[APB * kTQ];
@@ -52,7 +68,8 @@ __global__ __launch_bounds__(kBlock) void k_tan_forces(Dev d, Tan t, Phys p, con
   // own records and the first row slot before the replica lookup (padded
   // arrays: padding lanes read in bounds and are masked)
   const uint4 ui = pick(d.u, par)[i];
-  const float4 wi = w[i];
+  const float4 wi = SCALE ? make_float4(0.f, 0.f, 0.f, 0.f) : w[i];
+  const float4 gwi = ADJ && a.aW != 0.f ? a.gw[i] : make_float4(0.f, 0.f, 0.f, 0.f);
   const float4* m = d.mom + 3 * (size_t)i;
   const float4* md = t.mdot + 3 * (size_t)i;
   const float4 a0 = m[0], a1 = m[1], a2 = m[2], b0 = md[0], b1 = md[1], b2 = md[2];
@@ -70,7 +87,7 @@ __global__ __launch_bounds__(kBlock) void k_tan_forces(Dev d, Tan t, Phys p, con
   // term weights (sw_grad's term mask; an adjoint frame always takes both):
   // the pair derivative scales the two-body force and virial, the leg factor
   // lambda eps e_j every three-body contribution
-  const float m2 = ADJ ? 1.f : p.term2, m3 = ADJ ? 1.f : p.term3;
+  const float m2 = KIND == TK_GRAD ? p.term2 : 1.f, m3 = KIND == TK_GRAD ? p.term3 : 1.f;
   D Tm[6], Vm[3], Sm{0.f, 0.f};
   float E2i = 0.f, E3i = 0.f;
   for (int k = 0; k < 6; ++k) Tm[k] = D{0.f, 0.f};
@@ -91,14 +108,14 @@ __global__ __launch_bounds__(kBlock) void k_tan_forces(Dev d, Tan t, Phys p, con
     // the neighbour's position, tangent and moments in one batch, read
     // whatever the distance (entries beyond the cutoff are ignored)
     const uint4 uj = pick(d.u, par)[j];
-    const float4 wj = w[j];
+    const float4 wj = SCALE ? make_float4(0.f, 0.f, 0.f, 0.f) : w[j];
     const float4* mj = d.mom + 3 * (size_t)j;
     const float4* mdj = t.mdot + 3 * (size_t)j;
     const float4 na = mj[0], nb = mj[1], nc = mj[2], da = mdj[0], db = mdj[1], dc = mdj[2];
     asm volatile("" ::"v"(uj.x), "v"(wj.x), "v"(na.x), "v"(nb.x), "v"(nc.x), "v"(da.x), "v"(db.x), "v"(dc.x));
     const float3 dd = disp(ui, uj, R.scale[0], R.scale[1], R.scale[2]);
     if (dd.x * dd.x + dd.y * dd.y + dd.z * dd.z < p.rc2) {
-      const Leg G = leg_dual(dd, sub3(wj, wi), p);
+      const Leg G = leg_dual(dd, SCALE ? dd : sub3(wj, wi), p);
       const D idr2 = G.idr * G.idr;
       const D e1 = ex2D(p.sig_l2e * G.idr);
       const D sr = p.sig * G.ir, s2 = sr * sr, s4 = s2 * s2;
@@ -148,8 +165,12 @@ __global__ __launch_bounds__(kBlock) void k_tan_forces(Dev d, Tan t, Phys p, con
   w2.v = group_sum<LPA>(w2.v); w2.d = group_sum<LPA>(w2.d);
   w3.v = group_sum<LPA>(w3.v); w3.d = group_sum<LPA>(w3.d);
   if (lane == 0) {
-    double q[kTQ] = {0, 0, 0, 0, 0, 0, 0};
-    if (real) {
+    double q[kTQ] = {0, 0, 0, 0, 0, 0, 0, 0};
+    if (real && SCALE) {
+      // the virial gradient of this frame, and dW/ds for the sigma derivative
+      t.gw[i] = make_float4(fx.v + fx.d, fy.v + fy.d, fz.v + fz.d, 0.f);
+      q[7] = (double)w2.d + (double)w3.d;
+    } else if (real) {
       d.f[i] = make_float4(fx.v, fy.v, fz.v, 0.f);
       t.fdot[i] = make_float4(fx.d, fy.d, fz.d, 0.f);
       t.f3[i] = make_float4(gx, gy, gz, 0.f);
@@ -163,6 +184,11 @@ __global__ __launch_bounds__(kBlock) void k_tan_forces(Dev d, Tan t, Phys p, con
         xb.x += a.coef_cm * fx.d - (a.aU * fx.v + a.a3 * gx) * norm;
         xb.y += a.coef_cm * fy.d - (a.aU * fy.v + a.a3 * gy) * norm;
         xb.z += a.coef_cm * fz.d - (a.aU * fz.v + a.a3 * gz) * norm;
+        if (a.aW != 0.f) {   // + aW dW/dx / (N (S + 1))
+          xb.x += a.aW * norm * gwi.x;
+          xb.y += a.aW * norm * gwi.y;
+          xb.z += a.aW * norm * gwi.z;
+        }
         xb.w = 0.f;
         a.xb[i] = xb;
         if (!a.last)
@@ -182,9 +208,10 @@ __global__ __launch_bounds__(kBlock) void k_tan_forces(Dev d, Tan t, Phys p, con
     double acc = 0.0;
     for (int k = 0; k < APB; ++k) acc += red[k * kTQ + threadIdx.x];
     const size_t slot = (size_t)threadIdx.x * (d.npad / APB) + bid;
-    if (ADJ) {
+    if (ADJ || SCALE) {
       // each block owns its slot: the frames of a sweep add up in frame order
-      a.tacc[slot] += (threadIdx.x >= 4 ? a.coef_d : 1.0) * acc;
+      // (the w.F terms weighted by the frame coefficient; values unweighted)
+      a.tacc[slot] += (threadIdx.x >= 4 && threadIdx.x < 7 ? a.coef_d : 1.0) * acc;
     } else {
       t.tpartial[slot] = acc;
     }
@@ -197,6 +224,7 @@ __global__ __launch_bounds__(kBlock) void k_tan_forces(Dev d, Tan t, Phys p, con
 struct PTerm {
   double lam, eps, sig;
   double m2, m3;          // term weights of the energies in dU (the tangent pass weights the rest)
+  double aW;              // loss weight of the virial trace (sums of an adjoint sweep)
   double* wdF;
   double* dU;
   double* thbar;
@@ -235,16 +263,19 @@ __global__ __launch_bounds__(kBlock) void k_reduce_tan(Dev d, Tan t, int apb, PT
         q[k] = ((part[0][k] + part[1][k]) + part[2][k]) + part[3][k];
         t.tsum[rep * kTQ + k] = q[k];
       }
-      const double E2 = q[0], E3 = q[1], W2 = q[2], W3 = q[3], wF = q[4], wF3 = q[5], Wd = q[6];
+      const double E2 = q[0], E3 = q[1], W2 = q[2], W3 = q[3], wF = q[4], wF3 = q[5], Wd = q[6], Ws = q[7];
       const double g[3] = {wF3 / pt.lam, wF / pt.eps, -Wd / pt.sig};   // w . dF/d(lambda, eps, sigma)
       const double u[3] = {pt.m3 * E3 / pt.lam, (pt.m2 * E2 + pt.m3 * E3) / pt.eps, (W2 + W3) / pt.sig};
       const double u3[3] = {E3 / pt.lam, E3 / pt.eps, W3 / pt.sig};
       if (pt.wdF) for (int k = 0; k < 3; ++k) pt.wdF[3 * rep + k] = g[k];
       if (pt.dU) for (int k = 0; k < 3; ++k) pt.dU[3 * rep + k] = u[k];
       const double norm = 1.0 / ((double)R.n * (pt.S + 1));
+      // the virial trace: dW/dlambda = W3/lambda, dW/deps = W/eps, dW/dsigma = -(1/sigma) dW/ds
+      const double uw[3] = {W3 / pt.lam, (W2 + W3) / pt.eps, -Ws / pt.sig};
       if (pt.thbar)
-        for (int k = 0; k < 3; ++k) pt.thbar[3 * rep + k] += pt.coef_cm * g[k] + norm * (pt.aU * u[k] + pt.a3 * u3[k]);
-      if (pt.loss) pt.loss[rep] += norm * (pt.aU * (E2 + E3) + pt.a3 * E3);
+        for (int k = 0; k < 3; ++k)
+          pt.thbar[3 * rep + k] += pt.coef_cm * g[k] + norm * (pt.aU * u[k] + pt.a3 * u3[k] + pt.aW * uw[k]);
+      if (pt.loss) pt.loss[rep] += norm * (pt.aU * (E2 + E3) + pt.a3 * E3 + pt.aW * (W2 + W3));
     }
     __syncthreads();
   }
@@ -279,14 +310,16 @@ inline unsigned nb(long long n) { return (unsigned)((n + kBlock - 1) / kBlock); 
 
 template <int LPA>
 hipError_t tan_launch(const Dev& d, const Tan& t, const Phys& p, const float4* w, int par, const Adj* adj,
-                      const PTerm& pt, hipStream_t s) {
+                      const PTerm& pt, hipStream_t s, bool scale) {
   constexpr int APB = kBlock / LPA;
   const unsigned grid = (unsigned)(d.npad / APB);
   Adj a = adj ? *adj : Adj{};
-  if (adj) {   // an adjoint frame accumulates; the sweep reduces once at its end
-    hipLaunchKernelGGL((k_tan_forces<LPA, true>), dim3(grid), dim3(kBlock), 0, s, d, t, p, w, par, a);
+  if (scale) {   // the frame's virial gradient; its dW/ds joins the sweep's sums
+    hipLaunchKernelGGL((k_tan_forces<LPA, TK_SCALE>), dim3(grid), dim3(kBlock), 0, s, d, t, p, w, par, a);
+  } else if (adj) {   // an adjoint frame accumulates; the sweep reduces once at its end
+    hipLaunchKernelGGL((k_tan_forces<LPA, TK_ADJ>), dim3(grid), dim3(kBlock), 0, s, d, t, p, w, par, a);
   } else {
-    hipLaunchKernelGGL((k_tan_forces<LPA, false>), dim3(grid), dim3(kBlock), 0, s, d, t, p, w, par, a);
+    hipLaunchKernelGGL((k_tan_forces<LPA, TK_GRAD>), dim3(grid), dim3(kBlock), 0, s, d, t, p, w, par, a);
     hipLaunchKernelGGL(k_reduce_tan, dim3((unsigned)std::min(d.R, 4096)), dim3(kBlock), 0, s, d, t, APB, pt);
   }
   return hipGetLastError();
@@ -300,15 +333,15 @@ hipError_t launch_tan_reduce(const Dev& d, const Tan& t, int lpa, const PTerm& p
 }
 
 // Tangent forces, then (outside an adjoint sweep) the per-replica sums and
-// the parameter terms of pt.
+// the parameter terms of pt; with scale, the scaling pass of an adjoint frame.
 hipError_t launch_tan_forces(const Dev& d, const Tan& t, const Phys& p, int lpa, const float4* w, int par,
-                             const Adj* adj, const PTerm& pt, hipStream_t s) {
+                             const Adj* adj, const PTerm& pt, hipStream_t s, bool scale = false) {
   switch (lpa) {
-    case 4: return tan_launch<4>(d, t, p, w, par, adj, pt, s);
-    case 8: return tan_launch<8>(d, t, p, w, par, adj, pt, s);
-    case 16: return tan_launch<16>(d, t, p, w, par, adj, pt, s);
-    case 32: return tan_launch<32>(d, t, p, w, par, adj, pt, s);
-    case 64: return tan_launch<64>(d, t, p, w, par, adj, pt, s);
+    case 4: return tan_launch<4>(d, t, p, w, par, adj, pt, s, scale);
+    case 8: return tan_launch<8>(d, t, p, w, par, adj, pt, s, scale);
+    case 16: return tan_launch<16>(d, t, p, w, par, adj, pt, s, scale);
+    case 32: return tan_launch<32>(d, t, p, w, par, adj, pt, s, scale);
+    case 64: return tan_launch<64>(d, t, p, w, par, adj, pt, s, scale);
   }
   return hipErrorInvalidValue;
 }
@@ -487,6 +520,19 @@ hipError_t tangent_frame(sw_ctx* c, const Dev& dv, const Phys& ph, int lpa, int 
   return launch_tan_forces(dv, c->t, ph, lpa, w, par, adj, pt, s);
 }
 
+// Scaling pass of an adjoint frame with a virial term in the loss: moments
+// and forces with their tangent along a uniform scaling of every leg, which
+// leave the frame's virial gradient in c->t.gw and add dW/ds to the sweep's
+// sums.  The rows are rebuilt here when the frame's flag asks for it, and
+// the flag is then cleared, so the frame's tangent pass that follows reads
+// the same rows without building them again.
+hipError_t scale_frame(sw_ctx* c, const Dev& dv, const Phys& ph, int lpa, int par, const Adj* adj, hipStream_t s) {
+  hipError_t e;
+  if ((e = launch_moments_tan(dv, ph, lpa, par, 0, nullptr, c->t.mdot, s)) != hipSuccess) return e;
+  if ((e = launch_tan_forces(dv, c->t, ph, lpa, nullptr, par, adj, PTerm{}, s, true)) != hipSuccess) return e;
+  return launch_fill_i32(dv.dflag + (size_t)par * dv.R, 0, dv.R, s);
+}
+
 // Tangent pass at positions u[0] along w; rows rebuilt first, or kept when
 // no atom has moved half the skin since they were built (the skin scaled by
 // any change of the box since the build).
@@ -516,7 +562,7 @@ int sw_grad(sw_ctx* ctx, const float* x, const float* w, const sw_params* params
   ph.term2 = (term_mask & SW_TERM_TWO_BODY) ? 1.f : 0.f;
   ph.term3 = (term_mask & SW_TERM_THREE_BODY) ? 1.f : 0.f;
   const int lpa = lpa_for(ctx);
-  const PTerm pt{params->lambda, params->epsilon, params->sigma, (double)ph.term2, (double)ph.term3,
+  const PTerm pt{params->lambda, params->epsilon, params->sigma, (double)ph.term2, (double)ph.term3, 0.0,
                  wdF, dU, nullptr, nullptr, 0.0, 0.0, 0.0, 0};
   for (int attempt = 0; attempt < 6; ++attempt) {
     hipError_t e;
@@ -544,10 +590,12 @@ int sw_grad(sw_ctx* ctx, const float* x, const float* w, const sw_params* params
 }
 
 int sw_adjoint(sw_ctx* ctx, const float* x0, const float* v0, const sw_params* params, double mass, double dt,
-               int nsteps, int ckpt_every, double aU, double a3, const float* xbar_S, const float* vbar_S,
-               double* loss, float* xbar0, float* vbar0, double* thbar, float* xS, float* vS, void* stream) {
+               int nsteps, int ckpt_every, double aU, double a3, double aW, const float* xbar_S,
+               const float* vbar_S, double* loss, float* xbar0, float* vbar0, double* thbar, float* xS, float* vS,
+               void* stream) {
   if (!ctx || !x0 || !v0 || !loss || !xbar0 || !vbar0 || !thbar) return SW_EINVAL;
-  if (!(mass > 0.0) || !(dt > 0.0) || nsteps < 0 || ckpt_every <= 0 || !std::isfinite(aU) || !std::isfinite(a3))
+  if (!(mass > 0.0) || !(dt > 0.0) || nsteps < 0 || ckpt_every <= 0 || !std::isfinite(aU) || !std::isfinite(a3) ||
+      !std::isfinite(aW))
     return SW_EINVAL;
   hipStream_t s = (hipStream_t)stream;
   Phys ph{};
@@ -645,7 +693,8 @@ int sw_adjoint(sw_ctx* ctx, const float* x0, const float* v0, const sw_params* p
           const double coef = (sf == S || sf == 0) ? 0.5 * dt : dt;
           // frame sf - 1 is frame k - 1 of this store (a store holds its segment's start)
           const Adj a{xb, vb[cur ^ 1], (float)(coef * c_m), (float)dt, (float)aU, (float)a3, S, sf == 0,
-                      coef * c_m, tacc, sf > 0 ? fs.u + (size_t)(k - 1) * np : nullptr};
+                      coef * c_m, tacc, sf > 0 ? fs.u + (size_t)(k - 1) * np : nullptr, (float)aW, ctx->t.gw};
+          if (aW != 0.0 && (r = scale_frame(ctx, dv, ph, lpa, par, &a, q)) != hipSuccess) return r;
           if ((r = tangent_frame(ctx, dv, ph, lpa, par, 0, vb[cur], &a, PTerm{}, q)) != hipSuccess) return r;
           if (sf > 0) cur ^= 1;
         }
@@ -653,12 +702,13 @@ int sw_adjoint(sw_ctx* ctx, const float* x0, const float* v0, const sw_params* p
       // parameter adjoint and loss from the sums of all frames (weights already applied)
       Tan tr = ctx->t;
       tr.tpartial = tacc;
-      const PTerm pt{params->lambda, params->epsilon, params->sigma, 1.0, 1.0, nullptr, nullptr, thb, lossb, 1.0, aU, a3, S};
+      const PTerm pt{params->lambda, params->epsilon, params->sigma, 1.0, 1.0, aW, nullptr, nullptr, thb, lossb, 1.0,
+                     aU, a3, S};
       return launch_tan_reduce(ctx->d, tr, lpa, pt, q);
     };
     if (ctx->tune.graph_steps > 0) {
       // replay a captured core when everything it reads is unchanged
-      const double sc[9] = {aU, a3, dt, mass, c_m, params->lambda, params->epsilon, params->sigma, (double)S};
+      const double sc[10] = {aU, a3, aW, dt, mass, c_m, params->lambda, params->epsilon, params->sigma, (double)S};
       const int meta[5] = {K, nseg, lpa, ctx->alloc_gen, ctx->R};
       std::vector<unsigned char> key(sizeof(Dev) + sizeof(Tan) + sizeof(Phys) + sizeof sc + sizeof meta +
                                      sizeof(void*) * ctx->adj_buf.size());

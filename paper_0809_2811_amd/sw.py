@@ -93,7 +93,7 @@ def lib():
         L.sw_forces.argtypes = [vp, fp, P(sw_params), fp, vp, vp, vp]
         L.sw_step.argtypes = [vp, fp, fp, fp, P(sw_params), dp, dp, ip, ip, P(ctypes.c_double), dp, vp, ip, vp]
         L.sw_grad.argtypes = [vp, fp, fp, P(sw_params), ip, fp, vp, vp, vp]
-        L.sw_adjoint.argtypes = [vp, fp, fp, P(sw_params), dp, dp, ip, ip, dp, dp, fp, fp, vp, fp, fp, vp,
+        L.sw_adjoint.argtypes = [vp, fp, fp, P(sw_params), dp, dp, ip, ip, dp, dp, dp, fp, fp, vp, fp, fp, vp,
                                  fp, fp, vp]
         L.sw_set_tuning.argtypes = [vp, P(sw_tuning)]
         L.sw_get_tuning.argtypes = [vp, P(sw_tuning)]
@@ -240,11 +240,12 @@ def sw_grad(ctx: int, x, w, params: sw_params, hvp, wdF=None, dU=None, R: int = 
 
 
 def sw_adjoint(ctx: int, x0, v0, params: sw_params, mass: float, dt: float, nsteps: int, ckpt_every: int,
-               aU: float, a3: float, xbar_S, vbar_S, loss, xbar0, vbar0, thbar, xS=None, vS=None, R: int = 1):
+               aU: float, a3: float, xbar_S, vbar_S, loss, xbar0, vbar0, thbar, xS=None, vS=None, R: int = 1,
+               aW: float = 0.0):
     n = x0.shape[0]
     opt = lambda t, name: None if t is None else _atoms(t, n, name)  # noqa: E731
     _check(lib().sw_adjoint(ctypes.c_void_p(ctx), _atoms(x0, n, "x0"), _atoms(v0, n, "v0"), ctypes.byref(params),
-                            float(mass), float(dt), int(nsteps), int(ckpt_every), float(aU), float(a3),
+                            float(mass), float(dt), int(nsteps), int(ckpt_every), float(aU), float(a3), float(aW),
                             opt(xbar_S, "xbar_S"), opt(vbar_S, "vbar_S"), _doubles(loss, (R,), "loss"),
                             _atoms(xbar0, n, "xbar0"), _atoms(vbar0, n, "vbar0"), _doubles(thbar, (R, 3), "thbar"),
                             opt(xS, "xS"), opt(vS, "vS"), _stream()), "sw_adjoint")
@@ -463,9 +464,11 @@ class Context:
         return hvp, wdF, dU
 
     def adjoint(self, x0, v0, nsteps: int, dt: float = 10.0, mass: float = 18.015, ckpt_every: int = 20,
-                aU: float = 1.0, a3: float = 1.0, params: Optional[sw_params] = None, xbar_S=None, vbar_S=None):
+                aU: float = 1.0, a3: float = 1.0, params: Optional[sw_params] = None, xbar_S=None, vbar_S=None,
+                aW: float = 0.0):
         """Loss, dL/dx0, dL/dv0, dL/d(lambda, eps, sigma) and the final state of
-        an NVE trajectory (see sw_adjoint in include/sw.h)."""
+        an NVE trajectory (see sw_adjoint in include/sw.h; aW weights the
+        virial trace)."""
         torch = _torch()
         params = params_mw() if params is None else params
         loss = torch.empty(self.R, dtype=torch.float64, device=x0.device)
@@ -473,7 +476,7 @@ class Context:
         xbar0, vbar0 = torch.empty_like(x0), torch.empty_like(x0)
         xS, vS = torch.empty_like(x0), torch.empty_like(x0)
         sw_adjoint(self.handle, x0, v0, params, mass, dt, nsteps, ckpt_every, aU, a3, xbar_S, vbar_S, loss,
-                   xbar0, vbar0, thbar, xS, vS, R=self.R)
+                   xbar0, vbar0, thbar, xS, vS, R=self.R, aW=aW)
         return dict(loss=loss, xbar0=xbar0, vbar0=vbar0, thbar=thbar, xS=xS, vS=vS)
 
     def npt(self, x, v, nsteps: int, T0, p_bar=0.0, tau_T: float = 1000.0, tau_P: float = 2500.0, chain: int = 3,

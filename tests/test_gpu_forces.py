@@ -201,3 +201,33 @@ def test_clusters_against_closed_forms(lpa):
         assert abs(out["E"][0, 1] - o["E3"]) <= TOL * abs(o["E3"])
         assert force_error(out["F"], o["F"]) <= TOL, name
         out["ctx"].close()
+
+
+@pytest.mark.parametrize("sigma", [2.3918898517523677, 2.38, 2.41, 2.3925])
+def test_pair_swept_through_the_cutoff(sigma):
+    """A pair swept one float ulp at a time through r = a sigma (and a third
+    atom 3.2 A from one of them, so three-body terms see the swept leg).  The radial factors are exp(sigma / (r - a sigma)) and
+    exp(gamma sigma / (r - a sigma)) (Sec. II.A): they vanish at the cutoff, so
+    the energies and forces stay finite and equal the oracle's for every
+    distance.  The sigmas include ones whose float r^2 bound lets the rounded
+    r reach a sigma (exp(+inf) without the guard)."""
+    from paper_0809_2811_amd import sw
+    P = sw.params_mw(sigma=sigma)
+    Po = oracle.params(sig=sigma)
+    L = np.array([16.0, 16.0, 16.0])
+    rc = np.float32(1.8 * sigma)
+    ulp = np.float32(2.0 ** -21)          # float spacing over [4, 8) A
+    assert 4.0 <= rc < 8.0
+    x = f32(np.array([[0.0, 8.0, 8.0], [0.0, 8.0, 8.0], [0.0, 11.2, 8.0]]))
+    ctx = sw.Context([0, 3], [L], cutoff=1.8 * 2.45, skin=0.5, nbr_capacity=8, tuning=dict(lanes_per_atom=8))
+    for m in range(-40, 5):
+        x[1, 0] = np.float32(rc + np.float32(m) * ulp)
+        f, e, w = ctx.forces(to_dev(x), P)
+        F, E = from_dev(f), e.cpu().numpy()[0]
+        assert np.all(np.isfinite(F)) and np.all(np.isfinite(E)), (m, E)
+        o = oracle.forces(x, L, Po)
+        scale = abs(o["E2"]) + abs(o["E3"])
+        assert abs(E[0] - o["E2"]) <= TOL * scale, (m, E, o["E2"])
+        assert abs(E[1] - o["E3"]) <= TOL * scale, (m, E, o["E3"])
+        assert force_error(F, o["F"]) <= TOL, m
+    ctx.close()
