@@ -24,6 +24,7 @@
 namespace swk {
 
 constexpr int kBlock = 256;        // threads per block of every atom kernel
+constexpr int kRankInts = 16 + 27;  // cell-start mask (8 words + prefix counts) and cell bases of a row rebuild
 constexpr int kTile = 64;          // replicas are padded to multiples of this
 constexpr int kMaxLPA = 64;        // most lanes per atom of any kernel variant
 constexpr int kMinAPB = kBlock / kMaxLPA;   // fewest atoms per block: sizes per-block buffers

@@ -272,6 +272,14 @@ __device__ __forceinline__ void clear_next(const Dev& d, int par, int b, int G) 
   for (int c = b * kBlock + threadIdx.x; c < d.ctot; c += G * kBlock) pick(d.gcnt, par ^ 1)[c] = 0;
 }
 
+// The group's candidate count, and INT_MAX in the slots past it up to a
+// multiple of four (the capacity is one), so the sort reads whole quads.
+__device__ __forceinline__ void pad_count(int* cand, int* cnt, int run, int cap) {
+  *cnt = run;
+  const int t = min(run, cap);
+  for (int z = t; z < ((t + 3) & ~3); ++z) cand[z] = 0x7fffffff;
+}
+
 // lds: [APB][cap] candidates, [APB][cap] sorted, [APB] counts, [APB][56] cell
 // prefix and ids; with 16 or more lanes per atom also [APB][cap] candidate
 // positions (16-byte aligned)
@@ -370,17 +378,69 @@ __device__ void moments_tile(const Dev& d, const Phys& p, int par, int force_reb
       const int up = __shfl_up(incl, off, LPA);
       if (lane >= off) incl += up;
     }
+    // With fewer than 16 lanes per atom (and a row capacity that holds it),
+    // the candidate -> cell lookup is a rank: bit p of a 256-bit mask marks
+    // the first candidate of a non-empty cell, and the r-th non-empty cell's
+    // entry base sits in a table, so candidate k < 256 reads entry
+    // base[rank(k)] + k, with rank(k) = (set bits at or below k) - 1.  Both
+    // live in the sorted-row area, unused until the sort.  Mask words and
+    // their prefix counts interleave: msk[2w] = word w, msk[2w + 1] = bits
+    // set in the words below w.
+    constexpr bool kRankLookup = LPA < 16;
+    const bool rank_ok = kRankLookup && cap >= kRankInts;
+    int* msk = srt;
+    int* cbase = srt + 16;
     if (real) {
       int run = incl - own;
+      int ne = 0;
+      if (rank_ok) {
+#pragma unroll
+        for (int q = 0; q < CPL; ++q) ne += mc[q] > 0;
+        for (int w = lane; w < 8; w += LPA) msk[2 * w] = 0;
+      }
+      int nrank = ne;                        // inclusive scan of non-empty cells per lane
+#pragma unroll
+      for (int off = 1; off < LPA; off <<= 1) {
+        const int up = __shfl_up(nrank, off, LPA);
+        if (lane >= off) nrank += up;
+      }
+      nrank -= ne;
       if (lane == 0) pre[0] = 0;
 #pragma unroll
       for (int q = 0; q < CPL; ++q) {
         const int c = lane * CPL + q;
+        if (rank_ok && mc[q] > 0) {
+          if (run < 256) atomicOr(reinterpret_cast<unsigned*>(&msk[2 * (run >> 5)]), 1u << (run & 31));
+          cbase[nrank++] = (int)((unsigned)cl[q] * (unsigned)ccap - (unsigned)run);   // mod 2^32, like at below
+        }
         run += mc[q];
         if (c < 27) {
           pre[c + 1] = run;
           cid[c] = cl[q];
         }
+      }
+    }
+    __syncthreads();
+    if (real && rank_ok) {
+      // exclusive prefix of the mask words' bit counts (words [lane * WPL, +WPL))
+      constexpr int WPL = kRankLookup ? 8 / LPA : 1;
+      int pc[WPL], tot = 0;
+#pragma unroll
+      for (int j = 0; j < WPL; ++j) {
+        pc[j] = __builtin_popcount((unsigned)msk[2 * (lane * WPL + j)]);
+        tot += pc[j];
+      }
+      int inc = tot;
+#pragma unroll
+      for (int off = 1; off < LPA; off <<= 1) {
+        const int up = __shfl_up(inc, off, LPA);
+        if (lane >= off) inc += up;
+      }
+      int ex = inc - tot;
+#pragma unroll
+      for (int j = 0; j < WPL; ++j) {
+        msk[2 * (lane * WPL + j) + 1] = ex;
+        ex += pc[j];
       }
     }
     __syncthreads();
@@ -431,15 +491,15 @@ __device__ void moments_tile(const Dev& d, const Phys& p, int par, int force_reb
           run += __popcll(m);
         }
       }
-      if (lane == 0) cnt[g] = run;
+      if (lane == 0) pad_count(cand, cnt + g, run, cap);
     } else if (real) {
       // Few lanes per atom (large boxes, the CU full of waves: bound by
-      // instruction issue).  Each slot searches its cell on its own and skips
-      // the search and the load past the end; entry indices are 32-bit, and
-      // accepted entries are compacted with a group ballot (no LDS atomics).
+      // instruction issue).  Each slot finds its cell entry on its own (the
+      // rank lookup above, else a binary search over the cell prefix) and
+      // skips the load past the end; entry indices are 32-bit, and accepted
+      // entries are compacted with a group ballot (no LDS atomics).
       const int ncand = pre[27];
       const float rl2 = p.rl2;
-      constexpr int kCL = 8;
       const int wl = threadIdx.x & 63;
       const int gsh = wl & ~(LPA - 1);                           // the group's first lane
       // (this branch runs with fewer than 16 lanes per atom; the mask is
@@ -447,34 +507,47 @@ __device__ void moments_tile(const Dev& d, const Phys& p, int par, int force_reb
       constexpr unsigned gmk = LPA < 32 ? (1u << (LPA % 32)) - 1u : ~0u;
       const unsigned gbl = (1u << (wl - gsh)) - 1u;
       int run = 0;                                               // entries appended so far (group-uniform)
-      for (int k0 = lane; k0 < ncand; k0 += kCL * LPA) {
-        uint4 e[kCL];
+      constexpr int kCL = 8;
+      auto scan = [&](auto entry_at) {
+        for (int k0 = lane; k0 < ncand; k0 += kCL * LPA) {
+          uint4 e[kCL];
 #pragma unroll
-        for (int t = 0; t < kCL; ++t) {
-          const int k = k0 + t * LPA;
-          e[t] = make_uint4(ui.x, ui.y, ui.z, (unsigned)i);
-          if (k < ncand) {
-            int c = 0;
+          for (int t = 0; t < kCL; ++t) {
+            const int k = k0 + t * LPA;
+            e[t] = make_uint4(ui.x, ui.y, ui.z, (unsigned)i);
+            if (k < ncand) e[t] = gm[entry_at(k)];
+          }
 #pragma unroll
-            for (int step = 16; step >= 1; step >>= 1)
-              if (c + step < 27 && pre[c + step] <= k) c += step;
-            e[t] = gm[(unsigned)cid[c] * (unsigned)ccap + (unsigned)(k - pre[c])];
+          for (int t = 0; t < kCL; ++t) {
+            const int j = (int)e[t].w;
+            const float3 dd = disp(ui, e[t], sc0, sc1, sc2);
+            const bool acc = j != i && dd.x * dd.x + dd.y * dd.y + dd.z * dd.z < rl2;
+            const unsigned m = (unsigned)(__ballot(acc) >> gsh) & gmk;
+            if (acc) {
+              const int sl = run + __builtin_popcount(m & gbl);
+              if (sl < cap) cand[sl] = j;
+            }
+            run += __builtin_popcount(m);
           }
         }
+      };
+      // group-uniform choice; the search covers atoms with over 256 candidates
+      if (rank_ok && ncand <= 256) {
+        scan([&](int k) -> unsigned {
+          const int w = k >> 5;
+          const unsigned bits = (unsigned)msk[2 * w] & ((2u << (k & 31)) - 1u);
+          return (unsigned)cbase[msk[2 * w + 1] + __builtin_popcount(bits) - 1] + (unsigned)k;
+        });
+      } else {
+        scan([&](int k) -> unsigned {
+          int c = 0;
 #pragma unroll
-        for (int t = 0; t < kCL; ++t) {
-          const int j = (int)e[t].w;
-          const float3 dd = disp(ui, e[t], sc0, sc1, sc2);
-          const bool acc = j != i && dd.x * dd.x + dd.y * dd.y + dd.z * dd.z < rl2;
-          const unsigned m = (unsigned)(__ballot(acc) >> gsh) & gmk;
-          if (acc) {
-            const int sl = run + __builtin_popcount(m & gbl);
-            if (sl < cap) cand[sl] = j;
-          }
-          run += __builtin_popcount(m);
-        }
+          for (int step = 16; step >= 1; step >>= 1)
+            if (c + step < 27 && pre[c + step] <= k) c += step;
+          return (unsigned)cid[c] * (unsigned)ccap + (unsigned)(k - pre[c]);
+        });
       }
-      if (lane == 0) cnt[g] = run;
+      if (lane == 0) pad_count(cand, cnt + g, run, cap);
     }
     __syncthreads();
     int total = cnt[g];
@@ -487,8 +560,8 @@ __device__ void moments_tile(const Dev& d, const Phys& p, int par, int force_reb
       // Ascending neighbour index: the row and every later sum over it are
       // independent of the order the cells were filled in.  With candidate
       // positions in LDS the sorted list holds candidate slots, else indices.
-      // The list is read four entries at a time (16-byte aligned; entries
-      // past the count are masked).
+      // The list is read four entries at a time (16-byte aligned; the
+      // entries past the count up to a multiple of four hold INT_MAX).
       const int4* cand4 = reinterpret_cast<const int4*>(cand);
       for (int k = lane; k < total; k += LPA) {
         const int vj = cand[k];
@@ -496,8 +569,7 @@ __device__ void moments_tile(const Dev& d, const Phys& p, int par, int force_reb
 #pragma unroll 1
         for (int q = 0; q < total; q += 4) {
           const int4 w = cand4[q >> 2];
-          rank += (w.x < vj) + (q + 1 < total && w.y < vj) + (q + 2 < total && w.z < vj) +
-                  (q + 3 < total && w.w < vj);
+          rank += (w.x < vj) + (w.y < vj) + (w.z < vj) + (w.w < vj);
         }
         srt[rank] = (LPA >= 16 && !TAN) ? k : vj;
         d.nl[(size_t)i * cap + rank] = vj;

@@ -231,3 +231,33 @@ def test_pair_swept_through_the_cutoff(sigma):
         assert abs(E[1] - o["E3"]) <= TOL * scale, (m, E, o["E3"])
         assert force_error(F, o["F"]) <= TOL, m
     ctx.close()
+
+
+@pytest.mark.parametrize("lpa", [4, 8])
+@pytest.mark.parametrize("vacuum,skin", [(30.0, 2.69), (0.0, 3.0)])
+def test_rows_when_cells_hold_many_candidates(lpa, vacuum, skin):
+    """Row rebuilds whose 27 cells hold more than 256 candidates.  The
+    4096-atom liquid as a slab (30 A of vacuum along z, 2.69 A skin: 7 x 7 x
+    11 cells) gives about 340 candidates in the bulk and about 200 near the
+    surfaces, so waves mix atoms on either side of 256; the bulk liquid with a
+    3 A skin gives about 510 for every atom.  Rows equal the oracle's sets and
+    forces match the oracle."""
+    from paper_0809_2811_amd import sw
+    x, _, L = liquid(2)
+    x = f32(x)
+    L = np.array([L[0], L[1], L[2] + vacuum])
+    rl = RC + skin
+    cap = 80
+    ctx = sw.Context([0, len(x)], [L], cutoff=RC, skin=skin, nbr_capacity=cap, tuning=dict(lanes_per_atom=lpa))
+    f, e, w = ctx.forces(to_dev(x))
+    counts, rows = ctx.neighbors(cap)
+    ref = oracle.neighbour_lists(x, L, rl)
+    for i in range(len(x)):
+        got = rows[i, :counts[i]]
+        if not np.array_equal(got, ref[i]):
+            diff = np.setxor1d(got, ref[i])
+            d = x[diff] - x[i]
+            d -= L * np.round(d / L)
+            assert np.all(np.abs(np.linalg.norm(d, axis=1) - rl) < 1e-4), (i, diff)
+    check(x, L, dict(F=from_dev(f), E=e.cpu().numpy(), W=w.cpu().numpy()))
+    ctx.close()
