@@ -1,16 +1,16 @@
 """HBM traffic of the step kernels from two rocprofv3 counter passes.
 
-`rocprofv3 --pmc FETCH_SIZE` and then `--pmc WRITE_SIZE` (each its own run,
-CSV output) over
+`rocprofv3 --kernel-trace --pmc FETCH_SIZE` and then `--pmc WRITE_SIZE` (each
+its own run, CSV output) over
 
-    python3 bench.py --forms large --no-cpu --steps 300 --warmup 10 --copy-mib 1024 --graph-steps 0
+    python3 bench.py --forms liquid4096 --no-cpu --steps 300 --warmup 10 --copy-mib 1024 --graph-steps 0
 
 give per-dispatch KiB for every launch.  The run starts with a plain copy
 (`out = -in` over 1024 MiB of fp32: 1 GiB read, 1 GiB written), whose
 readings scale each counter to bytes.  `reduce()` averages the scaled
 counters over the launches of the NVE phase (every `k_forces<L, 2, false>`
 launch and each `k_moments<L, false>` launch directly followed by one) of the
-4096-atom main line (L = 32) and the 262144-atom box (L = 8) and writes the
+4096-atom liquid (L = 32) and the 262144-atom box (L = 8) and writes the
 record next to this file, keyed by a digest of the kernel sources so that the
 benchmark reports it only while they are unchanged:
 
@@ -68,8 +68,22 @@ def _rows(directory: str, counter: str):
     return r
 
 
-def _per_kernel(rows):
+def _durations(directory: str):
+    """Kernel durations (us) by dispatch id from the same run's kernel trace, if any."""
+    files = glob.glob(os.path.join(directory, "**", "*kernel_trace.csv"), recursive=True)
+    if not files:
+        return {}
+    with open(files[0]) as fh:
+        return {x["Dispatch_Id"]: (int(x["End_Timestamp"]) - int(x["Start_Timestamp"])) / 1e3
+                for x in csv.DictReader(fh)}
+
+
+def _per_kernel(rows, dur=None):
+    """Mean counter per launch of each NVE-phase kernel; k_moments launches
+    are also split into those that rebuilt rows and those that did not (the
+    launch durations are bimodal: split at the midpoint of their range)."""
     acc = collections.defaultdict(list)
+    mom = collections.defaultdict(list)
     for k, x in enumerate(rows):
         name = x["Kernel_Name"]
         for lpa, wl in WORKLOADS:
@@ -78,6 +92,14 @@ def _per_kernel(rows):
                 acc[f"{wl}/{fk}"].append(float(x["Counter_Value"]))
             elif mk in name and k + 1 < len(rows) and fk in rows[k + 1]["Kernel_Name"]:
                 acc[f"{wl}/{mk}"].append(float(x["Counter_Value"]))
+                if dur and x["Dispatch_Id"] in dur:
+                    mom[f"{wl}/{mk}"].append((dur[x["Dispatch_Id"]], float(x["Counter_Value"])))
+    for key, lst in mom.items():
+        lo, hi = min(d for d, _ in lst), max(d for d, _ in lst)
+        cut = 0.5 * (lo + hi)
+        for part, sel in (("rebuild", [c for d, c in lst if d > cut]), ("plain", [c for d, c in lst if d <= cut])):
+            if sel and hi > 1.5 * lo:
+                acc[f"{key}/{part}"] = sel
     return {k: (sum(v) / len(v), len(v)) for k, v in acc.items()}
 
 
@@ -89,17 +111,18 @@ def reduce(fetch_dir: str, write_dir: str, out: str = RECORD) -> dict:
         if not copy:
             raise ValueError(f"{counter}: no calibration copy launch in the trace")
         cal[counter] = sum(copy) / len(copy)
-        per[counter] = _per_kernel(rows)
+        per[counter] = _per_kernel(rows, _durations(d))
     rec = {
         "kernel_sources_sha256": kernel_sources_digest(),
         "fetch_scale": COPY_KIB / cal["FETCH_SIZE"],
         "write_scale": COPY_KIB / cal["WRITE_SIZE"],
         "calibration": {"kernel": "out = -in over 1024 MiB of fp32 (reads 1024 MiB, writes 1024 MiB)",
                         "fetch_KiB": cal["FETCH_SIZE"], "write_KiB": cal["WRITE_SIZE"], "expected_KiB": COPY_KIB},
-        "command": "rocprofv3 --pmc FETCH_SIZE (then WRITE_SIZE) --output-format csv -- python3 bench.py --forms large "
-                   "--no-cpu --steps 300 --warmup 10 --copy-mib 1024 --graph-steps 0",
+        "command": "rocprofv3 --kernel-trace --pmc FETCH_SIZE (then WRITE_SIZE) --output-format csv -- python3 "
+                   "bench.py --forms liquid4096 --no-cpu --steps 300 --warmup 10 --copy-mib 1024 --graph-steps 0",
         "selection": "launches of the NVE phase only: every k_forces<L, 2, false> launch and each k_moments<L, false> "
-                     "launch directly followed by one",
+                     "launch directly followed by one; k_moments also split by duration into launches that "
+                     "rebuilt rows and plain ones",
         "kernels": {},
     }
     for k in sorted(per["FETCH_SIZE"]):

@@ -47,3 +47,31 @@ def test_traffic_only_for_current_sources(tmp_path, monkeypatch):
     path.write_text(json.dumps(rec))
     assert hbm_counters.measured_traffic("k", "liquid4096") == 25.0
     assert hbm_counters.measured_traffic("other", "liquid4096") is None
+
+
+def _write_trace(directory, durations_ns):
+    path = os.path.join(directory, "host", "1", "run_kernel_trace.csv")
+    with open(path, "w", newline="") as fh:
+        w = csv.DictWriter(fh, fieldnames=["Dispatch_Id", "Start_Timestamp", "End_Timestamp"])
+        w.writeheader()
+        for k, d in enumerate(durations_ns):
+            w.writerow({"Dispatch_Id": k + 1, "Start_Timestamp": 1000 * k, "End_Timestamp": 1000 * k + d})
+
+
+def test_moments_split_into_rebuild_and_plain_launches(tmp_path):
+    """With the run's kernel trace beside the counters, k_moments launches
+    split at the midpoint of their (bimodal) durations; the plain average
+    over all of them stays as before."""
+    mom, frc = "void k_moments<8, false>(Dev, Phys, int, int)", "void k_forces<8, 2, false>(Dev, Phys, int)"
+    seq = [("neg_kernel", 1048576.0), (mom, 70.0), (frc, 5.0), (mom, 20.0), (frc, 5.0), (mom, 74.0), (frc, 5.0)]
+    dur = [500, 72000, 31000, 20000, 31000, 76000, 31000]
+    for sub, counter in (("f", "FETCH_SIZE"), ("w", "WRITE_SIZE")):
+        _write(str(tmp_path / sub), counter, seq)
+        _write_trace(str(tmp_path / sub), dur)
+    rec = hbm_counters.reduce(str(tmp_path / "f"), str(tmp_path / "w"), str(tmp_path / "rec.json"))
+    k = rec["kernels"]
+    base = "liquid262144/k_moments<8, false>"
+    assert k[base]["launches"] == 3 and abs(k[base]["fetch_bytes"] - 164.0 / 3 * 1024) < 1e-6
+    assert k[base + "/rebuild"] == {"fetch_bytes": 72.0 * 1024, "write_bytes": 72.0 * 1024, "launches": 2}
+    assert k[base + "/plain"] == {"fetch_bytes": 20.0 * 1024, "write_bytes": 20.0 * 1024, "launches": 1}
+    assert "liquid262144/k_forces<8, 2, false>/rebuild" not in k
