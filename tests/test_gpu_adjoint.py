@@ -5,8 +5,9 @@ Both sides start from the same FP32-rounded state.  The tangent pass is a
 derivative computed in FP32; its bar is max|d(Hw)| / RMS|Hw| <= 1e-4 and
 1e-4 relative for the parameter terms.  Trajectory gradients compare the
 GPU adjoint (of the FP32 trajectory) with the oracle's adjoint (of the FP64
-trajectory) over short horizons, and with central differences of the
-oracle's loss.
+trajectory) over horizons of up to 12 steps, at the same 1e-4 (the initial-
+state gradients as max|d xbar0| / RMS|xbar0|, measured 1e-6 to 3e-6 on the
+512-atom liquid), and with central differences of the oracle's loss.
 """
 import numpy as np
 import pytest
@@ -120,8 +121,8 @@ def test_adjoint_matches_oracle_short(S, K):
     o = oracle.adjoint(x, v, L, S, aU=1.0, a3=0.5)
     assert abs(g["loss"] - o["loss"]) <= 1e-5 * abs(o["loss"])
     assert np.allclose(g["thbar"], o["thbar"], rtol=1e-4, atol=0), (g["thbar"], o["thbar"])
-    assert rel_err(g["xbar0"], o["xbar0"]) <= 1e-3
-    assert rel_err(g["vbar0"], o["vbar0"]) <= 1e-3
+    assert rel_err(g["xbar0"], o["xbar0"]) <= 1e-4
+    assert rel_err(g["vbar0"], o["vbar0"]) <= 1e-4
 
 
 def test_terminal_seeds():
@@ -131,9 +132,9 @@ def test_terminal_seeds():
     xs, vs = f32(rng.normal(size=x.shape)), f32(rng.normal(size=x.shape))
     g = gpu_adjoint(x, v, L, 6, 3, aU=0.0, a3=0.0, xs=xs, vs=vs)
     o = oracle.adjoint(x, v, L, 6, aU=0.0, a3=0.0, xbar_S=xs, vbar_S=vs)
-    assert rel_err(g["xbar0"], o["xbar0"]) <= 1e-3
-    assert rel_err(g["vbar0"], o["vbar0"]) <= 1e-3
-    assert np.allclose(g["thbar"], o["thbar"], rtol=1e-3, atol=1e-6 * np.abs(o["thbar"]).max())
+    assert rel_err(g["xbar0"], o["xbar0"]) <= 1e-4
+    assert rel_err(g["vbar0"], o["vbar0"]) <= 1e-4
+    assert np.allclose(g["thbar"], o["thbar"], rtol=1e-4, atol=1e-6 * np.abs(o["thbar"]).max())
 
 
 def test_checkpoint_interval_does_not_change_the_gradient():
@@ -162,15 +163,15 @@ def test_autograd_function():
     gx, gth = torch.autograd.grad(loss.sum(), (x0, theta))
     o = oracle.adjoint(x, v, L, 8)
     assert np.allclose(gth.numpy(), o["thbar"], rtol=1e-4, atol=0)
-    assert rel_err(from_dev(gx), o["xbar0"]) <= 1e-3
+    assert rel_err(from_dev(gx), o["xbar0"]) <= 1e-4
     # a seed on the final positions goes through a second adjoint run
     seed = f32(np.random.default_rng(2).normal(size=x.shape))
     loss, xS, vS = trajectory_loss(ctx, x0, v0, theta, nsteps=8, ckpt_every=4)
     obj = 2.0 * loss.sum() + (xS * to_dev(seed)).sum()
     gx, gth = torch.autograd.grad(obj, (x0, theta))
     o2 = oracle.adjoint(x, v, L, 8, aU=2.0, a3=2.0, xbar_S=seed)
-    assert np.allclose(gth.numpy(), o2["thbar"], rtol=1e-3, atol=0)
-    assert rel_err(from_dev(gx), o2["xbar0"]) <= 1e-3
+    assert np.allclose(gth.numpy(), o2["thbar"], rtol=1e-4, atol=0)
+    assert rel_err(from_dev(gx), o2["xbar0"]) <= 1e-4
 
 
 @pytest.mark.slow
@@ -328,8 +329,8 @@ def test_adjoint_with_synchronised_rebuilds_per_replica():
         o = oracle.adjoint(x, vs[r], L, S)
         assert abs(g["loss"][r] - o["loss"]) <= 1e-5 * abs(o["loss"]), r
         assert np.allclose(g["thbar"][r], o["thbar"], rtol=1e-4, atol=0), (r, g["thbar"][r], o["thbar"])
-        assert rel_err(g["xbar0"][r * n:(r + 1) * n, :3].astype(np.float64), o["xbar0"]) <= 1e-3, r
-        assert rel_err(g["vbar0"][r * n:(r + 1) * n, :3].astype(np.float64), o["vbar0"]) <= 1e-3, r
+        assert rel_err(g["xbar0"][r * n:(r + 1) * n, :3].astype(np.float64), o["xbar0"]) <= 1e-4, r
+        assert rel_err(g["vbar0"][r * n:(r + 1) * n, :3].astype(np.float64), o["vbar0"]) <= 1e-4, r
 
 
 @pytest.mark.parametrize("S,K", [(0, 1), (10, 4)])
@@ -346,9 +347,9 @@ def test_virial_term_adjoint_matches_oracle(S, K):
     o = oracle.adjoint(x, v, L, S, aU=0.5, a3=0.0, aW=1.0)
     assert abs(g["loss"] - o["loss"]) <= 1e-5 * abs(o["loss"]), (g["loss"], o["loss"])
     assert np.allclose(g["thbar"], o["thbar"], rtol=1e-4, atol=0), (g["thbar"], o["thbar"])
-    assert rel_err(g["xbar0"], o["xbar0"]) <= 1e-3
+    assert rel_err(g["xbar0"], o["xbar0"]) <= 1e-4
     if S > 0:
-        assert rel_err(g["vbar0"], o["vbar0"]) <= 1e-3
+        assert rel_err(g["vbar0"], o["vbar0"]) <= 1e-4
     ctx.close()
 
 
