@@ -288,8 +288,10 @@ __device__ void moments_tile(const Dev& d, const Phys& p, int par, int force_reb
                              const float4* __restrict__ tw = nullptr, float4* __restrict__ tmd = nullptr) {
   constexpr int APB = kBlock / LPA;
   // row slots per lane per batch: a batch spans at most 32 slots, one
-  // 128-byte line of the row
-  constexpr int kMU = LPA >= 32 ? 1 : (32 / LPA < 4 ? 32 / LPA : 4);
+  // 128-byte line of the row; with 8 lanes per atom 24 slots, which hold the
+  // ~16-entry rows of a 0.5 A skin (a wavefront issues every slot of a batch,
+  // used or not)
+  constexpr int kMU = LPA == 8 ? 3 : (LPA >= 32 ? 1 : (32 / LPA < 4 ? 32 / LPA : 4));
   const int g = threadIdx.x / LPA, lane = threadIdx.x % LPA;
   const int i = bid * APB + g;
   // Every load that does not depend on another is issued up front, before
