@@ -36,8 +36,17 @@ constexpr int kNQ = 12;            // thermo quantities per replica
 // rebuild's candidate and sorted lists, counts, cell prefixes and ids, and
 // with 16 or more lanes per atom (apb <= 16) the candidates' positions,
 // 16-byte aligned after the int part.
+// Per-atom stride (ints) of the rebuild's candidate and sorted lists in LDS.
+// With 4 or 8 lanes per atom (apb 64 or 32) it is padded to LPA mod 2 LPA,
+// so the groups of a wavefront, each reading LPA consecutive words, start on
+// distinct LDS banks (capacity 48 at 8 lanes: stride 56, not 48, whose groups
+// g and g + 4 share banks).
+__host__ __device__ constexpr int lds_row_stride(int apb, int cap) {
+  return apb >= 32 ? cap + ((kBlock / apb) - cap % (2 * (kBlock / apb)) + 2 * (kBlock / apb)) % (2 * (kBlock / apb))
+                   : cap;
+}
 __host__ __device__ constexpr size_t moments_lds_ints(int apb, int cap) {
-  return 2 * (size_t)apb * cap + apb + 56 * (size_t)apb;
+  return 2 * (size_t)apb * lds_row_stride(apb, cap) + apb + 56 * (size_t)apb;
 }
 __host__ __device__ constexpr size_t moments_lds_bytes(int apb, int cap) {
   return ((sizeof(int) * moments_lds_ints(apb, cap) + 15) & ~(size_t)15) +

@@ -331,10 +331,11 @@ __device__ void moments_tile(const Dev& d, const Phys& p, int par, int force_reb
   const uint4* lds_u = nullptr;
 
   if (rebuild) {                           // block-uniform
-    int* cand = lds + g * cap;
-    int* srt = lds + APB * cap + g * cap;
-    int* cnt = lds + 2 * APB * cap;
-    int* pre = lds + 2 * APB * cap + APB + g * 56;   // [28] prefix of cell counts
+    const int cs = lds_row_stride(APB, cap);         // per-atom stride of the two lists (>= cap)
+    int* cand = lds + g * cs;
+    int* srt = lds + APB * cs + g * cs;
+    int* cnt = lds + 2 * APB * cs;
+    int* pre = lds + 2 * APB * cs + APB + g * 56;    // [28] prefix of cell counts
     // candidate positions (16+ lanes per atom): the moments below read the
     // rebuilt row's neighbour positions from here instead of gathering them
     uint4* cand_u = reinterpret_cast<uint4*>(
@@ -389,7 +390,7 @@ __device__ void moments_tile(const Dev& d, const Phys& p, int par, int force_reb
     // their prefix counts interleave: msk[2w] = word w, msk[2w + 1] = bits
     // set in the words below w.
     constexpr bool kRankLookup = LPA < 16;
-    const bool rank_ok = kRankLookup && cap >= kRankInts;
+    const bool rank_ok = kRankLookup && cs >= kRankInts;
     int* msk = srt;
     int* cbase = srt + 16;
     if (real) {
