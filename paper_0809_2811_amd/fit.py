@@ -65,9 +65,12 @@ def gauss_newton(ctx, x0, v0, target, theta0: dict, fit=("lambda_", "epsilon"), 
         path.append((dict(theta), res.copy()))
         if log:
             log(it, theta, res)
+        J = g[:, idx]
+        if not (np.all(np.isfinite(res)) and np.all(np.isfinite(J))):
+            raise FloatingPointError(f"non-finite observables or gradients at iterate {it}, theta={theta}: "
+                                     f"residual {res}, Jacobian {J.tolist()}")
         if np.max(np.abs(res)) < tol:
             break
-        J = g[:, idx]
         step = np.linalg.lstsq(J, -res, rcond=None)[0]
         for k, d in zip(fit, step):
             theta[k] = theta[k] + float(d)
