@@ -31,10 +31,46 @@ static __device__ __forceinline__ unsigned quantize(float x, double inv_L) {
   return (unsigned)(unsigned long long)(fr * kTwo32);  // 2^32 wraps to 0
 }
 
+// One DPP exchange of a float: the value of the lane that `ctrl` names.
+template <int CTRL>
+static __device__ __forceinline__ float dpp(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xf, 0xf, false));
+}
+
+// Sum over each aligned group of W lanes, the same bits in every lane of the
+// group (each step adds a pair whose two orders round alike).  Groups of up
+// to 16 lanes reduce within their DPP row: neighbours (quad_perm 1,0,3,2),
+// pairs (quad_perm 2,3,0,1), quads (row_half_mirror: lane 7 - l of the
+// half-row, which holds the other quad's sum), half-rows (row_mirror); wider
+// groups add the row-crossing steps by lane shuffles.
 template <int W>
 static __device__ __forceinline__ float group_sum(float v) {
+  if (W >= 2) v += dpp<0xB1>(v);
+  if (W >= 4) v += dpp<0x4E>(v);
+  if (W >= 8) v += dpp<0x141>(v);
+  if (W >= 16) v += dpp<0x140>(v);
 #pragma unroll
-  for (int m = W / 2; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+  for (int m = 16; m < W; m <<= 1) v += __shfl_xor(v, m, 64);
+  return v;
+}
+
+// Inclusive prefix sum over each aligned group of W lanes (lane = index in
+// the group).  Groups of up to 16 lanes use DPP row shifts (a source outside
+// the group is masked by the lane test); wider groups lane shuffles.
+template <int W>
+static __device__ __forceinline__ int group_prefix(int v, int lane) {
+  if (W > 16) {
+#pragma unroll
+    for (int o = 1; o < W; o <<= 1) {
+      const int u = __shfl_up(v, o, W);
+      if (lane >= o) v += u;
+    }
+    return v;
+  }
+  if (W > 1) { const int u = __builtin_amdgcn_update_dpp(0, v, 0x111, 0xf, 0xf, false); if (lane >= 1) v += u; }
+  if (W > 2) { const int u = __builtin_amdgcn_update_dpp(0, v, 0x112, 0xf, 0xf, false); if (lane >= 2) v += u; }
+  if (W > 4) { const int u = __builtin_amdgcn_update_dpp(0, v, 0x114, 0xf, 0xf, false); if (lane >= 4) v += u; }
+  if (W > 8) { const int u = __builtin_amdgcn_update_dpp(0, v, 0x118, 0xf, 0xf, false); if (lane >= 8) v += u; }
   return v;
 }
 

@@ -375,12 +375,7 @@ __device__ void moments_tile(const Dev& d, const Phys& p, int par, int force_reb
     int own = 0;
 #pragma unroll
     for (int q = 0; q < CPL; ++q) own += mc[q];
-    int incl = own;                          // inclusive scan of the lanes' totals
-#pragma unroll
-    for (int off = 1; off < LPA; off <<= 1) {
-      const int up = __shfl_up(incl, off, LPA);
-      if (lane >= off) incl += up;
-    }
+    const int incl = group_prefix<LPA>(own, lane);   // inclusive scan of the lanes' totals
     // With fewer than 16 lanes per atom (and a row capacity that holds it),
     // the candidate -> cell lookup is a rank: bit p of a 256-bit mask marks
     // the first candidate of a non-empty cell, and the r-th non-empty cell's
@@ -401,13 +396,7 @@ __device__ void moments_tile(const Dev& d, const Phys& p, int par, int force_reb
         for (int q = 0; q < CPL; ++q) ne += mc[q] > 0;
         for (int w = lane; w < 8; w += LPA) msk[2 * w] = 0;
       }
-      int nrank = ne;                        // inclusive scan of non-empty cells per lane
-#pragma unroll
-      for (int off = 1; off < LPA; off <<= 1) {
-        const int up = __shfl_up(nrank, off, LPA);
-        if (lane >= off) nrank += up;
-      }
-      nrank -= ne;
+      int nrank = group_prefix<LPA>(ne, lane) - ne;    // non-empty cells of the lanes below
       if (lane == 0) pre[0] = 0;
 #pragma unroll
       for (int q = 0; q < CPL; ++q) {
@@ -433,13 +422,7 @@ __device__ void moments_tile(const Dev& d, const Phys& p, int par, int force_reb
         pc[j] = __builtin_popcount((unsigned)msk[2 * (lane * WPL + j)]);
         tot += pc[j];
       }
-      int inc = tot;
-#pragma unroll
-      for (int off = 1; off < LPA; off <<= 1) {
-        const int up = __shfl_up(inc, off, LPA);
-        if (lane >= off) inc += up;
-      }
-      int ex = inc - tot;
+      int ex = group_prefix<LPA>(tot, lane) - tot;
 #pragma unroll
       for (int j = 0; j < WPL; ++j) {
         msk[2 * (lane * WPL + j) + 1] = ex;
