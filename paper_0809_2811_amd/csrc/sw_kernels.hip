@@ -280,9 +280,9 @@ __device__ __forceinline__ void pad_count(int* cand, int* cnt, int run, int cap)
   for (int z = t; z < ((t + 3) & ~3); ++z) cand[z] = 0x7fffffff;
 }
 
-// lds: [APB][cap] candidates, [APB][cap] sorted, [APB] counts, [APB][56] cell
-// prefix and ids; with 16 or more lanes per atom also [APB][cap] candidate
-// positions (16-byte aligned)
+// lds: [APB][cs] candidates, [APB][cs] sorted (cs = lds_row_stride(APB, cap)
+// >= cap), [APB] counts, [APB][56] cell prefix and ids; with 16 or more lanes
+// per atom also [APB][cap] candidate positions (16-byte aligned)
 template <int LPA, bool ENERGY, bool TAN = false>
 __device__ void moments_tile(const Dev& d, const Phys& p, int par, int force_rebuild, int bid, int* lds,
                              const float4* __restrict__ tw = nullptr, float4* __restrict__ tmd = nullptr) {
@@ -351,7 +351,7 @@ __device__ void moments_tile(const Dev& d, const Phys& p, int par, int force_reb
     const uint4* gm = pick(d.gmem, par);
     const int ccap = d.cc;
     // Lane l owns the contiguous cells [l*CPL, (l+1)*CPL): their counts are
-    // one batch of loads, and a shuffle scan over the group gives every
+    // one batch of loads, and a prefix scan over the group gives every
     // cell's prefix.  Neighbouring atoms read the same cells, so these reads
     // and the candidate reads below mostly hit the CU's L1.
     constexpr int CPL = (27 + LPA - 1) / LPA;
