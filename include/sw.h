@@ -308,9 +308,15 @@ typedef struct sw_tuning {
                            sweeps on the first call of a configuration and
                            replay them on later calls; 0 = plain launches.
                            Results are the same bits either way.               */
-  int persistent;       /* 0: one launch per phase; 1: sw_step's steps run in one
-                           cooperative persistent launch at full occupancy;
-                           k > 1: the same with at most k blocks per CU         */
+  int persistent;       /* 0: one launch per phase; 1: sw_step's steps run in
+                           cooperative persistent launches (up to 4096 steps
+                           each) at full occupancy; k > 1: the same with at most
+                           k blocks per CU.  When the replicas can be dealt to
+                           the device's XCCs within 25 % of an even load, each
+                           XCC's blocks run its replicas and synchronise among
+                           themselves (SW_Q_PERSISTENT_GROUPS); else grid-wide
+                           barriers.  Setting it plans the groups (synchronous,
+                           allocates the launch's control words).              */
   int rebuild_every;    /* also rebuild rows at least this often (0 = only on
                            displacement)                                        */
   int timing;           /* > 0: every timing-th step of sw_step, bracket the
@@ -352,8 +358,11 @@ enum {
   SW_Q_TIMED_STEPS = 10,    /* number of sampled steps (reset by sw_set_tuning) */
   SW_Q_AUDIT_PAIRS = 12,    /* pairs closer than a*sigma seen by audits (sw_tuning.audit_every),
                                since creation                                    */
-  SW_Q_MISSED_PAIRS = 13    /* of those, pairs absent from the rows in use (0 unless the
+  SW_Q_MISSED_PAIRS = 13,   /* of those, pairs absent from the rows in use (0 unless the
                                rebuild criterion failed)                         */
+  SW_Q_PERSISTENT_GROUPS = 14 /* barrier groups of the last persistent sw_step call:
+                               1 = grid-wide barriers, k > 1 = replicas dealt to k XCCs,
+                               each group's barriers kept on its XCC; 0 = none yet */
 };
 int sw_query(sw_ctx* ctx, int what, long long* out);
 

@@ -240,6 +240,7 @@ hipError_t read_flags(sw_ctx* c, hipStream_t s, Flags* f) {
   f->overlap = h[F_OVERLAP];
   f->abort = h[F_ABORT];
   f->box = h[F_BOX];
+  f->pgroups = h[F_PGROUPS];
   return hipSuccess;
 }
 
@@ -461,9 +462,64 @@ void sw_destroy(sw_ctx* ctx) {
   if (ctx->adj_gexec) (void)hipGraphExecDestroy(ctx->adj_gexec);
   if (ctx->adj_graph) (void)hipGraphDestroy(ctx->adj_graph);
   for (void* p : ctx->adj_buf) (void)hipFree(p);
+  if (ctx->d_pctl) (void)hipFree(ctx->d_pctl);
+  if (ctx->d_gtab) (void)hipFree(ctx->d_gtab);
   free_list(ctx, ctx->grow_allocs);
   free_list(ctx, ctx->allocs);
   delete ctx;
+}
+
+// Plan of the persistent launch (k_persistent): its control words, the XCC
+// ids of the device, and the replica groups.  Replicas are dealt to the
+// XCCs largest first, each to the least loaded group; the group form is
+// kept only if no group holds more than 1.25 times the mean load (a
+// context of fewer replicas than XCCs, or one dominated by a replica, runs
+// the grid form).  The plan depends on the replica sizes alone.
+static int plan_persistent(sw_ctx* c) {
+  hipError_t e;
+  if (!c->d_pctl && (e = hipMalloc((void**)&c->d_pctl, sizeof(unsigned) * kCtlWords)) != hipSuccess)
+    return e == hipErrorOutOfMemory ? SW_ENOMEM : fail_hip(c, e);
+  if (c->xmask == 0 && (e = xcc_census(c->d_bar, &c->xmask, nullptr)) != hipSuccess) return fail_hip(c, e);
+  c->pg_ng = 1;
+  const int nx = __builtin_popcount(c->xmask);
+  if (nx < 2 || c->R < nx) return SW_OK;
+  std::vector<long long> load(nx, 0);
+  std::vector<int> order(c->R), grp(c->R);
+  for (int r = 0; r < c->R; ++r) order[r] = r;
+  auto waves = [&](int r) { return (long long)(c->reps[r].ipad_end - c->reps[r].ioff) / kTile; };
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return waves(x) > waves(y); });
+  long long total = 0;
+  for (int r : order) {
+    const int g = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+    grp[r] = g;
+    load[g] += waves(r);
+    total += waves(r);
+  }
+  if ((double)*std::max_element(load.begin(), load.end()) * nx > 1.25 * (double)total) return SW_OK;
+  std::vector<int> tab(2 * (nx + 1) + c->R);
+  int* woff = tab.data();
+  int* roff = woff + nx + 1;
+  int* reps = roff + nx + 1;
+  int nr = 0;
+  for (int g = 0; g < nx; ++g) {
+    woff[g + 1] = woff[g] + (int)load[g];
+    roff[g] = nr;
+    for (int r = 0; r < c->R; ++r)
+      if (grp[r] == g) reps[nr++] = r;
+  }
+  roff[nx] = nr;
+  if (c->gtab_ints < tab.size()) {
+    if (c->d_gtab) (void)hipFree(c->d_gtab);
+    c->d_gtab = nullptr;
+    c->gtab_ints = 0;
+    if ((e = hipMalloc((void**)&c->d_gtab, sizeof(int) * tab.size())) != hipSuccess)
+      return e == hipErrorOutOfMemory ? SW_ENOMEM : fail_hip(c, e);
+    c->gtab_ints = tab.size();
+  }
+  if ((e = hipMemcpy(c->d_gtab, tab.data(), sizeof(int) * tab.size(), hipMemcpyHostToDevice)) != hipSuccess)
+    return fail_hip(c, e);
+  c->pg_ng = nx;
+  return SW_OK;
 }
 
 int sw_set_tuning(sw_ctx* ctx, const sw_tuning* t) {
@@ -474,6 +530,10 @@ int sw_set_tuning(sw_ctx* ctx, const sw_tuning* t) {
   if (t->graph_steps < 0 || t->rebuild_every < 0 || t->timing < 0 || t->persistent < 0 || t->audit_every < 0)
     return SW_EINVAL;
   if (t->sync_rebuild != 0 && t->sync_rebuild != 1) return SW_EINVAL;
+  if (t->persistent > 0) {
+    const int st = plan_persistent(ctx);
+    if (st != SW_OK) return st;
+  }
   ctx->tune = *t;
   ctx->d.sync_rb = t->sync_rebuild;
   ctx->t_mom_ms = ctx->t_for_ms = 0.0;
@@ -610,11 +670,15 @@ int sw_step(sw_ctx* ctx, float* x, float* v, float* f, const sw_params* params, 
       if ((e = launch_forces(ctx->d, ph, lpa, MODE_START, 0, 0, nullptr, s)) != hipSuccess) return fail_hip(ctx, e);
       const bool persistent = ctx->tune.persistent > 0;
       if (persistent) {
-        PArgs pa{1, nsteps, nsteps, thermo ? thermo_every : 0, ctx->tune.rebuild_every, thermo, ctx->d_bar,
-                 ctx->d.flags + F_ABORT};
-        if ((e = launch_persistent(ctx->d, ph, lpa, pa, ctx->tune.persistent > 1 ? ctx->tune.persistent : 0, s,
-                                   &ctx->last_grid)) != hipSuccess)
-          return fail_hip(ctx, e);
+        // launches of at most kPersistSteps steps (one control word per step)
+        for (int t0 = 1; t0 <= nsteps; t0 += kPersistSteps) {
+          const int t1 = std::min(nsteps, t0 + kPersistSteps - 1);
+          PArgs pa{t0, t1, nsteps, thermo ? thermo_every : 0, ctx->tune.rebuild_every, thermo, ctx->d_pctl,
+                   ctx->d.flags + F_ABORT, ctx->d.sync_rb, ctx->pg_ng, ctx->xmask, ctx->d_gtab};
+          if ((e = launch_persistent(ctx->d, ph, lpa, pa, ctx->tune.persistent > 1 ? ctx->tune.persistent : 0, s,
+                                     &ctx->last_grid)) != hipSuccess)
+            return fail_hip(ctx, e);
+        }
       }
       int t_first = 1;
       if (!persistent && ctx->tune.graph_steps > 0 && nsteps > 1) {
@@ -657,6 +721,7 @@ int sw_step(sw_ctx* ctx, float* x, float* v, float* f, const sw_params* params, 
     }
     Flags fl;
     if ((e = read_flags(ctx, s, &fl)) != hipSuccess) return fail_hip(ctx, e);
+    if (ctx->tune.persistent > 0 && nsteps > 0) ctx->last_groups = fl.pgroups;
     if (fl.abort) return SW_ETIMEOUT;
     if (fl.nbr_over || fl.cell_over) {
       if ((st = grow(ctx, fl)) != SW_OK) return st;
@@ -692,6 +757,7 @@ int sw_query(sw_ctx* ctx, int what, long long* out) {
     case SW_Q_TIME_MOMENTS_NS: *out = (long long)(ctx->t_mom_ms * 1e6); return SW_OK;
     case SW_Q_TIME_FORCES_NS: *out = (long long)(ctx->t_for_ms * 1e6); return SW_OK;
     case SW_Q_TIMED_STEPS: *out = ctx->t_samples; return SW_OK;
+    case SW_Q_PERSISTENT_GROUPS: *out = ctx->last_groups; return SW_OK;
     case SW_Q_MIN_CELL_EDGE: {
       double m = 1e300;
       for (const RepInfo& R : ctx->reps)

@@ -35,7 +35,14 @@ struct sw_ctx {
   uint4* d_uq = nullptr;
   int *d_key = nullptr, *d_scnt = nullptr, *d_sstart = nullptr, *d_scur = nullptr, *d_order = nullptr;
   Tan t{};
-  unsigned* d_bar = nullptr;       // grid barrier counter of the persistent launch
+  unsigned* d_bar = nullptr;       // one word: XCC census of the persistent plan
+  // persistent launch (planned by sw_set_tuning, allocated on first use)
+  unsigned* d_pctl = nullptr;      // [kCtlWords] control words
+  int* d_gtab = nullptr;           // replica groups (PArgs::gtab)
+  size_t gtab_ints = 0;
+  unsigned xmask = 0;              // XCC ids of the device (0: not taken yet)
+  int pg_ng = 1;                   // groups of the plan (1: grid-wide barriers)
+  int last_groups = 0;             // groups the last persistent call ran with
   unsigned long long* d_audit = nullptr;   // [2] pairs within the cut-off audited, pairs missing from rows
   // captured block of steps (graph_steps > 0)
   hipStream_t cap_stream = nullptr;
@@ -150,7 +157,7 @@ int fail_hip(sw_ctx* c, hipError_t e);
 int lpa_for(const sw_ctx* c);
 int make_phys(const sw_ctx* c, const sw_params* P, double mass, double dt, Phys* o);
 hipError_t reset_flags(sw_ctx* c, hipStream_t s);
-struct Flags { int nbr_over, nbr_need, cell_over, overlap, abort, box; };
+struct Flags { int nbr_over, nbr_need, cell_over, overlap, abort, box, pgroups; };
 hipError_t read_flags(sw_ctx* c, hipStream_t s, Flags* f);
 int grow(sw_ctx* c, const Flags& f);
 hipError_t sort_in(sw_ctx* c, const float* x, const float* v, hipStream_t s);

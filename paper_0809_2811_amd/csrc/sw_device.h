@@ -12,6 +12,25 @@ static __device__ __forceinline__ int xcd_remap(int bid, int G) {
   return xcd * per + min(xcd, rem) + local;
 }
 
+// Hardware id of the XCC (accelerator die, with its own L2) the wavefront
+// runs on.
+static __device__ __forceinline__ unsigned xcc_id() {
+  unsigned v;
+  asm volatile("s_getreg_b32 %0, hwreg(HW_REG_XCC_ID)" : "=s"(v));
+  return v & (kMaxXcc - 1);
+}
+
+// The thread index through a volatile asm copy: the compiler cannot hoist
+// it, or anything computed from it, out of a loop.  A kernel that loops
+// over whole steps passes it to each tile it processes, so lane offsets are
+// recomputed per tile (a few instructions) instead of being held in
+// registers across every phase of the loop.
+static __device__ __forceinline__ unsigned opaque_tid() {
+  unsigned r;
+  asm volatile("v_mov_b32 %0, %1" : "=v"(r) : "v"((unsigned)__builtin_amdgcn_workitem_id_x()));
+  return r;
+}
+
 static __device__ __forceinline__ float3 disp(const uint4& a, const uint4& b, const float sc0, const float sc1,
                                        const float sc2) {
   return make_float3((float)(int)(b.x - a.x) * sc0, (float)(int)(b.y - a.y) * sc1,

@@ -60,7 +60,8 @@ constexpr double kBar = 1e5 * 1e-30 * 6.02214076e23 / 4184.0;   // kcal/mol/A^3 
 // Flag slots in Dev::flags.
 // Slots below F_REBUILDS are cleared at the start of every call; F_REBUILDS
 // counts row rebuilds over the context's lifetime.
-enum { F_NBR_OVER = 0, F_NBR_NEED = 1, F_CELL_OVER = 2, F_OVERLAP = 3, F_ABORT = 4, F_BOX = 5, F_REBUILDS = 7,
+enum { F_NBR_OVER = 0, F_NBR_NEED = 1, F_CELL_OVER = 2, F_OVERLAP = 3, F_ABORT = 4, F_BOX = 5, F_PGROUPS = 6,
+       F_REBUILDS = 7,
        F_NFLAGS = 8 };
 
 struct RepInfo {
@@ -173,7 +174,9 @@ constexpr int kNptRow = 11;
 constexpr int kFusedBlocks = 512;
 // Whether some replica of d is too large for those in-kernel sums at apb
 // atoms per force block.
-inline bool needs_reduce_launch(const Dev& d, int apb) { return d.max_rep_pad / apb > kFusedBlocks; }
+__host__ __device__ inline bool needs_reduce_launch(const Dev& d, int apb) {
+  return d.max_rep_pad / apb > kFusedBlocks;
+}
 
 // Optional start/stop events recorded at a launch's dispatch.
 struct KTimer {
@@ -211,16 +214,35 @@ hipError_t launch_npt_kick(const Dev& d, const Phys& p, const NptArgs& a, hipStr
 
 // Persistent cooperative launch of steps t0..t1 of an sw_step call.
 struct PArgs {
-  int t0, t1;          // first and last step of this launch
+  int t0, t1;          // first and last step of this launch (t1 - t0 < kPersistSteps)
   int nsteps;          // steps of the whole call (the last one ends on a full-step velocity)
   int thermo_every;    // 0 = no thermo rows
   int rebuild_every;   // forced row rebuild period (0 = none)
   double* thermo;      // caller table [nsteps / thermo_every][R][kNQ] or null
-  unsigned* bar;       // grid barrier counter (zeroed by the launcher)
+  unsigned* ctl;       // [kCtlWords] control words (zeroed by the launcher)
   int* abort;          // raised by a barrier wait that timed out (flags[F_ABORT])
+  int sync_rb;         // synchronised rebuilds (the kernel gets Dev::sync_rb = 0)
+  int ng;              // replica groups (1: grid-wide barriers)
+  unsigned xmask;      // XCC ids of the groups, one bit each (ng bits set)
+  const int* gtab;     // group table (layout below), ng > 1
 };
+// Control words of a persistent launch.  Words that many blocks add to or
+// poll sit 64 words (256 B) apart.
+constexpr int kMaxXcc = 16;                      // XCC ids are 4 bits
+constexpr int kPersistSteps = 4096;              // steps of one launch
+constexpr int kCtlGrid = 0;                      // arrivals at grid-wide barriers
+constexpr int kCtlGroup = 64;                    // + 64 x: arrivals at the barriers of XCC x
+constexpr int kCtlCensus = 64 * (1 + kMaxXcc);   // + x: blocks found on XCC x
+constexpr int kCtlStep = kCtlCensus + 64;        // + s: step t0 + s done by a group (low byte),
+                                                 //   rebuild flags raised (<< 8)
+constexpr int kCtlWords = kCtlStep + kPersistSteps;
+// Group table of the persistent launch (ints): offsets [ng + 1] of the
+// groups' padded atoms in 64-atom units, offsets [ng + 1] into the replica
+// list, then the replicas of group 0, 1, ... in ascending order.
 hipError_t launch_persistent(const Dev& d, const Phys& p, int lpa, const PArgs& a, int blocks_per_cu,
                              hipStream_t s, int* grid_out);
+// Bit mask of the XCC ids the device's compute units report.
+hipError_t xcc_census(unsigned* d_word, unsigned* mask_out, hipStream_t s);
 
 // Tangent (forward-mode) kernels for sw_grad / sw_adjoint.
 constexpr int kTQ = 8;  // per replica: E2, E3, W2 trace, W3 trace, w.F, w.F3, d(W trace) along w,

@@ -267,9 +267,9 @@ __global__ __launch_bounds__(kBlock) void k_bin(Dev d, int par, int check, float
 // P, E2 on energy steps) over the active neighbours r < a sigma.
 // Clears the cell counts and displacement flags of the other parity; every
 // block of a moments launch (or phase) takes a grid-stride share.
-__device__ __forceinline__ void clear_next(const Dev& d, int par, int b, int G) {
-  for (int r = b * kBlock + threadIdx.x; r < d.R; r += G * kBlock) d.dflag[(par ^ 1) * d.R + r] = 0;
-  for (int c = b * kBlock + threadIdx.x; c < d.ctot; c += G * kBlock) pick(d.gcnt, par ^ 1)[c] = 0;
+__device__ __forceinline__ void clear_next(const Dev& d, int par, int b, int G, unsigned tid) {
+  for (int r = b * kBlock + tid; r < d.R; r += G * kBlock) d.dflag[(par ^ 1) * d.R + r] = 0;
+  for (int c = b * kBlock + tid; c < d.ctot; c += G * kBlock) pick(d.gcnt, par ^ 1)[c] = 0;
 }
 
 // The group's candidate count, and INT_MAX in the slots past it up to a
@@ -284,7 +284,7 @@ __device__ __forceinline__ void pad_count(int* cand, int* cnt, int run, int cap)
 // >= cap), [APB] counts, [APB][56] cell prefix and ids; with 16 or more lanes
 // per atom also [APB][cap] candidate positions (16-byte aligned)
 template <int LPA, bool ENERGY, bool TAN = false>
-__device__ void moments_tile(const Dev& d, const Phys& p, int par, int force_rebuild, int bid, int* lds,
+__device__ void moments_tile(const Dev& d, const Phys& p, int par, int force_rebuild, int bid, unsigned tid, int* lds,
                              const float4* __restrict__ tw = nullptr, float4* __restrict__ tmd = nullptr) {
   constexpr int APB = kBlock / LPA;
   // row slots per lane per batch: a batch spans at most 32 slots, one
@@ -292,7 +292,7 @@ __device__ void moments_tile(const Dev& d, const Phys& p, int par, int force_reb
   // ~16-entry rows of a 0.5 A skin (a wavefront issues every slot of a batch,
   // used or not)
   constexpr int kMU = LPA == 8 ? 3 : (LPA >= 32 ? 1 : (32 / LPA < 4 ? 32 / LPA : 4));
-  const int g = threadIdx.x / LPA, lane = threadIdx.x % LPA;
+  const int g = tid / LPA, lane = tid % LPA;
   const int i = bid * APB + g;
   // Every load that does not depend on another is issued up front, before
   // the kernel's first store: own position, row length and the first batch
@@ -320,7 +320,7 @@ __device__ void moments_tile(const Dev& d, const Phys& p, int par, int force_reb
   bool flagged;
   if (d.sync_rb) {
     int f = 0;
-    for (int r = (int)(threadIdx.x & 63); r < d.R; r += 64) f |= d.dflag[par * d.R + r];
+    for (int r = (tid & 63); r < d.R; r += 64) f |= d.dflag[par * d.R + r];
     flagged = __ballot(f != 0) != 0ull;
   } else {
     flagged = d.dflag[par * d.R + rep] != 0;
@@ -440,7 +440,7 @@ __device__ void moments_tile(const Dev& d, const Phys& p, int par, int force_reb
       // Accepted entries are compacted with a ballot over the group.
       const int ncand = pre[27];
       const float rl2 = p.rl2;
-      const int wl = threadIdx.x & 63;
+      const int wl = tid & 63;
       const unsigned long long gmask = LPA == 64 ? ~0ull : ((1ull << LPA) - 1) << (wl & ~(LPA - 1));
       const unsigned long long below = (1ull << wl) - 1;
       int run = 0;                             // entries appended so far (lane 0 sees every pass)
@@ -486,7 +486,7 @@ __device__ void moments_tile(const Dev& d, const Phys& p, int par, int force_reb
       // entries are compacted with a group ballot (no LDS atomics).
       const int ncand = pre[27];
       const float rl2 = p.rl2;
-      const int wl = threadIdx.x & 63;
+      const int wl = tid & 63;
       const int gsh = wl & ~(LPA - 1);                           // the group's first lane
       // (this branch runs with fewer than 16 lanes per atom; the mask is
       // spelled so that every instantiation compiles)
@@ -574,7 +574,7 @@ __device__ void moments_tile(const Dev& d, const Phys& p, int par, int force_reb
     }
 #pragma unroll
     for (int u = 0; u < kMU; ++u) jn[u] = srt[min(lane + u * LPA, cap - 1)];
-    if (bid * APB == ioff && threadIdx.x == 0) {
+    if (bid * APB == ioff && tid == 0) {
       atomicAdd(&d.flags[F_REBUILDS], 1);
       d.lref[rep] = R.L[0];
     }
@@ -596,7 +596,7 @@ __device__ void moments_tile(const Dev& d, const Phys& p, int par, int force_reb
   // slot batch (a lane that leaves the loop early has no entry left).
   constexpr bool kAct = LPA <= 8;
   int* act_row = d.act + (size_t)i * cap;
-  const int wla = threadIdx.x & 63;
+  const int wla = tid & 63;
   const int ash = wla & ~(LPA - 1);                          // the group's first lane
   const unsigned amask = (1u << (kAct ? LPA : 1)) - 1u;      // its bits, shifted down
   const unsigned abelow = (1u << (wla - ash)) - 1u;          // lanes of the group below this one
@@ -692,8 +692,8 @@ __device__ void moments_tile(const Dev& d, const Phys& p, int par, int force_reb
 template <int LPA, bool ENERGY>
 __global__ __launch_bounds__(kBlock) void k_moments(Dev d, Phys p, int par, int force_rebuild) {
   extern __shared__ int lds[];
-  moments_tile<LPA, ENERGY>(d, p, par, force_rebuild, xcd_remap(blockIdx.x, gridDim.x), lds);
-  clear_next(d, par, blockIdx.x, gridDim.x);
+  moments_tile<LPA, ENERGY>(d, p, par, force_rebuild, xcd_remap(blockIdx.x, gridDim.x), threadIdx.x, lds);
+  clear_next(d, par, blockIdx.x, gridDim.x, threadIdx.x);
 }
 
 // Moments with energies and their tangent along w: the primal moments of
@@ -702,8 +702,9 @@ template <int LPA>
 __global__ __launch_bounds__(kBlock) void k_moments_tan(Dev d, Phys p, int par, int force_rebuild,
                                                         const float4* __restrict__ w, float4* __restrict__ mdot) {
   extern __shared__ int lds[];
-  moments_tile<LPA, true, true>(d, p, par, force_rebuild, xcd_remap(blockIdx.x, gridDim.x), lds, w, mdot);
-  clear_next(d, par, blockIdx.x, gridDim.x);
+  moments_tile<LPA, true, true>(d, p, par, force_rebuild, xcd_remap(blockIdx.x, gridDim.x), threadIdx.x, lds, w,
+                                mdot);
+  clear_next(d, par, blockIdx.x, gridDim.x, threadIdx.x);
 }
 
 // ----------------------------------------------------------------- audit
@@ -765,7 +766,7 @@ __global__ __launch_bounds__(kBlock) void k_audit(Dev d, Phys p, int par, unsign
 // Block partial sums of the thermo quantities (fixed order within the block).
 // The per-replica sums are taken by k_reduce_thermo after the kernel ends.
 template <int APB>
-__device__ void block_partials(const Dev& d, int bid, const double* q, bool writer, int g) {
+__device__ void block_partials(const Dev& d, int bid, const double* q, bool writer, int g, unsigned tid) {
   static_assert(APB >= kMinAPB, "partial sums are sized for at least kMinAPB atoms per block");
   __shared__ double red[APB * kNQ];
   if (writer) {
@@ -773,10 +774,10 @@ __device__ void block_partials(const Dev& d, int bid, const double* q, bool writ
     for (int k = 0; k < kNQ; ++k) red[g * kNQ + k] = q[k];
   }
   __syncthreads();
-  if (threadIdx.x < kNQ) {
+  if (tid < kNQ) {
     double acc = 0.0;
-    for (int a = 0; a < APB; ++a) acc += red[a * kNQ + threadIdx.x];
-    d.partial[(size_t)threadIdx.x * (d.npad / APB) + bid] = acc;
+    for (int a = 0; a < APB; ++a) acc += red[a * kNQ + tid];
+    d.partial[(size_t)tid * (d.npad / APB) + bid] = acc;
   }
   __syncthreads();   // red[] is reused by the block's next tile
 }
@@ -789,9 +790,9 @@ __device__ void block_partials(const Dev& d, int bid, const double* q, bool writ
 //   NVE_LAST v += dt/2 a (full step: KE)
 //   KICK     as NVE_LAST, the thermostat kernel follows
 template <int LPA, int MODE, bool VIR>
-__device__ void forces_tile(const Dev& d, const Phys& p, int par, int bid) {
+__device__ void forces_tile(const Dev& d, const Phys& p, int par, int bid, unsigned tid) {
   constexpr int APB = kBlock / LPA;
-  const int g = threadIdx.x / LPA, lane = threadIdx.x % LPA;
+  const int g = tid / LPA, lane = tid % LPA;
   const int i = bid * APB + g;
   // Software pipelined.  Everything that does not depend on a previous load
   // is issued first as one batch: own position, moments and row length, the
@@ -968,17 +969,17 @@ __device__ void forces_tile(const Dev& d, const Phys& p, int par, int bid) {
       d.v[i] = v;
     }
   }
-  if (kReduce) block_partials<APB>(d, bid, q, lane == 0, g);
+  if (kReduce) block_partials<APB>(d, bid, q, lane == 0, g, tid);
 }
 
 template <int LPA, int MODE, bool VIR>
 __global__ __launch_bounds__(kBlock) void k_forces(Dev d, Phys p, int par) {
-  forces_tile<LPA, MODE, VIR>(d, p, par, xcd_remap(blockIdx.x, gridDim.x));
+  forces_tile<LPA, MODE, VIR>(d, p, par, xcd_remap(blockIdx.x, gridDim.x), threadIdx.x);
 }
 
 // Per-replica sums of the block partials: one block per (replica, quantity),
 // threads stride over the replica's blocks, then a fixed tree.
-__device__ void reduce_task(const Dev& d, int apb, double* ring_row, int task) {
+__device__ void reduce_task(const Dev& d, int apb, double* ring_row, int task, unsigned tid) {
   __shared__ double tree[kBlock];
   const int nbt = d.npad / apb;
   {
@@ -987,14 +988,14 @@ __device__ void reduce_task(const Dev& d, int apb, double* ring_row, int task) {
     const int b0 = R.ioff / apb, b1 = R.ipad_end / apb;
     const double* src = d.partial + (size_t)k * nbt;
     double acc = 0.0;
-    for (int b = b0 + (int)threadIdx.x; b < b1; b += kBlock) acc += src[b];
-    tree[threadIdx.x] = acc;
+    for (int b = b0 + tid; b < b1; b += kBlock) acc += src[b];
+    tree[tid] = acc;
     __syncthreads();
     for (int st = kBlock / 2; st > 0; st >>= 1) {
-      if ((int)threadIdx.x < st) tree[threadIdx.x] += tree[threadIdx.x + st];
+      if (tid < st) tree[tid] += tree[tid + st];
       __syncthreads();
     }
-    if (threadIdx.x == 0) {
+    if (tid == 0) {
       d.thermo_cur[rep * kNQ + k] = tree[0];
       if (ring_row) ring_row[rep * kNQ + k] = tree[0];
     }
@@ -1003,7 +1004,7 @@ __device__ void reduce_task(const Dev& d, int apb, double* ring_row, int task) {
 }
 
 __global__ __launch_bounds__(kBlock) void k_reduce_thermo(Dev d, int apb, double* ring_row) {
-  for (int task = blockIdx.x; task < d.R * kNQ; task += gridDim.x) reduce_task(d, apb, ring_row, task);
+  for (int task = blockIdx.x; task < d.R * kNQ; task += gridDim.x) reduce_task(d, apb, ring_row, task, threadIdx.x);
 }
 
 // Sums over replica R of the force launch's block partials of quantities
@@ -1013,9 +1014,9 @@ __global__ __launch_bounds__(kBlock) void k_reduce_thermo(Dev d, int apb, double
 // bits in every lane, so all waves of the replica hold identical totals.
 // All 64 lanes of the wave must call it.
 __device__ __forceinline__ void replica_sums(const Dev& d, int apb, const RepInfo& R, const int (&ks)[4], int nk,
-                                             double* out) {
+                                             double* out, unsigned tid) {
   constexpr int kJ = kFusedBlocks / 64;
-  const int lane = threadIdx.x & 63;
+  const int lane = tid & 63;
   const int nbt = d.npad / apb, b0 = R.ioff / apb, b1 = R.ipad_end / apb;
   double x[4][kJ];
 #pragma unroll
@@ -1049,7 +1050,8 @@ __device__ __forceinline__ bool fused_sums(const RepInfo& R, int apb) {
 // 4096-atom box (latency bound) would lose ~3 us per launch to the extra pass.
 constexpr long long kAggAtoms = 65536;
 
-__device__ __forceinline__ void thermostat_atom(const Dev& d, const Phys& p, int par, int last, int i, int apb) {
+__device__ __forceinline__ void thermostat_atom(const Dev& d, const Phys& p, int par, int last, int i, int apb,
+                                                unsigned tid) {
   const bool agg = d.npad >= kAggAtoms;
   if (i < d.npad) {
     // the atom's records before the replica lookup (padded arrays), pinned
@@ -1065,7 +1067,7 @@ __device__ __forceinline__ void thermostat_atom(const Dev& d, const Phys& p, int
     if (fused_sums(R, apb)) {
       const int ks[4] = {2, 2, 2, 2};
       double th[kNQ];
-      replica_sums(d, apb, R, ks, 1, th);
+      replica_sums(d, apb, R, ks, 1, th, tid);
       ke = th[2];
     } else {
       ke = d.thermo_cur[rep * kNQ + 2];
@@ -1099,7 +1101,7 @@ __device__ __forceinline__ void thermostat_atom(const Dev& d, const Phys& p, int
 }
 
 __global__ __launch_bounds__(kBlock) void k_thermostat(Dev d, Phys p, int par, int last, int apb) {
-  thermostat_atom(d, p, par, last, blockIdx.x * kBlock + threadIdx.x, apb);
+  thermostat_atom(d, p, par, last, blockIdx.x * kBlock + threadIdx.x, apb, threadIdx.x);
 }
 
 // ----------------------------------------------------------------- isobaric
@@ -1212,10 +1214,10 @@ __global__ __launch_bounds__(kBlock) void k_npt_kick(Dev d, Phys p, NptArgs a) {
 #pragma unroll
     for (int k = 0; k < kNQ; ++k) th[k] = 0.0;
     const int kin[4] = {2, 3, 4, 5}, rec1[4] = {0, 1, 9, 10}, rec2[4] = {11, 11, 11, 11};
-    replica_sums(d, a.apb, R, kin, 4, th);
+    replica_sums(d, a.apb, R, kin, 4, th, threadIdx.x);
     if (rec_wave) {
-      replica_sums(d, a.apb, R, rec1, 4, th);
-      replica_sums(d, a.apb, R, rec2, 1, th);
+      replica_sums(d, a.apb, R, rec1, 4, th, threadIdx.x);
+      replica_sums(d, a.apb, R, rec2, 1, th, threadIdx.x);
     }
   } else {
 #pragma unroll
@@ -1297,32 +1299,40 @@ __global__ __launch_bounds__(kBlock) void k_npt_kick(Dev d, Phys p, NptArgs a) {
 }
 
 // ----------------------------------------------------------------- persistent
-// Grid-wide barrier of a cooperative launch.  Arrivals add to a counter that
-// only grows (barrier k completes at k * G arrivals).  Every wait is bounded:
-// a block that waits too long raises `abort`, and every later barrier
-// returns at once, so the grid always drains.
+// Waits of a persistent launch.  Every wait is bounded: a block that waits
+// too long raises `abort`, and every later wait returns at once, so the
+// grid always drains.  Counters are read at agent scope (past the L1).
+__device__ bool wait_count(const PArgs& a, unsigned* w, unsigned target, unsigned mask, unsigned* seen) {
+  unsigned spins = 0;
+  for (;;) {
+    const unsigned v = __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if ((v & mask) >= target) {
+      *seen = v;
+      return true;
+    }
+    if (__hip_atomic_load(a.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return false;
+    __builtin_amdgcn_s_sleep(2);
+    if (++spins > (1u << 22)) {
+      atomicOr(a.abort, 1);
+      return false;
+    }
+  }
+}
+
+// Grid-wide barrier: arrivals add to a counter that only grows (barrier k
+// completes at k * G arrivals).  Blocks on different XCCs exchange data
+// through it, and each XCC has its own L2, so every block writes back and
+// invalidates its XCC's L2 (agent-scope release and acquire).
 __device__ bool grid_sync(const PArgs& a, unsigned G, unsigned& k) {
   __shared__ int ok;
+  __builtin_amdgcn_s_waitcnt(0);           // this wave's stores have reached the L2
   __syncthreads();
   ++k;
   if (threadIdx.x == 0) {
     __threadfence();                       // release this block's writes
-    atomicAdd(a.bar, 1u);
-    const unsigned target = k * G;
-    unsigned spins = 0;
-    int good = 1;
-    while (__hip_atomic_load(a.bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-      if (__hip_atomic_load(a.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
-        good = 0;
-        break;
-      }
-      __builtin_amdgcn_s_sleep(2);
-      if (++spins > (1u << 22)) {
-        atomicOr(a.abort, 1);
-        good = 0;
-        break;
-      }
-    }
+    atomicAdd(a.ctl + kCtlGrid, 1u);
+    unsigned v;
+    const bool good = wait_count(a, a.ctl + kCtlGrid, k * G, ~0u, &v);
     __threadfence();                       // acquire the other blocks' writes
     ok = good;
   }
@@ -1330,54 +1340,224 @@ __device__ bool grid_sync(const PArgs& a, unsigned G, unsigned& k) {
   return ok != 0;
 }
 
+// Barrier of the blocks on one XCC (group form).  A replica's data is only
+// touched by its group, and a group's writes all land in its XCC's L2, so
+// nothing is written back; each block only drops its compute unit's L1
+// lines after the wait (an agent-scope acquire: on this chip a narrower
+// invalidate leaves them in place).  Barrier k of the group completes at
+// k * (blocks of the group) arrivals.
+__device__ bool group_sync(const PArgs& a, unsigned* ctr, unsigned target) {
+  __shared__ int ok;
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    atomicAdd(ctr, 1u);
+    unsigned v;
+    ok = wait_count(a, ctr, target, ~0u, &v);
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  }
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  return ok != 0;
+}
+
+// End of a step in the group form with synchronised rebuilds: the group's
+// last block to arrive ORs the rebuild flags its blocks raised for the
+// next step (parity npar) and adds one arrival, with the flag, to the
+// step's word; every block waits until all groups have added theirs, which
+// also completes its own group's barrier.  `any` becomes the OR over all
+// replicas, as the one-launch-per-phase form reads it.
+__device__ bool step_sync(const PArgs& a, const Dev& d, unsigned* ctr, unsigned target, unsigned* word,
+                          const int* reps, int rlo, int rhi, int npar, int& any) {
+  __shared__ int ok, fl;
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const unsigned old = atomicAdd(ctr, 1u);
+    if (old + 1u == target) {
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      int f = 0;
+      for (int j = rlo; j < rhi; ++j) f |= d.dflag[npar * d.R + reps[j]];
+      atomicAdd(word, 1u | (f != 0 ? 256u : 0u));
+    }
+    unsigned v = 0;
+    ok = wait_count(a, word, (unsigned)a.ng, 0xffu, &v);
+    fl = (v >> 8) != 0u;
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  }
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  any = fl;
+  return ok != 0;
+}
+
+// Maps the group-relative units (tiles of `unit` atoms) of the group's
+// replicas, taken in table order and visited in increasing order, to
+// global unit numbers.
+struct GroupCursor {
+  int j, acc, n, first;
+  __device__ __forceinline__ int at(const Dev& d, const int* reps, int unit, int k) {
+    while (k >= acc + n) {
+      acc += n;
+      const RepInfo& R = d.reps[reps[j++]];
+      first = R.ioff / unit;
+      n = (R.ipad_end - R.ioff) / unit;
+    }
+    return first + k - acc;
+  }
+};
+
+// Clears, for the group's replicas, what clear_next clears for all.
+__device__ __forceinline__ void clear_group(const Dev& d, int par, const int* reps, int rlo, int rhi, unsigned slot,
+                                            unsigned nb, unsigned tid) {
+  for (int j = rlo; j < rhi; ++j) {
+    const int r = reps[j];
+    const RepInfo& R = d.reps[r];
+    if (slot == 0 && tid == 0) d.dflag[(par ^ 1) * d.R + r] = 0;
+    for (int c = (int)(slot * kBlock + tid); c < R.ncell; c += (int)(nb * kBlock)) pick(d.gcnt, par ^ 1)[R.cell_off + c] = 0;
+  }
+}
+
 // All steps t0..t1 of sw_step in one launch: the same tile functions as the
-// one-kernel-per-phase path, separated by grid barriers.  Worker w (blocks
-// remapped per XCD) owns a contiguous range of tiles in every phase.
+// one-kernel-per-phase path, separated by barriers.
+//   Grid form (ng = 1): worker w (blocks remapped per XCC) owns a
+//   contiguous range of tiles in every phase; grid-wide barriers.
+//   Group form (ng > 1): the replicas are dealt to the XCCs (the group
+//   table); the blocks found on an XCC share its replicas' tiles and
+//   synchronise among themselves, so no barrier writes back an L2.  With
+//   synchronised rebuilds the groups also meet once per step, through one
+//   word per step.  A census at the start checks that blocks run on exactly
+//   the XCCs the table names; otherwise the launch takes the grid form.
+// Both forms give the same bits as one launch per phase: every tile's
+// arithmetic is independent of which block runs it.
+// Four wavefronts per SIMD (128 VGPRs): the loop over steps holds state
+// that one launch per phase does not, and without the bound the kernel
+// takes 133 VGPRs and three wavefronts (no spills at 8 or more lanes per
+// atom; five wavefronts would spill 52 VGPRs).
 template <int LPA>
-__global__ __launch_bounds__(kBlock) void k_persistent(Dev d, Phys p, PArgs a) {
+__global__ __launch_bounds__(kBlock, 4) void k_persistent(Dev d, Phys p, PArgs a) {
   constexpr int APB = kBlock / LPA;
   extern __shared__ int lds[];
+  __shared__ unsigned sh_census[3];
   const unsigned G = gridDim.x;
-  const int w = xcd_remap(blockIdx.x, (int)G);
-  const int ntile = d.npad / APB;
-  const int tlo = (int)((long long)ntile * w / G), thi = (int)((long long)ntile * (w + 1) / G);
-  const int n256 = (d.npad + kBlock - 1) / kBlock;
-  const int alo = (int)((long long)n256 * w / G), ahi = (int)((long long)n256 * (w + 1) / G);
+  unsigned kgrid = 0;
+  const unsigned xc = xcc_id();
+  bool grouped = false;
+  unsigned slot = (unsigned)xcd_remap(blockIdx.x, (int)G), nb = G;
+  if (a.ng > 1) {
+    if (threadIdx.x == 0) sh_census[0] = atomicAdd(a.ctl + kCtlCensus + xc, 1u);
+    if (!grid_sync(a, G, kgrid)) return;
+    if (threadIdx.x == 0) {
+      unsigned good = (a.xmask >> xc) & 1u;
+      for (int x = 0; x < kMaxXcc; ++x) {
+        const unsigned c = __hip_atomic_load(a.ctl + kCtlCensus + x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if ((c != 0u) != (((a.xmask >> x) & 1u) != 0u)) good = 0u;
+        if (x == (int)xc) sh_census[1] = c;
+      }
+      sh_census[2] = good;
+    }
+    __syncthreads();
+    if (sh_census[2] != 0u) {
+      grouped = true;
+      slot = sh_census[0];
+      nb = sh_census[1];
+    }
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) atomicMax(&d.flags[F_PGROUPS], grouped ? a.ng : 1);
+  // the block's share of tiles and 64-atom waves (group form: numbered
+  // within the group), and the group's replicas
+  const int* reps = nullptr;
+  long long nt = d.npad / APB, nw = d.npad / kTile;
+  int rlo = 0, rhi = 0;
+  if (grouped) {
+    const int ng = a.ng;
+    const int g = __builtin_popcount(a.xmask & ((1u << xc) - 1u));
+    const int* woff = a.gtab;
+    const int* roff = woff + (ng + 1);
+    reps = roff + (ng + 1);
+    nw = woff[g + 1] - woff[g];
+    nt = nw * (kTile / APB);
+    rlo = roff[g];
+    rhi = roff[g + 1];
+  }
+  const int tlo = (int)(nt * slot / nb), thi = (int)(nt * (slot + 1) / nb);
+  const int wlo = (int)(nw * slot / nb), whi = (int)(nw * (slot + 1) / nb);
+  unsigned* gctr = a.ctl + kCtlGroup + 64 * xc;
+  unsigned kgrp = 0;
+  // Synchronised rebuilds (a.sync_rb; d.sync_rb is 0 here, so a tile reads
+  // only its own replica's flag): `any` is the OR of every replica's flag
+  // for the coming step, taken by each block from the flags themselves
+  // where they are visible to it (the first step, whose flags were written
+  // before the launch, and every step of the grid form, after its
+  // grid-wide barrier) and from the step words in the group form.
+  int any = 0;
+  auto all_flags = [&](int par) {
+    int f = 0;
+    for (int r = 0; r < d.R; ++r) f |= d.dflag[par * d.R + r];
+    return f != 0 ? 1 : 0;
+  };
   const bool thermostat = p.thermostat != 0;
-  unsigned k = 0;
+  auto sync = [&]() -> bool { return grouped ? group_sync(a, gctr, ++kgrp * nb) : grid_sync(a, G, kgrid); };
+  auto sync_end = [&](int t) -> bool {
+    if (!(grouped && a.sync_rb)) return sync();
+    return step_sync(a, d, gctr, ++kgrp * nb, a.ctl + kCtlStep + (t - a.t0), reps, rlo, rhi, (t + 1) & 1, any);
+  };
   for (int t = a.t0; t <= a.t1; ++t) {
     const int par = t & 1;
+    if (a.sync_rb && (t == a.t0 || !grouped)) any = all_flags(par);
     const bool rec = a.thermo_every > 0 && t % a.thermo_every == 0;
     const bool last = t == a.nsteps;
-    const int frb = a.rebuild_every > 0 && t % a.rebuild_every == 0;
+    const int frb = (a.rebuild_every > 0 && t % a.rebuild_every == 0) || any;
     double* row = rec && a.thermo ? a.thermo + (size_t)(t / a.thermo_every - 1) * d.R * kNQ : nullptr;
-    for (int b = tlo; b < thi; ++b) {
-      if (rec) moments_tile<LPA, true>(d, p, par, frb, b, lds);
-      else moments_tile<LPA, false>(d, p, par, frb, b, lds);
+    GroupCursor cm{rlo, 0, 0, 0};
+    for (int k = tlo; k < thi; ++k) {
+      const int b = grouped ? cm.at(d, reps, APB, k) : k;
+      if (rec) moments_tile<LPA, true>(d, p, par, frb, b, opaque_tid(), lds);
+      else moments_tile<LPA, false>(d, p, par, frb, b, opaque_tid(), lds);
     }
-    clear_next(d, par, blockIdx.x, (int)G);
-    if (!grid_sync(a, G, k)) return;
-    for (int b = tlo; b < thi; ++b) {
+    if (grouped) clear_group(d, par, reps, rlo, rhi, slot, nb, opaque_tid());
+    else clear_next(d, par, blockIdx.x, (int)G, opaque_tid());
+    if (!sync()) return;
+    GroupCursor cf{rlo, 0, 0, 0};
+    for (int k = tlo; k < thi; ++k) {
+      const int b = grouped ? cf.at(d, reps, APB, k) : k;
       if (thermostat) {
-        if (rec) forces_tile<LPA, MODE_KICK, true>(d, p, par, b);
-        else forces_tile<LPA, MODE_KICK, false>(d, p, par, b);
+        if (rec) forces_tile<LPA, MODE_KICK, true>(d, p, par, b, opaque_tid());
+        else forces_tile<LPA, MODE_KICK, false>(d, p, par, b, opaque_tid());
       } else if (last) {
-        if (rec) forces_tile<LPA, MODE_NVE_LAST, true>(d, p, par, b);
-        else forces_tile<LPA, MODE_NVE_LAST, false>(d, p, par, b);
+        if (rec) forces_tile<LPA, MODE_NVE_LAST, true>(d, p, par, b, opaque_tid());
+        else forces_tile<LPA, MODE_NVE_LAST, false>(d, p, par, b, opaque_tid());
       } else {
-        if (rec) forces_tile<LPA, MODE_NVE, true>(d, p, par, b);
-        else forces_tile<LPA, MODE_NVE, false>(d, p, par, b);
+        if (rec) forces_tile<LPA, MODE_NVE, true>(d, p, par, b, opaque_tid());
+        else forces_tile<LPA, MODE_NVE, false>(d, p, par, b, opaque_tid());
       }
     }
-    if (!grid_sync(a, G, k)) return;
-    if (rec || thermostat) {
-      for (int task = w; task < d.R * kNQ; task += (int)G) reduce_task(d, APB, row, task);
-      if (!grid_sync(a, G, k)) return;
+    // per-replica sums of the force phase's partials: for thermo rows, and
+    // for a thermostat on replicas too large for the thermostat phase to
+    // sum itself (as the per-phase launches)
+    if (rec || (thermostat && needs_reduce_launch(d, APB))) {
+      if (!sync()) return;
+      if (grouped) {
+        const int ntask = (rhi - rlo) * kNQ;
+        for (int j = (int)slot; j < ntask; j += (int)nb)
+          reduce_task(d, APB, row, reps[rlo + j / kNQ] * kNQ + j % kNQ, opaque_tid());
+      } else {
+        for (int task = (int)slot; task < d.R * kNQ; task += (int)G) reduce_task(d, APB, row, task, opaque_tid());
+      }
     }
-    if (thermostat) {
-      for (int b = alo; b < ahi; ++b) thermostat_atom(d, p, par, last, b * kBlock + threadIdx.x, APB);
-      if (!grid_sync(a, G, k)) return;
+    if (!thermostat) {
+      if (!sync_end(t)) return;
+      continue;
     }
+    if (!sync()) return;
+    // the block's waves take its 64-atom units in turn
+    GroupCursor ct{rlo, 0, 0, 0};
+    for (int k = wlo + (int)(threadIdx.x >> 6); k < whi; k += kBlock / 64) {
+      const int u = grouped ? ct.at(d, reps, kTile, k) : k;
+      const unsigned tid = opaque_tid();
+      thermostat_atom(d, p, par, last, u * kTile + (int)(tid & 63), APB, tid);
+    }
+    if (!sync_end(t)) return;
   }
 }
 
@@ -1489,6 +1669,10 @@ hipError_t forces_lpa(const Dev& d, const Phys& p, int mode, int vir, int par, d
   return hipErrorInvalidValue;
 }
 
+__global__ void k_xcc_census(unsigned* word) {
+  if (threadIdx.x == 0) atomicOr(word, 1u << xcc_id());
+}
+
 template <int LPA>
 hipError_t persistent_lpa(const Dev& d, const Phys& p, const PArgs& a, int blocks_per_cu, hipStream_t s,
                           int* grid_out) {
@@ -1505,8 +1689,10 @@ hipError_t persistent_lpa(const Dev& d, const Phys& p, const PArgs& a, int block
   const int grid = max(1, min(per_cu * ncu, ntile));
   *grid_out = grid;
   Dev dd = d;
+  dd.sync_rb = 0;           // the kernel takes synchronised rebuilds from PArgs
   Phys pp = p;
   PArgs aa = a;
+  aa.sync_rb = d.sync_rb;
   void* args[] = {&dd, &pp, &aa};
   return hipLaunchCooperativeKernel((const void*)k_persistent<LPA>, dim3(grid), dim3(kBlock), args,
                                     (unsigned)lds, s);
@@ -1514,10 +1700,26 @@ hipError_t persistent_lpa(const Dev& d, const Phys& p, const PArgs& a, int block
 
 }  // namespace
 
+hipError_t xcc_census(unsigned* d_word, unsigned* mask_out, hipStream_t s) {
+  hipError_t e;
+  int dev = 0, ncu = 0;
+  if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
+  if ((e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
+  if ((e = launch_fill_i32((int*)d_word, 0, 1, s)) != hipSuccess) return e;
+  // a few blocks per compute unit: the dispatcher deals them to every XCC
+  hipLaunchKernelGGL(k_xcc_census, dim3(4 * max(ncu, 1)), dim3(64), 0, s, d_word);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  unsigned h = 0;
+  if ((e = hipMemcpyAsync(&h, d_word, sizeof h, hipMemcpyDeviceToHost, s)) != hipSuccess) return e;
+  if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
+  *mask_out = h;
+  return hipSuccess;
+}
+
 hipError_t launch_persistent(const Dev& d, const Phys& p, int lpa, const PArgs& a, int blocks_per_cu,
                              hipStream_t s, int* grid_out) {
   hipError_t e;
-  if ((e = launch_fill_i32((int*)a.bar, 0, 1, s)) != hipSuccess) return e;
+  if ((e = launch_fill_i32((int*)a.ctl, 0, kCtlWords, s)) != hipSuccess) return e;
   switch (lpa) {
     case 4: return persistent_lpa<4>(d, p, a, blocks_per_cu, s, grid_out);
     case 8: return persistent_lpa<8>(d, p, a, blocks_per_cu, s, grid_out);

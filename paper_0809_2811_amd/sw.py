@@ -40,7 +40,7 @@ SW_THERMO_WIDTH = 12
 SW_Q_NATOMS, SW_Q_NREPLICAS, SW_Q_NBR_CAPACITY, SW_Q_REBUILDS = 0, 1, 2, 3
 SW_Q_CELL_CAPACITY, SW_Q_DEVICE_BYTES, SW_Q_STEPS = 5, 6, 7
 SW_Q_TIME_MOMENTS_NS, SW_Q_TIME_FORCES_NS, SW_Q_TIMED_STEPS = 8, 9, 10
-SW_Q_AUDIT_PAIRS, SW_Q_MISSED_PAIRS = 12, 13
+SW_Q_AUDIT_PAIRS, SW_Q_MISSED_PAIRS, SW_Q_PERSISTENT_GROUPS = 12, 13, 14
 
 # symbols declared in include/sw.h
 EXPORTS = ("sw_params_mw", "sw_create", "sw_destroy", "sw_build_neighbors", "sw_get_neighbors",

@@ -319,6 +319,41 @@ def test_persistent_launch_equals_launch_per_phase(thermostat):
         xd, vd = to_dev(np.concatenate(xs)), to_dev(np.concatenate(vs))
         f, th = ctx.step(xd, vd, 40, **kw)
         out.append((from_dev(xd), from_dev(vd), from_dev(f), th.cpu().numpy(), ctx.query(sw.SW_Q_REBUILDS)))
+        if persistent:
+            assert ctx.query(sw.SW_Q_PERSISTENT_GROUPS) == 1      # three replicas: grid-wide barriers
+    for k in range(5):
+        assert np.array_equal(out[0][k], out[1][k]), k
+
+
+@pytest.mark.parametrize("thermostat,sync", [("nve", 0), ("nve", 1), ("berendsen", 0), ("berendsen", 1)])
+def test_persistent_groups_per_xcc_equal_launch_per_phase(thermostat, sync):
+    """Sixteen replicas of one size: the persistent launch deals them to the
+    device's XCCs and keeps each group's barriers on its XCC (with
+    synchronised rebuilds the groups also meet once per step).  Results are
+    bitwise those of one launch per phase, over more steps than one
+    persistent launch holds (two launches)."""
+    from paper_0809_2811_amd import sw
+    xs, vs, boxes, T0 = [], [], [], []
+    for k in range(16):
+        rho, T = 0.92 + 0.01 * k, 220.0 + 6.0 * k
+        d = synth.lattice_at_density(4, rho, sigma=0.2, temperature=T, seed=300 + k)
+        xs.append(f32(d["x"])); vs.append(f32(d["v"])); boxes.append(d["box"]); T0.append(T)
+    offsets = np.cumsum([0] + [len(x) for x in xs])
+    kw = dict(thermo_every=7)
+    if thermostat == "berendsen":
+        kw.update(thermostat=sw.SW_BERENDSEN, T0=T0, tau_fs=100.0)
+    nsteps = 4096 + 45
+    out = []
+    for persistent in (0, 1):
+        ctx = make_ctx(np.concatenate(xs), None, offsets=offsets, boxes=boxes, persistent=persistent,
+                       sync_rebuild=sync)
+        xd, vd = to_dev(np.concatenate(xs)), to_dev(np.concatenate(vs))
+        print(f"persistent={persistent} thermostat={thermostat} sync={sync}", flush=True)
+        f, th = ctx.step(xd, vd, nsteps, **kw)
+        out.append((from_dev(xd), from_dev(vd), from_dev(f), th.cpu().numpy(), ctx.query(sw.SW_Q_REBUILDS)))
+        if persistent:
+            assert ctx.query(sw.SW_Q_PERSISTENT_GROUPS) > 1
+    assert out[0][4] > 16 * 50                                     # rows were rebuilt many times
     for k in range(5):
         assert np.array_equal(out[0][k], out[1][k]), k
 
