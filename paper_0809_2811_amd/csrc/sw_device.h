@@ -20,6 +20,14 @@ static __device__ __forceinline__ unsigned xcc_id() {
   return v & (kMaxXcc - 1);
 }
 
+// The compute unit the wavefront runs on, within its XCC: CU_ID, SH_ID
+// and SE_ID of the HW_ID register (bits 8..15), one value per CU.
+static __device__ __forceinline__ unsigned cu_key() {
+  unsigned v;
+  asm volatile("s_getreg_b32 %0, hwreg(HW_REG_HW_ID)" : "=s"(v));
+  return (v >> 8) & 0xffu;
+}
+
 // The thread index through a volatile asm copy: the compiler cannot hoist
 // it, or anything computed from it, out of a loop.  A kernel that loops
 // over whole steps passes it to each tile it processes, so lane offsets are

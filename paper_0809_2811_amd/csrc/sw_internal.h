@@ -235,7 +235,11 @@ constexpr int kCtlGroup = 64;                    // + 64 x: arrivals at the barr
 constexpr int kCtlCensus = 64 * (1 + kMaxXcc);   // + x: blocks found on XCC x
 constexpr int kCtlStep = kCtlCensus + 64;        // + s: step t0 + s done by a group (low byte),
                                                  //   rebuild flags raised (<< 8)
-constexpr int kCtlWords = kCtlStep + kPersistSteps;
+constexpr int kCtlEpoch = kCtlStep + kPersistSteps;   // + 256 x + cu: last barrier whose L1
+                                                      //   invalidate a block of that CU took on
+constexpr int kCtlDone = kCtlEpoch + kMaxXcc * 256;   // + 256 x + cu: last barrier whose
+                                                      //   invalidate is done
+constexpr int kCtlWords = kCtlDone + kMaxXcc * 256;
 // Group table of the persistent launch (ints): offsets [ng + 1] of the
 // groups' padded atoms in 64-atom units, offsets [ng + 1] into the replica
 // list, then the replicas of group 0, 1, ... in ascending order.

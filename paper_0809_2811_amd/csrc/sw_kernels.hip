@@ -1340,21 +1340,36 @@ __device__ bool grid_sync(const PArgs& a, unsigned G, unsigned& k) {
   return ok != 0;
 }
 
+// After group barrier k: drops the compute unit's L1 lines once.  The
+// first block of the CU past the barrier invalidates (an agent-scope
+// acquire: on this chip a narrower invalidate leaves the L1 lines in
+// place) and marks k done; the CU's other blocks wait for the mark.  An
+// invalidate costs each XCC's L2 tens of nanoseconds in turn, so one per
+// CU rather than per block shortens every barrier.
+__device__ bool drop_l1(const PArgs& a, unsigned* cu, unsigned k) {
+  if (atomicMax(cu + kCtlEpoch, k) < k) {
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    __builtin_amdgcn_s_waitcnt(0);
+    atomicMax(cu + kCtlDone, k);
+    return true;
+  }
+  unsigned v;
+  return wait_count(a, cu + kCtlDone, k, ~0u, &v);
+}
+
 // Barrier of the blocks on one XCC (group form).  A replica's data is only
 // touched by its group, and a group's writes all land in its XCC's L2, so
-// nothing is written back; each block only drops its compute unit's L1
-// lines after the wait (an agent-scope acquire: on this chip a narrower
-// invalidate leaves them in place).  Barrier k of the group completes at
-// k * (blocks of the group) arrivals.
-__device__ bool group_sync(const PArgs& a, unsigned* ctr, unsigned target) {
+// nothing is written back; only the L1 lines go (drop_l1).  Barrier k of
+// the group completes at k * nb arrivals (nb blocks in the group); `cu` is
+// a.ctl offset by the block's CU (256 x + cu_key()).
+__device__ bool group_sync(const PArgs& a, unsigned* ctr, unsigned k, unsigned nb, unsigned* cu) {
   __shared__ int ok;
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   if (threadIdx.x == 0) {
     atomicAdd(ctr, 1u);
     unsigned v;
-    ok = wait_count(a, ctr, target, ~0u, &v);
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    ok = wait_count(a, ctr, k * nb, ~0u, &v) && drop_l1(a, cu, k);
   }
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
@@ -1367,23 +1382,22 @@ __device__ bool group_sync(const PArgs& a, unsigned* ctr, unsigned target) {
 // step's word; every block waits until all groups have added theirs, which
 // also completes its own group's barrier.  `any` becomes the OR over all
 // replicas, as the one-launch-per-phase form reads it.
-__device__ bool step_sync(const PArgs& a, const Dev& d, unsigned* ctr, unsigned target, unsigned* word,
-                          const int* reps, int rlo, int rhi, int npar, int& any) {
+__device__ bool step_sync(const PArgs& a, const Dev& d, unsigned* ctr, unsigned k, unsigned nb, unsigned* cu,
+                          unsigned* word, const int* reps, int rlo, int rhi, int npar, int& any) {
   __shared__ int ok, fl;
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   if (threadIdx.x == 0) {
     const unsigned old = atomicAdd(ctr, 1u);
-    if (old + 1u == target) {
+    if (old + 1u == k * nb) {
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
       int f = 0;
       for (int j = rlo; j < rhi; ++j) f |= d.dflag[npar * d.R + reps[j]];
       atomicAdd(word, 1u | (f != 0 ? 256u : 0u));
     }
     unsigned v = 0;
-    ok = wait_count(a, word, (unsigned)a.ng, 0xffu, &v);
+    ok = wait_count(a, word, (unsigned)a.ng, 0xffu, &v) && drop_l1(a, cu, k);
     fl = (v >> 8) != 0u;
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   }
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
@@ -1483,6 +1497,7 @@ __global__ __launch_bounds__(kBlock, 4) void k_persistent(Dev d, Phys p, PArgs a
   const int tlo = (int)(nt * slot / nb), thi = (int)(nt * (slot + 1) / nb);
   const int wlo = (int)(nw * slot / nb), whi = (int)(nw * (slot + 1) / nb);
   unsigned* gctr = a.ctl + kCtlGroup + 64 * xc;
+  unsigned* cu = a.ctl + 256 * xc + cu_key();
   unsigned kgrp = 0;
   // Synchronised rebuilds (a.sync_rb; d.sync_rb is 0 here, so a tile reads
   // only its own replica's flag): `any` is the OR of every replica's flag
@@ -1497,10 +1512,10 @@ __global__ __launch_bounds__(kBlock, 4) void k_persistent(Dev d, Phys p, PArgs a
     return f != 0 ? 1 : 0;
   };
   const bool thermostat = p.thermostat != 0;
-  auto sync = [&]() -> bool { return grouped ? group_sync(a, gctr, ++kgrp * nb) : grid_sync(a, G, kgrid); };
+  auto sync = [&]() -> bool { return grouped ? group_sync(a, gctr, ++kgrp, nb, cu) : grid_sync(a, G, kgrid); };
   auto sync_end = [&](int t) -> bool {
     if (!(grouped && a.sync_rb)) return sync();
-    return step_sync(a, d, gctr, ++kgrp * nb, a.ctl + kCtlStep + (t - a.t0), reps, rlo, rhi, (t + 1) & 1, any);
+    return step_sync(a, d, gctr, ++kgrp, nb, cu, a.ctl + kCtlStep + (t - a.t0), reps, rlo, rhi, (t + 1) & 1, any);
   };
   for (int t = a.t0; t <= a.t1; ++t) {
     const int par = t & 1;
