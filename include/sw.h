@@ -306,7 +306,10 @@ typedef struct sw_tuning {
                            of 2 and of the record interval); any value > 0 also
                            makes sw_adjoint capture its forward and reverse
                            sweeps on the first call of a configuration and
-                           replay them on later calls; 0 = plain launches.
+                           replay them on later calls; with `persistent`,
+                           sw_step captures a call's persistent launches and
+                           replays them on later calls of the same step count
+                           and settings; 0 = plain launches.
                            Results are the same bits either way.               */
   int persistent;       /* 0: one launch per phase; 1: sw_step's steps run in
                            cooperative persistent launches (up to 4096 steps

@@ -386,6 +386,56 @@ hipError_t ensure_graph(sw_ctx* c, const Phys& ph, int lpa, int K, int thermosta
   return hipSuccess;
 }
 
+// The persistent launches of one sw_step call (steps 1..nsteps), in
+// launches of at most kPersistSteps steps; thermo rows go to `rows`.
+hipError_t enqueue_persistent(sw_ctx* c, const Phys& ph, int lpa, int nsteps, int every, double* rows,
+                              hipStream_t s) {
+  hipError_t e = hipSuccess;
+  for (int t0 = 1; t0 <= nsteps && e == hipSuccess; t0 += kPersistSteps) {
+    const int t1 = std::min(nsteps, t0 + kPersistSteps - 1);
+    PArgs pa{t0, t1, nsteps, rows ? every : 0, c->tune.rebuild_every, rows, c->d_pctl, c->d.flags + F_ABORT,
+             c->d.sync_rb, c->pg_ng, c->xmask, c->d_gtab};
+    e = launch_persistent(c->d, ph, lpa, pa, c->tune.persistent > 1 ? c->tune.persistent : 0, s, &c->last_grid);
+  }
+  return e;
+}
+
+// A captured copy of a call's persistent launches (the control-word fills
+// and cooperative launches of enqueue_persistent), keyed by everything
+// they read; thermo rows land in pring.
+hipError_t ensure_pgraph(sw_ctx* c, const Phys& ph, int lpa, int nsteps, int every) {
+  std::vector<unsigned char> key(sizeof(Phys) + 12 * sizeof(int));
+  const unsigned long long tab = (unsigned long long)(size_t)c->d_gtab;
+  int meta[12] = {nsteps, lpa, every, c->tune.rebuild_every, c->alloc_gen, c->d.sync_rb, c->pg_ng, (int)c->xmask,
+                  c->tune.persistent, (int)(tab & 0xffffffffu), (int)(tab >> 32), c->R};
+  std::memcpy(key.data(), &ph, sizeof(Phys));
+  std::memcpy(key.data() + sizeof(Phys), meta, sizeof meta);
+  if (c->pgexec && key == c->pgkey) return hipSuccess;
+  hipError_t e;
+  if (c->pgexec) { (void)hipGraphExecDestroy(c->pgexec); c->pgexec = nullptr; }
+  if (c->pgraph) { (void)hipGraphDestroy(c->pgraph); c->pgraph = nullptr; }
+  c->pgkey.clear();
+  if (!c->cap_stream && (e = hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking)) != hipSuccess) return e;
+  const size_t rows = every > 0 ? (size_t)(nsteps / every) : 0;
+  if (rows > c->pring_rows) {
+    if (c->pring) (void)hipFree(c->pring);
+    c->pring = nullptr;
+    c->pring_rows = 0;
+    if ((e = hipMalloc((void**)&c->pring, rows * c->R * kNQ * sizeof(double))) != hipSuccess) return e;
+    c->pring_rows = rows;
+  }
+  if ((e = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal)) != hipSuccess) return e;
+  const hipError_t le = enqueue_persistent(c, ph, lpa, nsteps, every, rows ? c->pring : nullptr, c->cap_stream);
+  hipGraph_t g = nullptr;
+  e = hipStreamEndCapture(c->cap_stream, &g);
+  if (le != hipSuccess) { if (g) (void)hipGraphDestroy(g); return le; }
+  if (e != hipSuccess) return e;
+  c->pgraph = g;
+  if ((e = hipGraphInstantiate(&c->pgexec, g, nullptr, nullptr, 0)) != hipSuccess) return e;
+  c->pgkey = key;
+  return hipSuccess;
+}
+
 }  // namespace swh
 
 using namespace swh;
@@ -462,6 +512,9 @@ void sw_destroy(sw_ctx* ctx) {
   if (ctx->adj_gexec) (void)hipGraphExecDestroy(ctx->adj_gexec);
   if (ctx->adj_graph) (void)hipGraphDestroy(ctx->adj_graph);
   for (void* p : ctx->adj_buf) (void)hipFree(p);
+  if (ctx->pgexec) (void)hipGraphExecDestroy(ctx->pgexec);
+  if (ctx->pgraph) (void)hipGraphDestroy(ctx->pgraph);
+  if (ctx->pring) (void)hipFree(ctx->pring);
   if (ctx->d_pctl) (void)hipFree(ctx->d_pctl);
   if (ctx->d_gtab) (void)hipFree(ctx->d_gtab);
   free_list(ctx, ctx->grow_allocs);
@@ -669,16 +722,18 @@ int sw_step(sw_ctx* ctx, float* x, float* v, float* f, const sw_params* params, 
     } else {
       if ((e = launch_forces(ctx->d, ph, lpa, MODE_START, 0, 0, nullptr, s)) != hipSuccess) return fail_hip(ctx, e);
       const bool persistent = ctx->tune.persistent > 0;
-      if (persistent) {
-        // launches of at most kPersistSteps steps (one control word per step)
-        for (int t0 = 1; t0 <= nsteps; t0 += kPersistSteps) {
-          const int t1 = std::min(nsteps, t0 + kPersistSteps - 1);
-          PArgs pa{t0, t1, nsteps, thermo ? thermo_every : 0, ctx->tune.rebuild_every, thermo, ctx->d_pctl,
-                   ctx->d.flags + F_ABORT, ctx->d.sync_rb, ctx->pg_ng, ctx->xmask, ctx->d_gtab};
-          if ((e = launch_persistent(ctx->d, ph, lpa, pa, ctx->tune.persistent > 1 ? ctx->tune.persistent : 0, s,
-                                     &ctx->last_grid)) != hipSuccess)
-            return fail_hip(ctx, e);
-        }
+      if (persistent && ctx->tune.graph_steps > 0) {
+        // the call's persistent launches replayed from a captured graph
+        const int every = thermo ? thermo_every : 0;
+        if ((e = ensure_pgraph(ctx, ph, lpa, nsteps, every)) != hipSuccess) return fail_hip(ctx, e);
+        if ((e = hipGraphLaunch(ctx->pgexec, s)) != hipSuccess) return fail_hip(ctx, e);
+        if (every > 0 && nsteps / every > 0 &&
+            (e = hipMemcpyAsync(thermo, ctx->pring, (size_t)(nsteps / every) * ctx->R * kNQ * sizeof(double),
+                                hipMemcpyDeviceToDevice, s)) != hipSuccess)
+          return fail_hip(ctx, e);
+      } else if (persistent) {
+        if ((e = enqueue_persistent(ctx, ph, lpa, nsteps, thermo ? thermo_every : 0, thermo, s)) != hipSuccess)
+          return fail_hip(ctx, e);
       }
       int t_first = 1;
       if (!persistent && ctx->tune.graph_steps > 0 && nsteps > 1) {

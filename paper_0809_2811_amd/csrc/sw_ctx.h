@@ -43,6 +43,12 @@ struct sw_ctx {
   unsigned xmask = 0;              // XCC ids of the device (0: not taken yet)
   int pg_ng = 1;                   // groups of the plan (1: grid-wide barriers)
   int last_groups = 0;             // groups the last persistent call ran with
+  // captured persistent call (persistent and graph_steps > 0)
+  hipGraph_t pgraph = nullptr;
+  hipGraphExec_t pgexec = nullptr;
+  std::vector<unsigned char> pgkey;
+  double* pring = nullptr;         // its thermo rows, copied out after each replay
+  size_t pring_rows = 0;
   unsigned long long* d_audit = nullptr;   // [2] pairs within the cut-off audited, pairs missing from rows
   // captured block of steps (graph_steps > 0)
   hipStream_t cap_stream = nullptr;

@@ -330,8 +330,9 @@ def test_persistent_groups_per_xcc_equal_launch_per_phase(thermostat, sync):
     """Sixteen replicas of one size: the persistent launch deals them to the
     device's XCCs and keeps each group's barriers on its XCC (with
     synchronised rebuilds the groups also meet once per step).  Results are
-    bitwise those of one launch per phase, over more steps than one
-    persistent launch holds (two launches)."""
+    bitwise those of one launch per phase, over two calls of more steps than
+    one persistent launch holds (two launches each), also when the second
+    call replays the first one's captured launches."""
     from paper_0809_2811_amd import sw
     xs, vs, boxes, T0 = [], [], [], []
     for k in range(16):
@@ -344,18 +345,25 @@ def test_persistent_groups_per_xcc_equal_launch_per_phase(thermostat, sync):
         kw.update(thermostat=sw.SW_BERENDSEN, T0=T0, tau_fs=100.0)
     nsteps = 4096 + 45
     out = []
-    for persistent in (0, 1):
+    # per-phase launches, persistent launches, and persistent launches
+    # captured on the first call and replayed on the second
+    for persistent, graph_steps in ((0, 0), (1, 0), (1, 10)):
         ctx = make_ctx(np.concatenate(xs), None, offsets=offsets, boxes=boxes, persistent=persistent,
-                       sync_rebuild=sync)
+                       sync_rebuild=sync, graph_steps=graph_steps)
         xd, vd = to_dev(np.concatenate(xs)), to_dev(np.concatenate(vs))
-        print(f"persistent={persistent} thermostat={thermostat} sync={sync}", flush=True)
-        f, th = ctx.step(xd, vd, nsteps, **kw)
-        out.append((from_dev(xd), from_dev(vd), from_dev(f), th.cpu().numpy(), ctx.query(sw.SW_Q_REBUILDS)))
-        if persistent:
-            assert ctx.query(sw.SW_Q_PERSISTENT_GROUPS) > 1
-    assert out[0][4] > 16 * 50                                     # rows were rebuilt many times
-    for k in range(5):
-        assert np.array_equal(out[0][k], out[1][k]), k
+        res = []
+        for call in range(2):
+            print(f"persistent={persistent} graph={graph_steps} thermostat={thermostat} sync={sync} call={call}",
+                  flush=True)
+            f, th = ctx.step(xd, vd, nsteps, **kw)
+            res += [from_dev(xd), from_dev(vd), from_dev(f), th.cpu().numpy()]
+            if persistent:
+                assert ctx.query(sw.SW_Q_PERSISTENT_GROUPS) > 1
+        out.append(res + [ctx.query(sw.SW_Q_REBUILDS)])
+    assert out[0][-1] > 16 * 100                                   # rows were rebuilt many times
+    for run in (1, 2):
+        for k in range(len(out[0])):
+            assert np.array_equal(out[0][k], out[run][k]), (run, k)
 
 
 @pytest.mark.parametrize("thermostat", ["nve", "berendsen"])
