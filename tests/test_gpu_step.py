@@ -366,6 +366,31 @@ def test_persistent_groups_per_xcc_equal_launch_per_phase(thermostat, sync):
             assert np.array_equal(out[0][k], out[run][k]), (run, k)
 
 
+@pytest.mark.parametrize("nsteps", [1, 4096, 4097])
+def test_persistent_groups_at_launch_boundaries(nsteps):
+    """Calls whose last step falls at the end of the first persistent launch,
+    one step after it (a second launch of one step), or in a one-step call,
+    with forced rebuilds: bitwise equal to one launch per phase."""
+    from paper_0809_2811_amd import sw
+    xs, vs, boxes = [], [], []
+    for k in range(16):
+        d = synth.lattice_at_density(4, 0.95 + 0.005 * k, sigma=0.2, temperature=260.0, seed=500 + k)
+        xs.append(f32(d["x"])); vs.append(f32(d["v"])); boxes.append(d["box"])
+    offsets = np.cumsum([0] + [len(x) for x in xs])
+    out = []
+    for persistent in (0, 1):
+        ctx = make_ctx(np.concatenate(xs), None, offsets=offsets, boxes=boxes, persistent=persistent,
+                       rebuild_every=7, sync_rebuild=1)
+        xd, vd = to_dev(np.concatenate(xs)), to_dev(np.concatenate(vs))
+        print(f"persistent={persistent} nsteps={nsteps}", flush=True)
+        f, _ = ctx.step(xd, vd, nsteps)
+        out.append((from_dev(xd), from_dev(vd), from_dev(f), ctx.query(sw.SW_Q_REBUILDS)))
+        if persistent:
+            assert ctx.query(sw.SW_Q_PERSISTENT_GROUPS) > 1
+    for k in range(4):
+        assert np.array_equal(out[0][k], out[1][k]), k
+
+
 @pytest.mark.parametrize("thermostat", ["nve", "berendsen"])
 def test_graph_replays_equal_plain_launches(thermostat):
     """Blocks of steps replayed from a captured hipGraph give bitwise the
