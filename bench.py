@@ -387,6 +387,8 @@ def bench_batched(steps=5000, melt_steps=1000, skin=1.0, sequential_steps=500):
             sync()
             dt = time.perf_counter() - t0
             out[name] = {"value": n * steps / dt, "ms_per_step": dt * 1e3 / steps, **form}
+            if form["persistent"]:   # 1: grid-wide barriers; k > 1: replicas dealt to k XCCs
+                out[name]["barrier_groups"] = ctx.query(sw.SW_Q_PERSISTENT_GROUPS)
     # the same replicas one after another, each in its own context
     xs, vs = x0.clone(), v0.clone()
     total = 0.0
