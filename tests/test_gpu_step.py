@@ -366,6 +366,36 @@ def test_persistent_groups_per_xcc_equal_launch_per_phase(thermostat, sync):
             assert np.array_equal(out[0][k], out[run][k]), (run, k)
 
 
+@pytest.mark.parametrize("thermostat", ["nve", "berendsen"])
+def test_persistent_groups_with_padded_replicas(thermostat):
+    """Replicas of 480 and 800 atoms (padded to 512 and 832 in the internal
+    order) dealt to the XCCs: padding atoms inside a group's tiles and
+    64-atom units, bitwise equal to one launch per phase."""
+    from paper_0809_2811_amd import sw
+    xs, vs, boxes, T0 = [], [], [], []
+    for k in range(16):
+        cells = (3, 4, 5) if k % 2 == 0 else (4, 5, 5)
+        d = synth.lattice_at_density(cells, 0.94 + 0.007 * k, sigma=0.2, temperature=230.0 + 5.0 * k, seed=700 + k)
+        xs.append(f32(d["x"])); vs.append(f32(d["v"])); boxes.append(d["box"]); T0.append(230.0 + 5.0 * k)
+    offsets = np.cumsum([0] + [len(x) for x in xs])
+    assert {len(x) for x in xs} == {480, 800}
+    kw = dict(thermo_every=11)
+    if thermostat == "berendsen":
+        kw.update(thermostat=sw.SW_BERENDSEN, T0=T0, tau_fs=100.0)
+    out = []
+    for persistent in (0, 1):
+        ctx = make_ctx(np.concatenate(xs), None, offsets=offsets, boxes=boxes, persistent=persistent,
+                       sync_rebuild=1)
+        xd, vd = to_dev(np.concatenate(xs)), to_dev(np.concatenate(vs))
+        print(f"persistent={persistent} thermostat={thermostat}", flush=True)
+        f, th = ctx.step(xd, vd, 330, **kw)
+        out.append((from_dev(xd), from_dev(vd), from_dev(f), th.cpu().numpy(), ctx.query(sw.SW_Q_REBUILDS)))
+        if persistent:
+            assert ctx.query(sw.SW_Q_PERSISTENT_GROUPS) > 1
+    for k in range(5):
+        assert np.array_equal(out[0][k], out[1][k]), k
+
+
 @pytest.mark.parametrize("nsteps", [1, 4096, 4097])
 def test_persistent_groups_at_launch_boundaries(nsteps):
     """Calls whose last step falls at the end of the first persistent launch,
